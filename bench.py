@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Throughput of the MSD radix sort on one MI355X.
+
+Workload (default): 2^28 records of 16 B -- a uint64 key uniform over 64 bits
+and a uint64 payload holding the record's input index -- sorted by the 8 key
+bytes with 1-byte digits.  Synthetic, seeded, generated on the host and
+uploaded once; every step sorts its own resident copy of the input, so the
+timed region holds nothing but sorts.
+
+Prints one JSON line.  `value` is records sorted per second over the timed
+steps.  `roofline` covers the dominant kernel, the top-level scatter, from HIP
+events recorded around its launch in every timed step: algorithmic bytes per
+launch = 2 * n * R (every record read once and written once) over its mean
+duration, against the 8 TB/s HBM peak.  `cpu_baseline` is the CPU oracle
+(std::stable_sort, one thread) timed on a bounded sample of the same
+workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "records sorted/s and % of HBM roofline (16B recs, 2^28); batched vs plain"
+PROFILE_SLOTS = ["top_hist", "top_scatter", "round2_hist", "round2_scatter", "lds_sort"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_top_scatter_uniform16.json")
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+class HipEvents:
+    """Raw HIP events through libamdhip64 (the library records them)."""
+
+    def __init__(self):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                 ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self, count: int) -> list[int]:
+        out = []
+        for _ in range(count):
+            ev = ctypes.c_void_p()
+            if self.hip.hipEventCreate(ctypes.byref(ev)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            out.append(ev.value)
+        return out
+
+    def elapsed_ms(self, a: int, b: int) -> float:
+        ms = ctypes.c_float()
+        if self.hip.hipEventElapsedTime(ctypes.byref(ms), a, b) != 0:
+            return float("nan")
+        return float(ms.value)
+
+    def destroy(self, evs: list[int]) -> None:
+        for e in evs:
+            self.hip.hipEventDestroy(e)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("raduls_kernels.hpp", "raduls_common.hpp"):
+        with open(os.path.join(ROOT, "paper_1703_00687_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(n: int) -> float | None:
+    """HBM bytes per top-scatter launch from committed PMC counters, if they
+    were taken on the current kernel source for this n."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("n") != n:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def check_sorted_device(out, src, n):
+    """Stable-sort properties on the device: keys non-decreasing, payloads a
+    permutation, every record equal to the input record its payload names,
+    equal keys in input order.  Together they pin the unique stable result."""
+    import torch
+    w = out.view(torch.int64).view(n, 2)
+    sign = torch.tensor(-(1 << 63), dtype=torch.int64, device=w.device)
+    k = w[:, 0] ^ sign  # order-preserving map of uint64 onto int64
+    p = w[:, 1]
+    if not bool((k[1:] >= k[:-1]).all()):
+        return False
+    if not bool(((p >= 0) & (p < n)).all()):
+        return False
+    seen = torch.zeros(n, dtype=torch.bool, device=w.device)
+    seen[p] = True
+    if not bool(seen.all()):
+        return False
+    ws = src.view(torch.int64).view(n, 2)
+    if not bool((ws[p] == w).all()):
+        return False
+    eq = k[1:] == k[:-1]
+    return bool((p[1:][eq] > p[:-1][eq]).all())
+
+
+def cpu_baseline(log2n: int) -> dict:
+    import oracle
+    from paper_1703_00687_amd import workloads as wl
+    n = 1 << log2n
+    host = wl.uniform16(n)
+    oracle.sort(host[:1024], 8)  # load/build outside the timing
+    t0 = time.perf_counter()
+    out = oracle.sort(host, 8)
+    dt = time.perf_counter() - t0
+    assert oracle.check_sorted(out[: 1 << 16], 8)
+    return {"value": n / dt, "unit": "records/s", "cores": 1, "kind": "oracle",
+            "sample": f"first 2^{log2n} records of the same uniform16 workload "
+                      f"(std::stable_sort, one thread, {dt:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--log2n", type=int, default=28, help="records = 2^log2n (default 28)")
+    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-verify", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU path is a design in DESIGN.md, not built)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1703_00687_amd import binding as b
+    from paper_1703_00687_amd import workloads as wl
+
+    n, R, K = 1 << args.log2n, 16, 8
+    steps, warm = args.steps, args.warmup
+    log(f"[bench] generating uniform16 n=2^{args.log2n}")
+    host = wl.uniform16(n)
+    dev = torch.device("cuda:0")
+    src = torch.from_numpy(host.reshape(-1)).to(dev)
+    del host
+    copies = []
+    for _ in range(warm + steps):
+        c = torch.empty_like(src)
+        c.copy_(src)
+        copies.append(c)
+    tmp = torch.empty(b.raduls_tmp_bytes(n, R, K), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    log(f"[bench] {warm + steps} resident copies of {n * R / 2**30:.1f} GiB, tmp "
+        f"{tmp.numel() / 2**30:.2f} GiB")
+
+    hip = HipEvents()
+    nslot = len(PROFILE_SLOTS)
+    step_events = [hip.create(2 * nslot) for _ in range(steps)]
+
+    for i in range(warm):
+        b.raduls_sort(copies[i], tmp, n, R, K)
+    torch.cuda.synchronize()
+    st, stats = b.raduls_check(tmp, n, R, False)
+    if st != b.OK:
+        raise RuntimeError(f"device error in warm-up: {stats}")
+    log(f"[bench] warm-up done; stats {stats}")
+
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for i in range(steps):
+        b.raduls_set_profile_events(step_events[i])
+        b.raduls_sort(copies[warm + i], tmp, n, R, K)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.raduls_set_profile_events([])
+    gpu_ms = start.elapsed_time(stop)
+    ms_per_step = gpu_ms / steps
+    log(f"[bench] timed {steps} steps: {gpu_ms:.2f} ms on the GPU clock, {wall * 1e3:.2f} ms wall")
+
+    st, stats = b.raduls_check(tmp, n, R, False)
+    if st != b.OK:
+        raise RuntimeError(f"device error in timed steps: {stats}")
+    verified = None
+    if not args.no_verify:
+        verified = check_sorted_device(copies[-1], src, n)
+        if not verified:
+            raise RuntimeError("sorted output failed the stable-sort property check")
+        log("[bench] last step's output verified on the device")
+
+    phases = {}
+    for j, name in enumerate(PROFILE_SLOTS):
+        vals = [hip.elapsed_ms(ev[2 * j], ev[2 * j + 1]) for ev in step_events]
+        phases[name] = sum(vals) / len(vals)
+    for ev in step_events:
+        hip.destroy(ev)
+    pass_bytes = 2 * n * R
+    scat_ms = phases["top_scatter"]
+    achieved = pass_bytes / (scat_ms * 1e-3) / 1e9
+    traffic = load_traffic(n)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "k_scatter<2,1,1> (top-level scatter)",
+                "bytes_per_launch": pass_bytes, "mean_launch_ms": round(scat_ms, 4)}
+    phase_gbs = {
+        "top_hist": n * R / (phases["top_hist"] * 1e-3) / 1e9,
+        "top_scatter": achieved,
+        "round2_hist": n * R / (phases["round2_hist"] * 1e-3) / 1e9,
+        "round2_scatter": pass_bytes / (phases["round2_scatter"] * 1e-3) / 1e9,
+        "lds_sort": pass_bytes / (phases["lds_sort"] * 1e-3) / 1e9,
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle on 2^{args.cpu_sample_log2} records")
+        cpu = cpu_baseline(args.cpu_sample_log2)
+
+    value = n / (ms_per_step * 1e-3)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "records/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"uniform16: 2^{args.log2n} records of 16 B (uint64 key uniform, "
+                               "uint64 payload = index), key 8 B, 1-byte digits",
+                   "n": n, "rec_bytes": R, "key_bytes": K},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "phases_gbs": {k: round(v, 1) for k, v in phase_gbs.items()},
+        "whole_sort_gbs_per_pass": round(pass_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "stats": stats,
+        "verified": verified,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,172 @@
+/*
+ * raduls.h -- C ABI of libraduls.so, an MI355X (gfx950) MSD radix sort of
+ * fixed-size records after RADULS2 (Kokot, Deorowicz, Dlugosz, "Even faster
+ * sorting of (not only) integers", arXiv 1703.00687).
+ *
+ * Problem (paper: abstract, Sec. 3.1, Sec. 4.2).  An array holds n records of
+ * R bytes each, stored contiguously (record i at byte offset i*R).  The key of
+ * a record is its first K bytes read as an unsigned little-endian integer
+ * (byte K-1 most significant; for K = 16 the word at offset 8 is the high
+ * word).  Bytes at offsets K..R-1 are data: they travel with the record and
+ * never affect the order.  Sorting permutes the records so that keys are
+ * non-decreasing.  This library's result is also stable (records with equal
+ * keys keep their input order), so it is unique.
+ *
+ * Method (Sec. 3): MSD radix sort on digits of `digit_bits` key bits (one
+ * byte by default, as in the paper): per-bin digit histograms, exclusive
+ * prefix scans into bucket offsets, a scatter of records into buckets, and
+ * recursion into bins that are still large; small bins are finished inside one
+ * workgroup's LDS and tiny bins by an enumeration sort (Sec. 2.2, Sec. 3.3).
+ *
+ * Conventions for every call:
+ *   - All calls are host calls.  Device work is enqueued on `stream` (0 = the
+ *     null stream) and runs asynchronously; a call returns as soon as the work
+ *     is enqueued.  The sort calls never allocate, free or synchronize, so
+ *     they may be captured into a HIP graph.
+ *   - Pointers named recs/tmp/src/dst/ws/d_* are DEVICE pointers owned by the
+ *     caller, 16-byte aligned, valid until the enqueued work completes.
+ *   - R (rec_bytes) must be a multiple of 8 in [8, 64]; K (key_bytes) in
+ *     [1, R]; n < 2^32 per array.
+ *   - Argument errors are returned synchronously, before anything is
+ *     enqueued.  Errors found on the device (a workspace too small for the
+ *     data, a bounded wait that expired) are recorded in the workspace and
+ *     reported by raduls_check().
+ */
+#ifndef RADULS_H
+#define RADULS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum raduls_status {
+  RADULS_OK = 0,
+  RADULS_E_INVALID = -1,     /* bad K, null pointer, overlapping buffers, bad digit */
+  RADULS_E_ALIGN = -2,       /* a device pointer is not 16-byte aligned */
+  RADULS_E_TMP_SMALL = -3,   /* tmp / ws smaller than the size query returned */
+  RADULS_E_UNSUPPORTED = -4, /* R not a multiple of 8 in [8, 64], or n >= 2^32 */
+  RADULS_E_HIP = -5,         /* a HIP runtime call or kernel launch failed */
+  RADULS_E_DEVICE = -6       /* raduls_check(): the device recorded an error */
+} raduls_status;
+
+/* Tuning knobs (process-global; set them before enqueuing sorts, never while
+ * sorts are being enqueued from another thread).  Zero means "default".  The
+ * result never depends on them, only the speed does. */
+typedef struct raduls_tuning {
+  uint32_t digit_bits;   /* radix digit width in bits, 1..8 (default 8: one byte, Sec. 3.1) */
+  uint32_t tiny_max;     /* bins of <= tiny_max records are finished by enumeration
+                            sort (Sec. 3.3); 1..256 (default 32) */
+  uint32_t mid_max;      /* bins of <= mid_max records are sorted inside one workgroup's
+                            LDS (the "small bin fits in cache" case, Sec. 3.2); clamped
+                            to the LDS capacity for R; default = that capacity */
+  uint32_t grid_blocks;  /* workgroups of the persistent kernels (default 2 per CU) */
+  uint32_t nontemporal;  /* 1: scatter stores use the nontemporal (streaming) cache
+                            policy, 2: ordinary stores (default 1) */
+  uint32_t reserved[11];
+} raduls_tuning;
+
+/* Device-side counters left in the workspace by the last sort that used it. */
+typedef struct raduls_stats {
+  uint32_t error;          /* bit 0: list capacity exceeded; bit 1: bounded look-back
+                              wait expired; bit 2: a bin larger than mid_max reached the
+                              LDS sorter; bit 3: batch total exceeded its capacity;
+                              bit 4: a scatter destination fell outside its bin
+                              (write suppressed) */
+  uint32_t rounds;         /* radix rounds that found at least one large bin */
+  uint32_t large_bins;     /* large bins processed over all rounds */
+  uint32_t scattered_bins; /* large bins that were moved (not constant / all equal) */
+  uint32_t mid_jobs;       /* LDS sort jobs */
+  uint32_t copy_jobs;      /* tmp -> recs copies of finished bins */
+  uint64_t moved_records;  /* records moved by global scatter passes */
+  uint64_t large_records;  /* records in large bins, summed over rounds */
+} raduls_stats;
+
+/* Bytes of `tmp` that raduls_sort needs for n records: n*R for the scatter
+ * ping-pong plus an auxiliary workspace (bin lists, look-back status, job
+ * queues) placed after them.  Depends on the current tuning. */
+int raduls_tmp_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint64_t *out_bytes);
+
+/* Sort n records in `recs` by their key (the whole method of Sec. 3).
+ * recs: n*R bytes, in/out.  tmp: at least raduls_tmp_bytes() bytes of
+ * scratch whose contents on return are undefined; it must not overlap recs.
+ * n <= 1 is a no-op.  On completion of the enqueued work `recs` holds the
+ * stably sorted records. */
+int raduls_sort(void *recs, void *tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
+                hipStream_t stream);
+
+/* One array of a batch: device pointers recs (n*R bytes) and tmp (at least
+ * n*R bytes; no auxiliary tail needed), and its record count. */
+typedef struct raduls_array {
+  void *recs;
+  void *tmp;
+  uint64_t n;
+} raduls_array;
+
+/* Workspace bytes for raduls_sort_batch with `count` arrays holding at most
+ * `total_n` records together. */
+int raduls_batch_ws_bytes(uint32_t count, uint64_t total_n, uint32_t rec_bytes,
+                          uint32_t key_bytes, uint64_t *out_bytes);
+
+/* Sort `count` independent arrays in one set of launches.  d_arrays is a
+ * DEVICE array of `count` raduls_array descriptors (it may be rewritten
+ * between replays of a captured graph).  The sum of their n must not exceed
+ * total_n, the capacity ws was sized for (checked on the device; see
+ * raduls_check).  Every array is sorted as raduls_sort would sort it.  The
+ * launch shapes depend only on (count, total_n, R, K) and the tuning, never on
+ * the array contents, so one captured graph serves any batch within them. */
+int raduls_sort_batch(const raduls_array *d_arrays, uint32_t count, uint64_t total_n,
+                      uint32_t rec_bytes, uint32_t key_bytes, void *ws, uint64_t ws_bytes,
+                      hipStream_t stream);
+
+/* Workspace bytes for raduls_histogram / raduls_partition on n records. */
+int raduls_step_ws_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint64_t *out_bytes);
+
+/* Digit histogram of one bin, the whole array (Sec. 1: counting step of a
+ * radix phase).  The digit is key bits [bits - w, bits), w = min(width, bits),
+ * 1 <= width <= 8, 1 <= bits <= 8K.  d_counts: DEVICE uint32[2^w], written. */
+int raduls_histogram(const void *recs, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
+                     uint32_t bits, uint32_t width, uint32_t *d_counts, void *ws,
+                     uint64_t ws_bytes, hipStream_t stream);
+
+/* One stable counting-sort pass of the whole array on one digit (Sec. 1;
+ * the scatter of Sec. 3.2): src -> dst, records grouped by digit in
+ * increasing digit order, input order kept inside each group.  d_offsets
+ * (DEVICE uint32[2^w], may be NULL) receives the exclusive prefix sum of the
+ * digit counts, i.e. where each bucket starts in dst.  src and dst must not
+ * overlap. */
+int raduls_partition(const void *src, void *dst, uint64_t n, uint32_t rec_bytes,
+                     uint32_t key_bytes, uint32_t bits, uint32_t width, uint32_t *d_offsets,
+                     void *ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Synchronously read the device counters of the last call that used this
+ * workspace: for raduls_sort pass (tmp, n, R, 0); for raduls_sort_batch,
+ * raduls_histogram and raduls_partition pass (ws, 0, R, 1).  Waits for
+ * `stream` first.  Returns RADULS_OK, or RADULS_E_DEVICE if stats->error is
+ * non-zero. */
+int raduls_check(const void *tmp_or_ws, uint64_t n, uint32_t rec_bytes, int ws_only,
+                 raduls_stats *stats, hipStream_t stream);
+
+int raduls_set_tuning(const raduls_tuning *tuning);
+int raduls_get_tuning(raduls_tuning *tuning);
+
+/* Measurement aid.  With count > 0, later sort calls record events[2i] and
+ * events[2i+1] (caller-created HIP events) on their stream just before and
+ * after the launches of kernel class i: 0 top-level histogram, 1 top-level
+ * scatter, 2 second-round histogram, 3 second-round scatter, 4 LDS sorter.
+ * count = 0 turns it off.  Process-global; never set while sorts are being
+ * enqueued or captured. */
+int raduls_set_profile_events(hipEvent_t *events, uint32_t count);
+
+/* Largest mid_max (records) the LDS sorter supports for records of R bytes. */
+uint32_t raduls_mid_capacity(uint32_t rec_bytes);
+
+const char *raduls_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADULS_H */

@@ -1,0 +1,148 @@
+// Shared host/device definitions of libraduls: workspace layout, bin and job
+// descriptors, launch parameters.  Device code and host runtime both include
+// this file; nothing here touches torch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace raduls {
+
+// ---------------------------------------------------------------- constants
+
+constexpr int kRadixBitsMax = 8;
+constexpr int kRadix = 1 << kRadixBitsMax;  // buckets per digit (upper bound)
+constexpr int kWave = 64;                   // CDNA wavefront width
+
+// Scatter / histogram workgroups: 8 waves.  Records per thread per tile are
+// chosen per record width so that one tile stages about 64 KiB in LDS and two
+// tiles fit in a CU's 160 KiB.
+constexpr int kScatterBlock = 512;
+constexpr int kScatterWaves = kScatterBlock / kWave;
+__host__ __device__ constexpr int scatter_items(int rw) {
+  return rw == 1 ? 15 : rw == 2 ? 8 : rw == 3 ? 5 : rw == 4 ? 4 : rw == 5 ? 3 : 2;
+}
+// Dynamic LDS of one scatter workgroup: staged records, their digits,
+// per-wave counters, three 256-entry tables and the per-digit global bases.
+__host__ __device__ constexpr uint32_t scatter_lds_bytes(int rw) {
+  return uint32_t(kScatterBlock * scatter_items(rw)) * (8u * rw + 1u) +
+         uint32_t(kScatterWaves * 256 * 2) + 3u * 256u * 4u + 256u * 8u;
+}
+
+// LDS sorter workgroups: 16 waves, one workgroup per CU.
+constexpr int kMidBlock = 1024;
+constexpr int kMidWaves = kMidBlock / kWave;
+__host__ __device__ constexpr int mid_items(int rw) {
+  return rw == 1 ? 12 : rw == 2 ? 8 : rw == 3 ? 6 : rw <= 5 ? 4 : 3;
+}
+constexpr uint32_t kLdsBytes = 160 * 1024;
+constexpr uint32_t kMidStackCap = 512;
+constexpr uint32_t kMidFixedLds = 8 * 1024;  // scan scratch, stack, flags
+
+// Finished bins that sit in tmp are copied back in chunks of this many records.
+constexpr uint32_t kCopyChunk = 1u << 16;
+
+// Device error bits (raduls_stats.error).
+constexpr uint32_t kErrCapacity = 1u << 0;
+constexpr uint32_t kErrSpin = 1u << 1;
+constexpr uint32_t kErrMidSize = 1u << 2;
+constexpr uint32_t kErrBatchTotal = 1u << 3;
+constexpr uint32_t kErrBounds = 1u << 4;
+
+// Measurement slots of raduls_set_profile_events (event pairs).
+constexpr uint32_t kProfTopHist = 0;    // top-level histogram
+constexpr uint32_t kProfTopScatter = 1; // top-level scatter
+constexpr uint32_t kProfRoundHist = 2;  // second round histogram
+constexpr uint32_t kProfRoundScatter = 3;
+constexpr uint32_t kProfMid = 4;        // LDS sorter
+constexpr uint32_t kProfileSlots = 5;
+
+// Look-back status word: [63:62] flag, [61:0] count.
+constexpr uint64_t kFlagAggregate = 1ull << 62;
+constexpr uint64_t kFlagPrefix = 2ull << 62;
+constexpr uint64_t kValueMask = (1ull << 62) - 1;
+
+// ---------------------------------------------------------------- descriptors
+
+struct ArrayDesc {  // same layout as raduls_array
+  uint8_t* recs;
+  uint8_t* tmp;
+  uint64_t n;
+};
+
+// A bin (a contiguous run of records that share all key bits above `bits`)
+// or an LDS sort job / copy job over such runs.  16 bytes.
+struct Bin {
+  uint32_t start;  // first record, relative to the array
+  uint32_t size;   // records
+  uint32_t array;  // index into the array table
+  uint16_t bits;   // key bits [0, bits) still to be sorted
+  uint8_t side;    // 0: records currently in recs, 1: in tmp
+  uint8_t flags;
+};
+
+// Device control block at the start of the auxiliary workspace; cleared at
+// the start of every call.
+struct Ctrl {
+  uint32_t large_count[2];  // large-bin list sizes (ping-pong by round)
+  uint32_t mid_count;
+  uint32_t copy_count;
+  uint32_t ticket;       // scatter tile tickets of the current round
+  uint32_t round_tiles;  // tiles of the current round
+  uint32_t error;
+  uint32_t rounds;
+  uint32_t large_bins;
+  uint32_t scattered_bins;
+  uint32_t pad[2];
+  unsigned long long moved_records;
+  unsigned long long large_records;
+  unsigned long long batch_total;
+};
+
+// Device pointers into the auxiliary workspace.
+struct Layout {
+  Ctrl* ctrl;
+  ArrayDesc* arrays;
+  Bin* large[2];
+  uint32_t* hist[2];      // [cap_large][kRadix]
+  uint64_t* diff[2];      // [cap_large][8]
+  uint32_t* tile_prefix;  // [cap_large + 1]
+  uint32_t* tile_bin;     // [cap_tiles]: bin index of each tile of the round
+  uint64_t* status;       // [cap_tiles][kRadix]
+  Bin* mid;
+  Bin* copy;
+  uint32_t cap_large, cap_tiles, cap_mid, cap_copy;
+};
+
+enum Mode : uint32_t { kModeSort = 0, kModeBatch = 1, kModeHist = 2, kModePartition = 3 };
+
+// Everything a launch sequence needs; passed to kernels by value.
+struct Params {
+  Layout L;
+  uint32_t R, K;
+  uint64_t kmask;         // mask of the key bytes in the top key word
+  uint32_t digit_bits;    // 1..8
+  uint32_t tiny_max;
+  uint32_t mid_max;       // <= LDS capacity
+  uint32_t tile;          // records per scatter tile
+  uint32_t nontemporal;
+  uint32_t rounds;
+  uint32_t mode;
+  uint32_t count;          // arrays
+  uint64_t total_cap;      // batch: records the workspace was sized for
+  // single array / step calls
+  uint8_t* recs;
+  uint8_t* tmp;
+  uint64_t n;
+  const ArrayDesc* d_arrays_in;  // batch descriptors (device)
+  uint32_t step_bits, step_width;
+  uint32_t* d_counts_out;
+  uint32_t* d_offsets_out;
+  // launch shapes
+  uint32_t grid_hist, grid_scatter, grid_classify, grid_mid, grid_copy;
+  uint32_t mid_lds_bytes, scatter_lds_bytes;
+};
+
+__host__ __device__ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace raduls

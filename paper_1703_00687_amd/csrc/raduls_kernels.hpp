@@ -1,0 +1,1089 @@
+// Device kernels of libraduls (gfx950, wave64).  Included by one translation
+// unit per record width; each instantiates the kernels for its R = 8*RW and
+// every key width KW = ceil(K/8) <= RW.
+//
+// The sort is an MSD radix sort of fixed-size records (RADULS2, Sec. 3):
+//   round r (large bins):  k_prep     tile counts of the round's bins
+//                          k_hist     per-bin digit histogram (+ key spread)
+//                          k_scatter  stable scatter with decoupled look-back
+//                          k_classify child bins -> next round / LDS jobs
+//   then                   k_mid      bins that fit in LDS, sorted there; tiny
+//                                     sub-bins by enumeration sort
+//                          k_copy     finished bins left in tmp -> recs
+#pragma once
+
+#include "raduls_common.hpp"
+
+namespace raduls {
+
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+// ------------------------------------------------------------ small helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+template <int RW>
+__device__ __forceinline__ void load_rec(const uint8_t* base, uint64_t idx, uint64_t (&w)[RW]) {
+  const uint64_t* p = reinterpret_cast<const uint64_t*>(base) + idx * RW;
+  if constexpr (RW % 2 == 0) {
+    const u64x2* q = reinterpret_cast<const u64x2*>(p);
+#pragma unroll
+    for (int i = 0; i < RW / 2; ++i) {
+      u64x2 v = q[i];
+      w[2 * i] = v.x;
+      w[2 * i + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < RW; ++i) w[i] = p[i];
+  }
+}
+
+template <int RW>
+__device__ __forceinline__ void store_rec(uint8_t* base, uint64_t idx, const uint64_t* w, bool nt) {
+  uint64_t* p = reinterpret_cast<uint64_t*>(base) + idx * RW;
+  if constexpr (RW % 2 == 0) {
+    u64x2* q = reinterpret_cast<u64x2*>(p);
+#pragma unroll
+    for (int i = 0; i < RW / 2; ++i) {
+      u64x2 v;
+      v.x = w[2 * i];
+      v.y = w[2 * i + 1];
+      if (nt) __builtin_nontemporal_store(v, q + i);
+      else q[i] = v;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+      if (nt) __builtin_nontemporal_store((unsigned long long)w[i], (unsigned long long*)p + i);
+      else p[i] = w[i];
+    }
+  }
+}
+
+// Key words of a record (word KW-1 most significant), top word masked to the
+// key bytes it holds.
+template <int KW>
+__device__ __forceinline__ void key_of(const uint64_t* w, uint64_t kmask, uint64_t (&k)[KW]) {
+#pragma unroll
+  for (int i = 0; i < KW; ++i) k[i] = w[i];
+  k[KW - 1] &= kmask;
+}
+
+// Bits [lo, lo + w) of a multi-word key, 1 <= w <= 8.
+template <int KW>
+__device__ __forceinline__ uint32_t digit_of(const uint64_t (&k)[KW], uint32_t lo, uint32_t w) {
+  const uint32_t wi = lo >> 6, sh = lo & 63;
+  uint64_t a = 0, b = 0;
+#pragma unroll
+  for (int j = 0; j < KW; ++j) {
+    a = (uint32_t(j) == wi) ? k[j] : a;
+    b = (uint32_t(j) == wi + 1) ? k[j] : b;
+  }
+  uint64_t v = a >> sh;
+  if (sh + w > 64) v |= b << (64 - sh);
+  return uint32_t(v) & ((1u << w) - 1u);
+}
+
+template <int KW>
+__device__ __forceinline__ bool key_lt(const uint64_t (&a)[KW], const uint64_t (&b)[KW]) {
+  bool lt = false, decided = false;
+#pragma unroll
+  for (int i = KW - 1; i >= 0; --i) {
+    const bool ne = a[i] != b[i];
+    lt = (!decided && ne) ? (a[i] < b[i]) : lt;
+    decided = decided || ne;
+  }
+  return lt;
+}
+
+template <int KW>
+__device__ __forceinline__ bool key_eq(const uint64_t (&a)[KW], const uint64_t (&b)[KW]) {
+  bool eq = true;
+#pragma unroll
+  for (int i = 0; i < KW; ++i) eq = eq && (a[i] == b[i]);
+  return eq;
+}
+
+// Index of the highest set bit of a multi-word value, -1 if it is zero.
+template <int KW>
+__device__ __forceinline__ int top_bit(const uint64_t (&d)[KW]) {
+  int r = -1;
+#pragma unroll
+  for (int i = 0; i < KW; ++i)
+    if (d[i]) r = 64 * i + 63 - __clzll((long long)d[i]);
+  return r;
+}
+
+__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t u = __shfl_up(v, o);
+    if (lane >= uint32_t(o)) v += u;
+  }
+  return v;
+}
+
+// Exclusive prefix sum of one value per thread over threads [0, 256).  Every
+// thread of the block must call it (it holds barriers).  scratch: 4 words.
+__device__ __forceinline__ void block_exclusive_scan256(uint32_t v, uint32_t* out,
+                                                        uint32_t* scratch) {
+  const uint32_t t = threadIdx.x;
+  uint32_t inc = 0;
+  if (t < 256) {
+    inc = wave_inclusive_scan(v);
+    if ((t & 63) == 63) scratch[t >> 6] = inc;
+  }
+  __syncthreads();
+  if (t < 256) {
+    uint32_t add = 0;
+    for (uint32_t w = 0; w < (t >> 6); ++w) add += scratch[w];
+    out[t] = inc - v + add;
+  }
+  __syncthreads();
+}
+
+// Peers of each lane: the valid lanes of this wave holding the same digit,
+// found with one ballot per digit bit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, uint32_t nbits) {
+  uint64_t peers = __ballot(valid);
+  for (uint32_t b = 0; b < nbits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bal = __ballot(bit);
+    peers &= bit ? bal : ~bal;
+  }
+  return peers;
+}
+
+// Stable rank of each item among the items of this wave with the same digit,
+// counting earlier items first: items are processed in order j, and inside an
+// item by lane.  wcnt: this wave's 256 counters in LDS, advanced by the
+// number of items per digit.  Only one lane per distinct digit touches wcnt
+// in each step, so no atomics are needed.
+template <int ITEMS>
+__device__ __forceinline__ void wave_rank(const uint32_t (&d)[ITEMS], const bool (&valid)[ITEMS],
+                                          uint32_t nbits, uint16_t* wcnt,
+                                          uint32_t (&rank)[ITEMS]) {
+  const uint64_t lt = lanemask_lt();
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const uint64_t peers = match_digit(d[j], valid[j], nbits);
+    const uint32_t below = __popcll(peers & lt);
+    uint32_t old = 0;
+    if (valid[j] && below == 0) {
+      old = wcnt[d[j]];
+      wcnt[d[j]] = uint16_t(old + __popcll(peers));
+    }
+    const int leader = peers ? (__ffsll((long long)peers) - 1) : int(lane);
+    old = __shfl(old, leader);
+    rank[j] = old + below;
+  }
+}
+
+// After wave_rank in all waves and a barrier: turn the per-wave counters into
+// exclusive prefixes over waves, write per-digit totals and the exclusive
+// prefix over digits.  Contains barriers.
+template <int WAVES>
+__device__ __forceinline__ void block_digit_scan(uint16_t* cnt, uint32_t* tot, uint32_t* off,
+                                                 uint32_t* scratch) {
+  const uint32_t t = threadIdx.x;
+  uint32_t run = 0;
+  if (t < kRadix) {
+#pragma unroll 4
+    for (int w = 0; w < WAVES; ++w) {
+      const uint32_t c = cnt[w * kRadix + t];
+      cnt[w * kRadix + t] = uint16_t(run);
+      run += c;
+    }
+    tot[t] = run;
+  }
+  block_exclusive_scan256(run, off, scratch);
+}
+
+__device__ __forceinline__ bool push_bin(Bin* list, uint32_t* count, uint32_t cap, const Bin& b,
+                                         uint32_t* err, uint32_t* out_index = nullptr) {
+  const uint32_t i = atomicAdd(count, 1u);
+  if (i >= cap) {
+    atomicOr(err, kErrCapacity);
+    return false;
+  }
+  list[i] = b;
+  if (out_index) *out_index = i;
+  return true;
+}
+
+// Append a bin to the next large list and clear its histogram and key-spread
+// rows (they are accumulated with atomics by the next round's k_hist).
+__device__ __forceinline__ void push_large(const Params& P, uint32_t nxt, const Bin& b) {
+  uint32_t i;
+  if (!push_bin(P.L.large[nxt], &P.L.ctrl->large_count[nxt], P.L.cap_large, b, &P.L.ctrl->error, &i))
+    return;
+  uint4* h = reinterpret_cast<uint4*>(P.L.hist[nxt] + uint64_t(i) * kRadix);
+  for (int q = 0; q < kRadix / 4; ++q) h[q] = make_uint4(0, 0, 0, 0);
+  uint64_t* df = P.L.diff[nxt] + uint64_t(i) * 8;
+  for (int q = 0; q < 8; ++q) df[q] = 0;
+}
+
+// Copy jobs for a finished run of records that sits in tmp.
+__device__ __forceinline__ void push_copy(const Params& P, uint32_t array, uint32_t start,
+                                          uint32_t size) {
+  const uint32_t chunks = (size + kCopyChunk - 1) / kCopyChunk;
+  const uint32_t i0 = atomicAdd(&P.L.ctrl->copy_count, chunks);
+  for (uint32_t c = 0; c < chunks; ++c) {
+    if (i0 + c >= P.L.cap_copy) {
+      atomicOr(&P.L.ctrl->error, kErrCapacity);
+      return;
+    }
+    Bin j;
+    j.start = start + c * kCopyChunk;
+    j.size = min(kCopyChunk, size - c * kCopyChunk);
+    j.array = array;
+    j.bits = 0;
+    j.side = 1;
+    j.flags = 0;
+    P.L.copy[i0 + c] = j;
+  }
+}
+
+// ------------------------------------------------------------ seeding
+
+// Clears the control block and installs the root bin of a single-array call.
+static __global__ void __launch_bounds__(64) k_seed_single(Params P) {
+  Ctrl* c = P.L.ctrl;
+  if (threadIdx.x == 0) {
+    *c = Ctrl{};
+    ArrayDesc a;
+    a.recs = P.recs;
+    a.tmp = P.tmp;
+    a.n = P.n;
+    P.L.arrays[0] = a;
+    Bin b;
+    b.start = 0;
+    b.size = uint32_t(P.n);
+    b.array = 0;
+    b.side = 0;
+    b.flags = 0;
+    if (P.mode == kModeHist || P.mode == kModePartition) {
+      b.bits = uint16_t(P.step_bits);
+      P.L.large[0][0] = b;
+      c->large_count[0] = P.n ? 1 : 0;
+    } else {
+      b.bits = uint16_t(8 * P.K);
+      if (P.n > P.mid_max) {
+        P.L.large[0][0] = b;
+        c->large_count[0] = 1;
+      } else if (P.n >= 2) {
+        P.L.mid[0] = b;
+        c->mid_count = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (P.mode != kModeSort || P.n > P.mid_max) {
+    uint32_t* h = P.L.hist[0];
+    for (int q = threadIdx.x; q < kRadix; q += 64) h[q] = 0;
+    if (threadIdx.x < 8) P.L.diff[0][threadIdx.x] = 0;
+  }
+}
+
+static __global__ void __launch_bounds__(64) k_zero_ctrl(Params P) {
+  if (threadIdx.x == 0) *P.L.ctrl = Ctrl{};
+}
+
+// Every array of a batch becomes a root bin: large roots start round 0, small
+// ones become LDS jobs directly.
+static __global__ void __launch_bounds__(256) k_seed_batch(Params P) {
+  Ctrl* c = P.L.ctrl;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < P.count; a += stride) {
+    ArrayDesc d = P.d_arrays_in[a];
+    bool ok = d.n < (1ull << 32);
+    if (ok) {
+      const unsigned long long before = atomicAdd(&c->batch_total, (unsigned long long)d.n);
+      ok = before + d.n <= P.total_cap;
+    }
+    if (!ok) {
+      atomicOr(&c->error, kErrBatchTotal);
+      d.n = 0;
+    }
+    P.L.arrays[a] = d;
+    Bin b;
+    b.start = 0;
+    b.size = uint32_t(d.n);
+    b.array = a;
+    b.bits = uint16_t(8 * P.K);
+    b.side = 0;
+    b.flags = 0;
+    if (d.n > P.mid_max) push_large(P, 0, b);
+    else if (d.n >= 2) push_bin(P.L.mid, &c->mid_count, P.L.cap_mid, b, &c->error);
+  }
+}
+
+// ------------------------------------------------------------ round: prep
+
+// Tile prefix over the round's large bins (one workgroup).
+static __global__ void __launch_bounds__(1024) k_prep(Params P, uint32_t cur) {
+  __shared__ uint32_t s_part[16];
+  __shared__ unsigned long long s_sz[16];
+  Ctrl* c = P.L.ctrl;
+  const uint32_t nb = min(c->large_count[cur], P.L.cap_large);
+  const Bin* bins = P.L.large[cur];
+  const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  uint32_t running = 0;
+  unsigned long long records = 0;
+  for (uint32_t base = 0; base < nb; base += 1024) {
+    const uint32_t i = base + t;
+    uint32_t v = 0;
+    uint32_t sz = 0;
+    if (i < nb) {
+      sz = bins[i].size;
+      v = (sz + P.tile - 1) / P.tile;
+    }
+    const uint32_t inc = wave_inclusive_scan(v);
+    unsigned long long s64 = sz;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s64 += __shfl_xor(s64, o);
+    if (lane == 63) s_part[wave] = inc;
+    if (lane == 0) s_sz[wave] = s64;
+    __syncthreads();
+    uint32_t add = 0, tot = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+      add += (w < wave) ? s_part[w] : 0;
+      tot += s_part[w];
+    }
+    unsigned long long chunk_rec = 0;
+    for (uint32_t w = 0; w < 16; ++w) chunk_rec += s_sz[w];
+    if (i < nb) P.L.tile_prefix[i] = running + add + inc - v;
+    running += tot;
+    records += chunk_rec;
+    __syncthreads();
+  }
+  if (t == 0) {
+    P.L.tile_prefix[nb] = running;
+    c->round_tiles = running;
+    c->ticket = 0;
+    c->large_count[cur ^ 1] = 0;
+    if (nb) {
+      c->rounds += 1;
+      c->large_bins += nb;
+      c->large_records += records;
+    }
+  }
+}
+
+// ------------------------------------------------------------ round: histogram
+
+// Digit histogram of every large bin of the round, and the OR over the bin of
+// (key xor first key), which shows whether the digit or the whole key is
+// constant.  Workgroups take contiguous tile ranges and accumulate in LDS,
+// flushing to the bin's global row when the range crosses into the next bin.
+// Also clears the look-back status rows of its tiles and records their bin.
+template <int RW, int KW, int TOP>
+__global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) {
+  constexpr int ITEMS = scatter_items(RW);
+  constexpr int W = kScatterWaves;
+  constexpr uint32_t TILE = kScatterBlock * ITEMS;
+  __shared__ uint32_t s_cnt[W * kRadix];
+  __shared__ unsigned long long s_diff[W][KW];
+
+  const Ctrl* c = P.L.ctrl;
+  const uint32_t total = c->round_tiles;
+  const uint32_t nbins = min(c->large_count[cur], P.L.cap_large);
+  if (total == 0) return;
+  const uint32_t t0 = uint32_t(uint64_t(total) * blockIdx.x / gridDim.x);
+  const uint32_t t1 = uint32_t(uint64_t(total) * (blockIdx.x + 1) / gridDim.x);
+  if (t0 >= t1) return;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+
+  // clear look-back rows of this range
+  {
+    uint4* st = reinterpret_cast<uint4*>(P.L.status + uint64_t(t0) * kRadix);
+    const uint64_t nq = uint64_t(t1 - t0) * kRadix / 2;
+    for (uint64_t q = tid; q < nq; q += kScatterBlock) st[q] = make_uint4(0, 0, 0, 0);
+  }
+  for (int q = lane; q < kRadix; q += kWave) s_cnt[wave * kRadix + q] = 0;
+
+  const uint32_t* tp = P.L.tile_prefix;
+  uint32_t lo = 0, hi = nbins;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tp[mid] <= t0) lo = mid;
+    else hi = mid;
+  }
+  uint32_t b = lo;
+
+  uint64_t dacc[KW];
+#pragma unroll
+  for (int i = 0; i < KW; ++i) dacc[i] = 0;
+
+  auto flush = [&](uint32_t bb) {
+#pragma unroll
+    for (int i = 0; i < KW; ++i) {
+      const uint64_t v = wave_or(dacc[i]);
+      if (lane == 0) s_diff[wave][i] = v;
+      dacc[i] = 0;
+    }
+    __syncthreads();
+    if (tid < kRadix) {
+      uint32_t s = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        s += s_cnt[w * kRadix + tid];
+        s_cnt[w * kRadix + tid] = 0;
+      }
+      if (s) atomicAdd(P.L.hist[cur] + uint64_t(bb) * kRadix + tid, s);
+    }
+    if (tid < KW) {
+      unsigned long long v = 0;
+      for (int w = 0; w < W; ++w) v |= s_diff[w][tid];
+      if (v) atomicOr((unsigned long long*)(P.L.diff[cur] + uint64_t(bb) * 8 + tid), v);
+    }
+    __syncthreads();
+  };
+
+  Bin bin = P.L.large[cur][b];
+  ArrayDesc arr = P.L.arrays[bin.array];
+  const uint8_t* src = bin.side ? arr.tmp : arr.recs;
+  uint64_t key0[KW];
+  key_of<KW>(reinterpret_cast<const uint64_t*>(src) + uint64_t(bin.start) * RW, P.kmask, key0);
+
+  for (uint32_t t = t0; t < t1; ++t) {
+    while (b + 1 < nbins && t >= tp[b + 1]) {
+      flush(b);
+      ++b;
+      bin = P.L.large[cur][b];
+      arr = P.L.arrays[bin.array];
+      src = bin.side ? arr.tmp : arr.recs;
+      key_of<KW>(reinterpret_cast<const uint64_t*>(src) + uint64_t(bin.start) * RW, P.kmask, key0);
+    }
+    if (tid == 0) P.L.tile_bin[t] = b;
+    const uint32_t k = t - tp[b];
+    const uint32_t tbeg = bin.start + k * TILE;
+    const uint32_t tn = min(TILE, bin.size - k * TILE);
+    const uint32_t ipw = (tn + kWave * W - 1) / (kWave * W);
+    const uint32_t w = min(P.digit_bits, uint32_t(bin.bits));
+    const uint32_t lob = bin.bits - w;
+    const uint64_t* sw = reinterpret_cast<const uint64_t*>(src);
+    uint32_t dg[ITEMS];
+    bool valid[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+      valid[j] = (uint32_t(j) < ipw) && (i < tn);
+      dg[j] = 0;
+      if (valid[j]) {
+        uint64_t key[KW];
+        key_of<KW>(sw + uint64_t(tbeg + i) * RW, P.kmask, key);
+        dg[j] = digit_of<KW>(key, lob, w);
+#pragma unroll
+        for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
+      }
+    }
+    uint32_t* wc = s_cnt + wave * kRadix;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint64_t peers = match_digit(dg[j], valid[j], w);
+      if (valid[j] && __popcll(peers & lanemask_lt()) == 0) wc[dg[j]] += __popcll(peers);
+    }
+  }
+  flush(b);
+}
+
+// ------------------------------------------------------------ round: scatter
+
+// Stable scatter of every active large bin (Sec. 3.2 buffered scatter, done
+// the GPU way).  Tiles are taken in ticket order; each tile ranks its records
+// by digit inside the wave (ballot matching) and across waves (LDS counters),
+// publishes its per-digit counts, looks back over earlier tiles of the same
+// bin for the exclusive prefix, stages the tile in LDS in digit order and
+// writes every digit's run as consecutive, coalesced records.
+template <int RW, int KW, int TOP>
+__global__ void __launch_bounds__(kScatterBlock) k_scatter(Params P, uint32_t cur) {
+  constexpr int ITEMS = scatter_items(RW);
+  constexpr int W = kScatterWaves;
+  constexpr uint32_t TILE = kScatterBlock * ITEMS;
+  extern __shared__ __align__(16) uint8_t smem[];
+  uint64_t* s_rec = reinterpret_cast<uint64_t*>(smem);
+  uint8_t* s_dig = reinterpret_cast<uint8_t*>(s_rec + TILE * RW);
+  uint16_t* s_cnt = reinterpret_cast<uint16_t*>(s_dig + TILE);
+  uint32_t* s_tot = reinterpret_cast<uint32_t*>(s_cnt + W * kRadix);
+  uint32_t* s_off = s_tot + kRadix;
+  uint32_t* s_binoff = s_off + kRadix;
+  uint64_t* s_gbase = reinterpret_cast<uint64_t*>(s_binoff + kRadix);
+  __shared__ uint32_t s_ticket;
+  __shared__ uint32_t s_scan[8];
+
+  Ctrl* c = P.L.ctrl;
+  const uint32_t total = c->round_tiles;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const bool nt = P.nontemporal != 2;
+
+  for (;;) {
+    if (tid == 0) s_ticket = atomicAdd(&c->ticket, 1u);
+    __syncthreads();
+    const uint32_t t = s_ticket;
+    if (t >= total) break;
+    const uint32_t b = P.L.tile_bin[t];
+    const Bin bin = P.L.large[cur][b];
+    const uint32_t k = t - P.L.tile_prefix[b];
+    const ArrayDesc arr = P.L.arrays[bin.array];
+    const uint8_t* src = bin.side ? arr.tmp : arr.recs;
+    uint8_t* dst = bin.side ? arr.recs : arr.tmp;
+    const uint32_t w = min(P.digit_bits, uint32_t(bin.bits));
+    const uint32_t lob = bin.bits - w;
+    const uint32_t nb = 1u << w;
+
+    const uint32_t h = tid < nb ? P.L.hist[cur][uint64_t(b) * kRadix + tid] : 0;
+    bool active = true;
+    if (P.mode != kModePartition) {
+      uint64_t any = 0;
+#pragma unroll
+      for (int i = 0; i < KW; ++i) any |= P.L.diff[cur][uint64_t(b) * 8 + i];
+      active = any != 0;
+      // a digit shared by the whole bin is skipped without moving it
+      active = active && !__syncthreads_or(tid < nb && h == bin.size);
+    }
+    if (!active) {
+      __syncthreads();
+      continue;
+    }
+    block_exclusive_scan256(h, s_binoff, s_scan);
+
+    const uint32_t tbeg = bin.start + k * TILE;
+    const uint32_t tn = min(TILE, bin.size - k * TILE);
+    const uint32_t ipw = (tn + kWave * W - 1) / (kWave * W);
+    uint64_t rec[ITEMS][RW];
+    uint32_t dg[ITEMS], rank[ITEMS];
+    bool valid[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+      valid[j] = (uint32_t(j) < ipw) && (i < tn);
+      dg[j] = 0;
+      if (valid[j]) {
+        load_rec<RW>(src, uint64_t(tbeg) + i, rec[j]);
+        uint64_t key[KW];
+        key_of<KW>(rec[j], P.kmask, key);
+        dg[j] = digit_of<KW>(key, lob, w);
+      }
+    }
+    uint16_t* wc = s_cnt + wave * kRadix;
+    for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
+    wave_rank<ITEMS>(dg, valid, w, wc, rank);
+    __syncthreads();
+    block_digit_scan<W>(s_cnt, s_tot, s_off, s_scan);
+
+    // publish this tile's counts, then look back for the exclusive prefix
+    if (tid < nb) {
+      uint64_t* row = P.L.status + uint64_t(t) * kRadix;
+      const uint64_t cnt = s_tot[tid];
+      uint64_t excl = 0;
+      if (k == 0) {
+        __hip_atomic_store(row + tid, kFlagPrefix | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        __hip_atomic_store(row + tid, kFlagAggregate | cnt, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t j = t - 1;
+        const uint64_t t_start = wall_clock64();
+        uint32_t spins = 0;
+        for (;;) {
+          const uint64_t v = __hip_atomic_load(P.L.status + uint64_t(j) * kRadix + tid,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint64_t flag = v >> 62;
+          if (flag == 0) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 255) == 0) {
+              // bounded wait: 0.2 s at the 100 MHz constant clock, or another
+              // wave already gave up
+              if (wall_clock64() - t_start > 20000000ull ||
+                  __hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                      kErrSpin) {
+                atomicOr(&c->error, kErrSpin);
+                break;
+              }
+            }
+            continue;
+          }
+          excl += v & kValueMask;
+          if (flag == 2) break;
+          --j;
+        }
+        __hip_atomic_store(row + tid, kFlagPrefix | (excl + cnt), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+      s_gbase[tid] = uint64_t(bin.start) + s_binoff[tid] + excl - s_off[tid];
+    }
+
+    // stage the tile in digit order
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (valid[j]) {
+        const uint32_t pos = s_off[dg[j]] + wc[dg[j]] + rank[j];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) s_rec[pos * RW + q] = rec[j][q];
+        s_dig[pos] = uint8_t(dg[j]);
+      }
+    }
+    __syncthreads();
+    bool oob = false;
+    for (uint32_t p = tid; p < tn; p += kScatterBlock) {
+      const uint32_t d = s_dig[p];
+      const uint64_t at = s_gbase[d] + p;
+      // never write outside the bin, whatever the counts say
+      if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_rec + uint64_t(p) * RW, nt);
+      else oob = true;
+    }
+    if (oob) atomicOr(&c->error, kErrBounds);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ round: classify
+
+// Decide what happens to each large bin after the round (Sec. 3.1-3.3): all
+// keys equal -> finished; digit constant -> same bin, next differing digit;
+// otherwise its children become next-round large bins or LDS jobs.  Small
+// siblings are packed greedily into jobs of at most mid_max records (Sec. 3.3
+// remarks that scanning empty sub-bins one by one costs time).
+template <int KW>
+__global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
+  __shared__ uint32_t s_cnt[kRadix], s_off[kRadix], s_scan[8];
+  Ctrl* c = P.L.ctrl;
+  const uint32_t nbins = min(c->large_count[cur], P.L.cap_large);
+  const uint32_t nxt = cur ^ 1;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t b = blockIdx.x; b < nbins; b += gridDim.x) {
+    __syncthreads();
+    const Bin bin = P.L.large[cur][b];
+    const uint32_t w = min(P.digit_bits, uint32_t(bin.bits));
+    const uint32_t lob = bin.bits - w;
+    const uint32_t nb = 1u << w;
+    uint64_t dif[KW];
+#pragma unroll
+    for (int i = 0; i < KW; ++i) dif[i] = P.L.diff[cur][uint64_t(b) * 8 + i];
+    const int tb = top_bit<KW>(dif);
+    if (tb < 0) {  // every key equal: finished where it is
+      if (tid == 0 && bin.side == 1) push_copy(P, bin.array, bin.start, bin.size);
+      continue;
+    }
+    const uint32_t h = tid < nb ? P.L.hist[cur][uint64_t(b) * kRadix + tid] : 0;
+    if (__syncthreads_or(tid < nb && h == bin.size)) {
+      if (tid == 0) {
+        Bin nbn = bin;
+        nbn.bits = uint16_t(tb + 1);
+        push_large(P, nxt, nbn);
+      }
+      continue;
+    }
+    s_cnt[tid] = h;
+    block_exclusive_scan256(h, s_off, s_scan);
+    const uint8_t cside = bin.side ^ 1;
+    if (tid == 0) {
+      atomicAdd(&c->scattered_bins, 1u);
+      atomicAdd(&c->moved_records, (unsigned long long)bin.size);
+    }
+    if (lob == 0) {  // key exhausted: every child holds equal keys
+      if (tid == 0 && cside == 1) push_copy(P, bin.array, bin.start, bin.size);
+      continue;
+    }
+    if (tid < nb && h > P.mid_max) {
+      Bin ch;
+      ch.start = bin.start + s_off[tid];
+      ch.size = h;
+      ch.array = bin.array;
+      ch.bits = uint16_t(lob);
+      ch.side = cside;
+      ch.flags = 0;
+      push_large(P, nxt, ch);
+    }
+    if (tid == 0) {
+      uint32_t js = 0, jn = 0, jc = 0;
+      auto flush = [&]() {
+        if (jn > 0 && !(jn == 1 && cside == 0)) {
+          Bin j;
+          j.start = bin.start + js;
+          j.size = jn;
+          j.array = bin.array;
+          j.bits = uint16_t(jc == 1 ? lob : bin.bits);
+          j.side = cside;
+          j.flags = uint8_t(jc > 1);
+          push_bin(P.L.mid, &c->mid_count, P.L.cap_mid, j, &c->error);
+        }
+        jn = 0;
+        jc = 0;
+      };
+      for (uint32_t d = 0; d < nb; ++d) {
+        const uint32_t cd = s_cnt[d];
+        if (cd == 0) continue;
+        if (cd > P.mid_max) {
+          flush();
+          continue;
+        }
+        if (jn + cd > P.mid_max) flush();
+        if (jn == 0) js = s_off[d];
+        jn += cd;
+        ++jc;
+      }
+      flush();
+    }
+  }
+}
+
+// ------------------------------------------------------------ LDS sorter
+
+// Highest set bit of the boundary bitmap in [lo, p], or -1.
+__device__ __forceinline__ int bm_prev(const uint32_t* bm, int p, int lo) {
+  int w = p >> 5;
+  uint32_t m = bm[w] & (uint32_t(2u << (p & 31)) - 1u);
+  while (!m) {
+    if ((w << 5) <= lo) return -1;
+    --w;
+    m = bm[w];
+  }
+  const int r = (w << 5) + 31 - __clz(m);
+  return r >= lo ? r : -1;
+}
+
+// Lowest set bit of the boundary bitmap in (p, hi], or -1.
+__device__ __forceinline__ int bm_next(const uint32_t* bm, int p, int hi) {
+  if (p >= hi) return -1;
+  const int q = p + 1;
+  int w = q >> 5;
+  uint32_t m = bm[w] & ~((1u << (q & 31)) - 1u);
+  for (;;) {
+    if (m) {
+      const int r = (w << 5) + __ffs(m) - 1;
+      return r <= hi ? r : -1;
+    }
+    ++w;
+    if ((w << 5) > hi) return -1;
+    m = bm[w];
+  }
+}
+
+// Sorts jobs of at most mid_max records entirely in LDS (the small-bin case of
+// Sec. 3.2, with LDS in the role of the cache).  The job is loaded once; then
+// ranges larger than tiny_max are split by stable LDS radix passes, each on
+// the highest digit in which the range's keys differ; ranges of at most
+// tiny_max records are finished by enumeration sort (Sec. 2.2, 3.3): each
+// record's final place is the number of smaller keys plus the number of equal
+// keys before it.  The sorted job is written to recs in one coalesced pass.
+template <int RW, int KW>
+__global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
+  constexpr int ITEMS = mid_items(RW);
+  constexpr int W = kMidWaves;
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint32_t T = P.mid_max;
+  uint64_t* s_rec = reinterpret_cast<uint64_t*>(smem);
+  uint16_t* s_perm = reinterpret_cast<uint16_t*>(s_rec + uint64_t(T) * RW);
+  uint16_t* s_cnt = s_perm;  // ranking counters, not live at the same time as s_perm
+  uint32_t* s_bm =
+      reinterpret_cast<uint32_t*>(s_perm + align_up(T > W * kRadix ? T : W * kRadix, 2));
+  __shared__ uint32_t s_stack[kMidStackCap];
+  __shared__ uint32_t s_top, s_cur;
+  __shared__ uint32_t s_tot[kRadix], s_off[kRadix], s_scan[8];
+  __shared__ unsigned long long s_diff[W][KW];
+
+  Ctrl* c = P.L.ctrl;
+  const uint32_t njobs = min(c->mid_count, P.L.cap_mid);
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t tiny = P.tiny_max;
+
+  for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
+    const Bin job = P.L.mid[jb];
+    const uint32_t m = job.size;
+    if (m > T) {
+      if (tid == 0) atomicOr(&c->error, kErrMidSize);
+      continue;
+    }
+    const ArrayDesc arr = P.L.arrays[job.array];
+    const uint64_t* sw = reinterpret_cast<const uint64_t*>(job.side ? arr.tmp : arr.recs) +
+                         uint64_t(job.start) * RW;
+    uint64_t* dw = reinterpret_cast<uint64_t*>(arr.recs) + uint64_t(job.start) * RW;
+
+    for (uint32_t q = tid; q < m * RW; q += kMidBlock) s_rec[q] = sw[q];
+    for (uint32_t q = tid; q < (m >> 5) + 2; q += kMidBlock) s_bm[q] = 0;
+    if (tid == 0) s_top = 0;
+    __syncthreads();
+    if (tid == 0) {
+      s_bm[0] = 1u;
+      if (m > tiny) {
+        s_stack[0] = m << 16;
+        s_top = 1;
+      }
+    }
+
+    // ---- radix passes over ranges larger than tiny
+    for (;;) {
+      __syncthreads();
+      if (tid == 0) {
+        const uint32_t top = s_top;
+        s_cur = top ? s_stack[top - 1] : 0xFFFFFFFFu;
+        if (top) s_top = top - 1;
+      }
+      __syncthreads();
+      const uint32_t e = s_cur;
+      if (e == 0xFFFFFFFFu) break;
+      const uint32_t rs = e & 0xFFFFu, rn = e >> 16;
+
+      const uint32_t ipw = (rn + kWave * W - 1) / (kWave * W);
+      uint64_t rec[ITEMS][RW];
+      uint32_t dg[ITEMS], rank[ITEMS];
+      bool valid[ITEMS];
+      uint64_t key0[KW], dacc[KW];
+      key_of<KW>(s_rec + uint64_t(rs) * RW, P.kmask, key0);
+#pragma unroll
+      for (int q = 0; q < KW; ++q) dacc[q] = 0;
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+        valid[j] = (uint32_t(j) < ipw) && (i < rn);
+        if (valid[j]) {
+#pragma unroll
+          for (int q = 0; q < RW; ++q) rec[j][q] = s_rec[uint64_t(rs + i) * RW + q];
+          uint64_t key[KW];
+          key_of<KW>(rec[j], P.kmask, key);
+#pragma unroll
+          for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < KW; ++q) {
+        const uint64_t v = wave_or(dacc[q]);
+        if (lane == 0) s_diff[wave][q] = v;
+      }
+      __syncthreads();
+      uint64_t dall[KW];
+#pragma unroll
+      for (int q = 0; q < KW; ++q) {
+        dall[q] = 0;
+        for (int w2 = 0; w2 < W; ++w2) dall[q] |= s_diff[w2][q];
+      }
+      const int tb = top_bit<KW>(dall);
+      if (tb < 0) continue;  // all keys of the range equal: already in order
+      const uint32_t hb = uint32_t(tb) + 1;
+      const uint32_t w = min(P.digit_bits, hb);
+      const uint32_t lob = hb - w;
+      const uint32_t nb = 1u << w;
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        dg[j] = 0;
+        if (valid[j]) {
+          uint64_t key[KW];
+          key_of<KW>(rec[j], P.kmask, key);
+          dg[j] = digit_of<KW>(key, lob, w);
+        }
+      }
+      uint16_t* wc = s_cnt + wave * kRadix;
+      for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
+      wave_rank<ITEMS>(dg, valid, w, wc, rank);
+      __syncthreads();
+      block_digit_scan<W>(s_cnt, s_tot, s_off, s_scan);
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        if (valid[j]) {
+          const uint32_t pos = rs + s_off[dg[j]] + wc[dg[j]] + rank[j];
+#pragma unroll
+          for (int q = 0; q < RW; ++q) s_rec[uint64_t(pos) * RW + q] = rec[j][q];
+        }
+      }
+      if (tid < nb) {
+        const uint32_t cnt = s_tot[tid];
+        if (cnt) {
+          const uint32_t st = rs + s_off[tid];
+          atomicOr(&s_bm[st >> 5], 1u << (st & 31));
+          if (cnt > tiny && lob > 0) {
+            const uint32_t slot = atomicAdd(&s_top, 1u);
+            if (slot < kMidStackCap) s_stack[slot] = st | (cnt << 16);
+            else atomicOr(&c->error, kErrCapacity);
+          }
+        }
+      }
+    }
+
+    // ---- tiny ranges: enumeration sort; everything else stays in place
+    for (uint32_t p = tid; p < m; p += kMidBlock) {
+      uint32_t dest = p;
+      const int lo = int(p) > int(tiny) ? int(p - tiny) : 0;
+      const int s = bm_prev(s_bm, int(p), lo);
+      if (s >= 0) {
+        const int hi = min(s + int(tiny), int(m) - 1);
+        int e = bm_next(s_bm, int(p), hi);
+        if (e < 0 && s + int(tiny) >= int(m)) e = int(m);
+        if (e > 0 && e - s >= 2) {
+          uint64_t kp[KW];
+          key_of<KW>(s_rec + uint64_t(p) * RW, P.kmask, kp);
+          uint32_t r = 0;
+          for (int q = s; q < e; ++q) {
+            uint64_t kq[KW];
+            key_of<KW>(s_rec + uint64_t(q) * RW, P.kmask, kq);
+            r += (key_lt<KW>(kq, kp) || (q < int(p) && key_eq<KW>(kq, kp))) ? 1u : 0u;
+          }
+          dest = uint32_t(s) + r;
+        }
+      }
+      s_perm[dest] = uint16_t(p);
+    }
+    __syncthreads();
+    for (uint32_t p = tid; p < m; p += kMidBlock) {
+      const uint64_t* r = s_rec + uint64_t(s_perm[p]) * RW;
+      uint64_t* o = dw + uint64_t(p) * RW;
+      if constexpr (RW % 2 == 0) {
+#pragma unroll
+        for (int q = 0; q < RW; q += 2) {
+          u64x2 v;
+          v.x = r[q];
+          v.y = r[q + 1];
+          *reinterpret_cast<u64x2*>(o + q) = v;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < RW; ++q) o[q] = r[q];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ copies
+
+template <int RW>
+__global__ void __launch_bounds__(256) k_copy(Params P) {
+  Ctrl* c = P.L.ctrl;
+  const uint32_t njobs = min(c->copy_count, P.L.cap_copy);
+  for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
+    const Bin job = P.L.copy[jb];
+    const ArrayDesc arr = P.L.arrays[job.array];
+    const uint64_t* s = reinterpret_cast<const uint64_t*>(arr.tmp) + uint64_t(job.start) * RW;
+    uint64_t* d = reinterpret_cast<uint64_t*>(arr.recs) + uint64_t(job.start) * RW;
+    const uint64_t words = uint64_t(job.size) * RW;
+    if ((reinterpret_cast<uintptr_t>(s) & 15) == 0 && (reinterpret_cast<uintptr_t>(d) & 15) == 0) {
+      const u64x2* s2 = reinterpret_cast<const u64x2*>(s);
+      u64x2* d2 = reinterpret_cast<u64x2*>(d);
+      for (uint64_t q = threadIdx.x; q < words / 2; q += 256) d2[q] = s2[q];
+      if ((words & 1) && threadIdx.x == 0) d[words - 1] = s[words - 1];
+    } else {
+      for (uint64_t q = threadIdx.x; q < words; q += 256) d[q] = s[q];
+    }
+  }
+}
+
+// ------------------------------------------------------------ step outputs
+
+// Copies the single bin's histogram (and its exclusive prefix) out of the
+// workspace for the step entry points.
+static __global__ void __launch_bounds__(256) k_step_out(Params P) {
+  __shared__ uint32_t s_off[kRadix], s_scan[8];
+  const uint32_t w = min(P.step_width, P.step_bits);
+  const uint32_t nb = 1u << w;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t h = tid < nb ? P.L.hist[0][tid] : 0;
+  block_exclusive_scan256(h, s_off, s_scan);
+  if (tid < nb) {
+    if (P.d_counts_out) P.d_counts_out[tid] = h;
+    if (P.d_offsets_out) P.d_offsets_out[tid] = s_off[tid];
+  }
+}
+
+// ------------------------------------------------------------ launch sequence
+
+template <auto Kern>
+inline void set_lds_limit(uint32_t bytes) {
+  static uint32_t done = 0;
+  if (done < bytes) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(Kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+    done = bytes;
+  }
+}
+
+// Optional measurement events (see raduls_set_profile_events): pairs of
+// events recorded around kernel classes on the launch stream.
+struct ProfileEvents {
+  hipEvent_t ev[2 * kProfileSlots];
+  uint32_t count;
+};
+extern ProfileEvents g_profile;
+
+inline void prof_mark(uint32_t slot, int end, hipStream_t s) {
+  const uint32_t i = 2 * slot + uint32_t(end);
+  if (i < g_profile.count && g_profile.ev[i]) (void)hipEventRecord(g_profile.ev[i], s);
+}
+
+template <int RW, int KW>
+hipError_t run_sequence(const Params& P, hipStream_t s) {
+  set_lds_limit<k_scatter<RW, KW, 1>>(P.scatter_lds_bytes);
+  set_lds_limit<k_scatter<RW, KW, 0>>(P.scatter_lds_bytes);
+  set_lds_limit<k_mid<RW, KW>>(P.mid_lds_bytes);
+  if (P.mode == kModeBatch) {
+    k_zero_ctrl<<<1, 64, 0, s>>>(P);
+    const uint32_t g = P.count ? (P.count + 255) / 256 : 1;
+    k_seed_batch<<<g < 1024 ? g : 1024, 256, 0, s>>>(P);
+  } else {
+    k_seed_single<<<1, 64, 0, s>>>(P);
+  }
+  if (P.mode == kModeHist || P.mode == kModePartition) {
+    k_prep<<<1, 1024, 0, s>>>(P, 0);
+    k_hist<RW, KW, 1><<<P.grid_hist, kScatterBlock, 0, s>>>(P, 0);
+    if (P.mode == kModePartition)
+      k_scatter<RW, KW, 1><<<P.grid_scatter, kScatterBlock, P.scatter_lds_bytes, s>>>(P, 0);
+    k_step_out<<<1, 256, 0, s>>>(P);
+    return hipGetLastError();
+  }
+  for (uint32_t r = 0; r < P.rounds; ++r) {
+    const uint32_t cur = r & 1;
+    const uint32_t slot = r == 0 ? kProfTopHist : kProfRoundHist;
+    k_prep<<<1, 1024, 0, s>>>(P, cur);
+    if (r <= 1) prof_mark(slot, 0, s);
+    if (r == 0) k_hist<RW, KW, 1><<<P.grid_hist, kScatterBlock, 0, s>>>(P, cur);
+    else k_hist<RW, KW, 0><<<P.grid_hist, kScatterBlock, 0, s>>>(P, cur);
+    if (r <= 1) prof_mark(slot, 1, s);
+    if (r <= 1) prof_mark(slot + 1, 0, s);
+    if (r == 0) k_scatter<RW, KW, 1><<<P.grid_scatter, kScatterBlock, P.scatter_lds_bytes, s>>>(P, cur);
+    else k_scatter<RW, KW, 0><<<P.grid_scatter, kScatterBlock, P.scatter_lds_bytes, s>>>(P, cur);
+    if (r <= 1) prof_mark(slot + 1, 1, s);
+    k_classify<KW><<<P.grid_classify, 256, 0, s>>>(P, cur);
+  }
+  prof_mark(kProfMid, 0, s);
+  k_mid<RW, KW><<<P.grid_mid, kMidBlock, P.mid_lds_bytes, s>>>(P);
+  prof_mark(kProfMid, 1, s);
+  k_copy<RW><<<P.grid_copy, 256, 0, s>>>(P);
+  return hipGetLastError();
+}
+
+template <int RW>
+hipError_t run_rw(const Params& P, uint32_t kw, hipStream_t s) {
+  switch (kw) {
+#define RADULS_KW_CASE(N) \
+  case N:                 \
+    if constexpr (N <= RW) return run_sequence<RW, N>(P, s); \
+    break;
+    RADULS_KW_CASE(1)
+    RADULS_KW_CASE(2)
+    RADULS_KW_CASE(3)
+    RADULS_KW_CASE(4)
+    RADULS_KW_CASE(5)
+    RADULS_KW_CASE(6)
+    RADULS_KW_CASE(7)
+    RADULS_KW_CASE(8)
+#undef RADULS_KW_CASE
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace raduls

@@ -1,0 +1,418 @@
+// Host runtime and C ABI of libraduls: argument validation, workspace
+// layout, tuning, launch shapes.  Never allocates, frees or synchronizes in
+// the sort calls.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+
+#include "raduls.h"
+#include "raduls_common.hpp"
+
+namespace raduls {
+struct ProfileEvents {
+  hipEvent_t ev[2 * kProfileSlots];
+  uint32_t count;
+};
+ProfileEvents g_profile = {};
+
+hipError_t run_rw1(const Params&, uint32_t, hipStream_t);
+hipError_t run_rw2(const Params&, uint32_t, hipStream_t);
+hipError_t run_rw3(const Params&, uint32_t, hipStream_t);
+hipError_t run_rw4(const Params&, uint32_t, hipStream_t);
+hipError_t run_rw5(const Params&, uint32_t, hipStream_t);
+hipError_t run_rw6(const Params&, uint32_t, hipStream_t);
+hipError_t run_rw7(const Params&, uint32_t, hipStream_t);
+hipError_t run_rw8(const Params&, uint32_t, hipStream_t);
+
+namespace {
+
+raduls_tuning g_tuning = {};
+std::mutex g_tuning_mu;
+
+raduls_tuning current_tuning() {
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  return g_tuning;
+}
+
+// LDS bytes of one LDS-sort workgroup for jobs of up to T records of RW words;
+// mirrors the carve-up at the top of k_mid.
+uint64_t mid_dynamic_lds(uint32_t T, uint32_t rw) {
+  const uint64_t perm = align_up(std::max<uint64_t>(T, uint64_t(kMidWaves) * kRadix), 2) * 2;
+  return uint64_t(T) * rw * 8 + perm + 4ull * ((T >> 5) + 2);
+}
+
+uint32_t mid_capacity_rw(uint32_t rw) {
+  const uint32_t hard = uint32_t(kMidBlock) * uint32_t(mid_items(int(rw)));
+  const uint64_t budget = kLdsBytes - kMidFixedLds;
+  uint32_t T = hard - hard % 64;
+  while (T > 64 && mid_dynamic_lds(T, rw) > budget) T -= 64;
+  return T;
+}
+
+struct Eff {  // tuning after defaults and clamps, for one record width
+  uint32_t digit_bits, tiny_max, mid_max, tile, nontemporal, grid_blocks;
+};
+
+Eff effective(const raduls_tuning& t, uint32_t R) {
+  const uint32_t rw = R / 8;
+  Eff e;
+  e.digit_bits = t.digit_bits ? std::min<uint32_t>(std::max<uint32_t>(t.digit_bits, 1), 8) : 8;
+  const uint32_t cap = mid_capacity_rw(rw);
+  e.mid_max = t.mid_max ? std::min(t.mid_max, cap) : cap;
+  e.tiny_max = t.tiny_max ? std::min<uint32_t>(std::max<uint32_t>(t.tiny_max, 1), 256) : 32;
+  // ranges waiting for an LDS pass are disjoint and larger than tiny_max,
+  // so this bounds their number by the LDS stack capacity
+  e.tiny_max = std::max<uint32_t>(e.tiny_max, (e.mid_max + kMidStackCap - 1) / kMidStackCap);
+  e.tile = uint32_t(kScatterBlock) * uint32_t(scatter_items(int(rw)));
+  e.nontemporal = t.nontemporal ? t.nontemporal : 1;
+  e.grid_blocks = t.grid_blocks;
+  return e;
+}
+
+struct Shape {
+  uint32_t cap_large, cap_tiles, cap_mid, cap_copy, rounds;
+  uint64_t off_ctrl, off_arrays, off_large[2], off_hist[2], off_diff[2], off_tp, off_tb, off_status,
+      off_mid, off_copy, bytes;
+};
+
+// Capacities of the device lists.  Large bins of one round are disjoint and
+// hold more than mid_max records each; every round consumes at least one key
+// bit per bin, so there are at most ceil(8K / digit_bits) rounds.  LDS jobs:
+// a parent's greedy packing yields at most 2*small/mid_max + (large children)
+// + 2 jobs.  Copy jobs: every record is copied at most once, in chunks.
+Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const Eff& e,
+                 bool step) {
+  Shape s{};
+  const uint64_t T = e.mid_max;
+  s.rounds = step ? 1 : (8 * K + e.digit_bits - 1) / e.digit_bits;
+  const uint64_t large = step ? 1 : n_total / (T + 1) + 1;
+  const uint64_t tiles = n_total / e.tile + large + 1;
+  const uint64_t mid = step ? 1 : 2 * (n_total / std::max<uint64_t>(T, 1) + 1) + 3ull * s.rounds * large + count + 16;
+  const uint64_t copy = step ? 1 : n_total / kCopyChunk + uint64_t(s.rounds) * large + 16;
+  s.cap_large = uint32_t(std::min<uint64_t>(large, 0xFFFFFFFFull));
+  s.cap_tiles = uint32_t(std::min<uint64_t>(tiles, 0xFFFFFFFFull));
+  s.cap_mid = uint32_t(std::min<uint64_t>(mid, 0xFFFFFFFFull));
+  s.cap_copy = uint32_t(std::min<uint64_t>(copy, 0xFFFFFFFFull));
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  s.off_ctrl = take(sizeof(Ctrl));
+  s.off_arrays = take(uint64_t(std::max<uint32_t>(count, 1)) * sizeof(ArrayDesc));
+  for (int i = 0; i < 2; ++i) s.off_large[i] = take(uint64_t(s.cap_large) * sizeof(Bin));
+  for (int i = 0; i < 2; ++i) s.off_hist[i] = take(uint64_t(s.cap_large) * kRadix * 4);
+  for (int i = 0; i < 2; ++i) s.off_diff[i] = take(uint64_t(s.cap_large) * 8 * 8);
+  s.off_tp = take((uint64_t(s.cap_large) + 1) * 4);
+  s.off_tb = take(uint64_t(s.cap_tiles) * 4);
+  s.off_status = take(uint64_t(s.cap_tiles) * kRadix * 8);
+  s.off_mid = take(uint64_t(s.cap_mid) * sizeof(Bin));
+  s.off_copy = take(uint64_t(s.cap_copy) * sizeof(Bin));
+  s.bytes = o;
+  return s;
+}
+
+Layout make_layout(uint8_t* aux, const Shape& s) {
+  Layout L;
+  L.ctrl = reinterpret_cast<Ctrl*>(aux + s.off_ctrl);
+  L.arrays = reinterpret_cast<ArrayDesc*>(aux + s.off_arrays);
+  for (int i = 0; i < 2; ++i) {
+    L.large[i] = reinterpret_cast<Bin*>(aux + s.off_large[i]);
+    L.hist[i] = reinterpret_cast<uint32_t*>(aux + s.off_hist[i]);
+    L.diff[i] = reinterpret_cast<uint64_t*>(aux + s.off_diff[i]);
+  }
+  L.tile_prefix = reinterpret_cast<uint32_t*>(aux + s.off_tp);
+  L.tile_bin = reinterpret_cast<uint32_t*>(aux + s.off_tb);
+  L.status = reinterpret_cast<uint64_t*>(aux + s.off_status);
+  L.mid = reinterpret_cast<Bin*>(aux + s.off_mid);
+  L.copy = reinterpret_cast<Bin*>(aux + s.off_copy);
+  L.cap_large = s.cap_large;
+  L.cap_tiles = s.cap_tiles;
+  L.cap_mid = s.cap_mid;
+  L.cap_copy = s.cap_copy;
+  return L;
+}
+
+int check_shape(uint32_t R, uint32_t K) {
+  if (R < 8 || R > 64 || (R % 8) != 0) return RADULS_E_UNSUPPORTED;
+  if (K == 0 || K > R) return RADULS_E_INVALID;
+  return RADULS_OK;
+}
+
+bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) != 0; }
+
+bool overlap(const void* a, uint64_t an, const void* b, uint64_t bn) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return an && bn && x < y + bn && y < x + an;
+}
+
+// Size check against the allocation that holds `p`, when HIP can tell.
+int check_room(const void* p, uint64_t need) {
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+    (void)hipGetLastError();
+    return RADULS_OK;
+  }
+  const uintptr_t end = reinterpret_cast<uintptr_t>(base) + size;
+  if (reinterpret_cast<uintptr_t>(p) + need > end) return RADULS_E_TMP_SMALL;
+  return RADULS_OK;
+}
+
+struct DevInfo {
+  int cus = 0;
+};
+
+DevInfo device_info() {
+  static std::mutex mu;
+  static DevInfo cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (cache[dev].cus == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    cache[dev].cus = cus;
+  }
+  return cache[dev];
+}
+
+void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t R, uint32_t K,
+                 uint32_t mode, uint32_t count) {
+  P = Params{};
+  P.L = make_layout(aux, s);
+  P.R = R;
+  P.K = K;
+  const uint32_t top = K - 8 * ((K - 1) / 8);  // key bytes in the top word, 1..8
+  P.kmask = top == 8 ? ~0ull : ((1ull << (8 * top)) - 1);
+  P.digit_bits = e.digit_bits;
+  P.tiny_max = e.tiny_max;
+  P.mid_max = e.mid_max;
+  P.tile = e.tile;
+  P.nontemporal = e.nontemporal;
+  P.rounds = s.rounds;
+  P.mode = mode;
+  P.count = count;
+  const DevInfo d = device_info();
+  const uint32_t cus = uint32_t(d.cus);
+  P.grid_hist = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_tiles, 4 * cus));
+  P.grid_scatter = e.grid_blocks ? e.grid_blocks
+                                 : std::max<uint32_t>(1, std::min<uint32_t>(s.cap_tiles, 2 * cus));
+  P.grid_classify = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_large, 4 * cus));
+  P.scatter_lds_bytes = scatter_lds_bytes(int(R / 8));
+  P.mid_lds_bytes = uint32_t(mid_dynamic_lds(e.mid_max, R / 8));
+  const uint32_t per_cu = (P.mid_lds_bytes + kMidFixedLds) * 2 <= kLdsBytes ? 2 : 1;
+  P.grid_mid = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_mid, per_cu * cus));
+  P.grid_copy = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_copy, 2 * cus));
+}
+
+int launch(const Params& P, uint32_t R, uint32_t K, hipStream_t stream) {
+  const uint32_t kw = (K + 7) / 8;
+  hipError_t err;
+  switch (R / 8) {
+    case 1: err = run_rw1(P, kw, stream); break;
+    case 2: err = run_rw2(P, kw, stream); break;
+    case 3: err = run_rw3(P, kw, stream); break;
+    case 4: err = run_rw4(P, kw, stream); break;
+    case 5: err = run_rw5(P, kw, stream); break;
+    case 6: err = run_rw6(P, kw, stream); break;
+    case 7: err = run_rw7(P, kw, stream); break;
+    case 8: err = run_rw8(P, kw, stream); break;
+    default: return RADULS_E_UNSUPPORTED;
+  }
+  return err == hipSuccess ? RADULS_OK : RADULS_E_HIP;
+}
+
+uint64_t aux_offset(uint64_t n, uint32_t R) { return align_up(n * R, 256); }
+
+}  // namespace
+}  // namespace raduls
+
+using namespace raduls;
+
+extern "C" {
+
+int raduls_tmp_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint64_t* out_bytes) {
+  int st = check_shape(rec_bytes, key_bytes);
+  if (st) return st;
+  if (!out_bytes) return RADULS_E_INVALID;
+  if (n >= (1ull << 32)) return RADULS_E_UNSUPPORTED;
+  const Eff e = effective(current_tuning(), rec_bytes);
+  const Shape s = plan_shape(n, 1, rec_bytes, key_bytes, e, false);
+  *out_bytes = aux_offset(n, rec_bytes) + s.bytes;
+  return RADULS_OK;
+}
+
+int raduls_sort(void* recs, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
+                hipStream_t stream) {
+  int st = check_shape(rec_bytes, key_bytes);
+  if (st) return st;
+  if (n >= (1ull << 32)) return RADULS_E_UNSUPPORTED;
+  if (n <= 1) return RADULS_OK;
+  if (!recs || !tmp) return RADULS_E_INVALID;
+  if (misaligned(recs) || misaligned(tmp)) return RADULS_E_ALIGN;
+  const Eff e = effective(current_tuning(), rec_bytes);
+  const Shape s = plan_shape(n, 1, rec_bytes, key_bytes, e, false);
+  const uint64_t need = aux_offset(n, rec_bytes) + s.bytes;
+  if (overlap(recs, n * rec_bytes, tmp, need)) return RADULS_E_INVALID;
+  st = check_room(tmp, need);
+  if (st) return st;
+  Params P;
+  fill_params(P, e, s, static_cast<uint8_t*>(tmp) + aux_offset(n, rec_bytes), rec_bytes,
+              key_bytes, kModeSort, 1);
+  P.recs = static_cast<uint8_t*>(recs);
+  P.tmp = static_cast<uint8_t*>(tmp);
+  P.n = n;
+  if (n <= e.mid_max) P.rounds = 0;
+  return launch(P, rec_bytes, key_bytes, stream);
+}
+
+int raduls_batch_ws_bytes(uint32_t count, uint64_t total_n, uint32_t rec_bytes,
+                          uint32_t key_bytes, uint64_t* out_bytes) {
+  int st = check_shape(rec_bytes, key_bytes);
+  if (st) return st;
+  if (!out_bytes) return RADULS_E_INVALID;
+  const Eff e = effective(current_tuning(), rec_bytes);
+  *out_bytes = plan_shape(total_n, count, rec_bytes, key_bytes, e, false).bytes;
+  return RADULS_OK;
+}
+
+int raduls_sort_batch(const raduls_array* d_arrays, uint32_t count, uint64_t total_n,
+                      uint32_t rec_bytes, uint32_t key_bytes, void* ws, uint64_t ws_bytes,
+                      hipStream_t stream) {
+  int st = check_shape(rec_bytes, key_bytes);
+  if (st) return st;
+  if (count == 0) return RADULS_OK;
+  if (!d_arrays || !ws) return RADULS_E_INVALID;
+  if (misaligned(d_arrays) || misaligned(ws)) return RADULS_E_ALIGN;
+  const Eff e = effective(current_tuning(), rec_bytes);
+  const Shape s = plan_shape(total_n, count, rec_bytes, key_bytes, e, false);
+  if (ws_bytes < s.bytes) return RADULS_E_TMP_SMALL;
+  if (overlap(d_arrays, uint64_t(count) * sizeof(raduls_array), ws, s.bytes))
+    return RADULS_E_INVALID;
+  Params P;
+  fill_params(P, e, s, static_cast<uint8_t*>(ws), rec_bytes, key_bytes, kModeBatch, count);
+  P.d_arrays_in = reinterpret_cast<const ArrayDesc*>(d_arrays);
+  P.total_cap = total_n;
+  return launch(P, rec_bytes, key_bytes, stream);
+}
+
+int raduls_step_ws_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint64_t* out_bytes) {
+  int st = check_shape(rec_bytes, key_bytes);
+  if (st) return st;
+  if (!out_bytes) return RADULS_E_INVALID;
+  if (n >= (1ull << 32)) return RADULS_E_UNSUPPORTED;
+  const Eff e = effective(current_tuning(), rec_bytes);
+  *out_bytes = plan_shape(n, 1, rec_bytes, key_bytes, e, true).bytes;
+  return RADULS_OK;
+}
+
+static int step_common(const void* src, void* dst, uint64_t n, uint32_t R, uint32_t K,
+                       uint32_t bits, uint32_t width, uint32_t* d_counts, uint32_t* d_offsets,
+                       void* ws, uint64_t ws_bytes, uint32_t mode, hipStream_t stream) {
+  int st = check_shape(R, K);
+  if (st) return st;
+  if (n >= (1ull << 32)) return RADULS_E_UNSUPPORTED;
+  if (width < 1 || width > 8 || bits < 1 || bits > 8 * K) return RADULS_E_INVALID;
+  if (!src || !ws || (mode == kModePartition && !dst) || (mode == kModeHist && !d_counts))
+    return RADULS_E_INVALID;
+  if (misaligned(src) || misaligned(ws) || (dst && misaligned(dst))) return RADULS_E_ALIGN;
+  const Eff e = effective(current_tuning(), R);
+  const Shape s = plan_shape(n, 1, R, K, e, true);
+  if (ws_bytes < s.bytes) return RADULS_E_TMP_SMALL;
+  if (mode == kModePartition && overlap(src, n * R, dst, n * R)) return RADULS_E_INVALID;
+  if (overlap(src, n * R, ws, s.bytes) || (dst && overlap(dst, n * R, ws, s.bytes)))
+    return RADULS_E_INVALID;
+  Params P;
+  fill_params(P, e, s, static_cast<uint8_t*>(ws), R, K, mode, 1);
+  P.recs = static_cast<uint8_t*>(const_cast<void*>(src));
+  P.tmp = static_cast<uint8_t*>(dst);
+  P.n = n;
+  P.step_bits = bits;
+  P.step_width = width;
+  P.digit_bits = width;
+  P.d_counts_out = d_counts;
+  P.d_offsets_out = d_offsets;
+  return launch(P, R, K, stream);
+}
+
+int raduls_histogram(const void* recs, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
+                     uint32_t bits, uint32_t width, uint32_t* d_counts, void* ws,
+                     uint64_t ws_bytes, hipStream_t stream) {
+  return step_common(recs, nullptr, n, rec_bytes, key_bytes, bits, width, d_counts, nullptr, ws,
+                     ws_bytes, kModeHist, stream);
+}
+
+int raduls_partition(const void* src, void* dst, uint64_t n, uint32_t rec_bytes,
+                     uint32_t key_bytes, uint32_t bits, uint32_t width, uint32_t* d_offsets,
+                     void* ws, uint64_t ws_bytes, hipStream_t stream) {
+  return step_common(src, dst, n, rec_bytes, key_bytes, bits, width, nullptr, d_offsets, ws,
+                     ws_bytes, kModePartition, stream);
+}
+
+int raduls_check(const void* tmp_or_ws, uint64_t n, uint32_t rec_bytes, int ws_only,
+                 raduls_stats* stats, hipStream_t stream) {
+  if (!tmp_or_ws || !stats) return RADULS_E_INVALID;
+  if (!ws_only && (rec_bytes < 8 || rec_bytes > 64 || rec_bytes % 8)) return RADULS_E_UNSUPPORTED;
+  const uint8_t* base = static_cast<const uint8_t*>(tmp_or_ws) + (ws_only ? 0 : aux_offset(n, rec_bytes));
+  if (hipStreamSynchronize(stream) != hipSuccess) return RADULS_E_HIP;
+  Ctrl c;
+  if (hipMemcpy(&c, base, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) return RADULS_E_HIP;
+  std::memset(stats, 0, sizeof(*stats));
+  stats->error = c.error;
+  stats->rounds = c.rounds;
+  stats->large_bins = c.large_bins;
+  stats->scattered_bins = c.scattered_bins;
+  stats->mid_jobs = c.mid_count;
+  stats->copy_jobs = c.copy_count;
+  stats->moved_records = c.moved_records;
+  stats->large_records = c.large_records;
+  return c.error ? RADULS_E_DEVICE : RADULS_OK;
+}
+
+int raduls_set_tuning(const raduls_tuning* tuning) {
+  if (!tuning) return RADULS_E_INVALID;
+  if (tuning->digit_bits > 8 || tuning->tiny_max > 256 || tuning->nontemporal > 2)
+    return RADULS_E_INVALID;
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  g_tuning = *tuning;
+  return RADULS_OK;
+}
+
+int raduls_get_tuning(raduls_tuning* tuning) {
+  if (!tuning) return RADULS_E_INVALID;
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  *tuning = g_tuning;
+  return RADULS_OK;
+}
+
+int raduls_set_profile_events(hipEvent_t* events, uint32_t count) {
+  if (count > 2 * kProfileSlots || (count && !events)) return RADULS_E_INVALID;
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  for (uint32_t i = 0; i < 2 * kProfileSlots; ++i) g_profile.ev[i] = i < count ? events[i] : nullptr;
+  g_profile.count = count;
+  return RADULS_OK;
+}
+
+uint32_t raduls_mid_capacity(uint32_t rec_bytes) {
+  if (rec_bytes < 8 || rec_bytes > 64 || rec_bytes % 8) return 0;
+  return mid_capacity_rw(rec_bytes / 8);
+}
+
+const char* raduls_strerror(int status) {
+  switch (status) {
+    case RADULS_OK: return "ok";
+    case RADULS_E_INVALID: return "invalid argument";
+    case RADULS_E_ALIGN: return "device pointer not 16-byte aligned";
+    case RADULS_E_TMP_SMALL: return "scratch buffer or workspace too small";
+    case RADULS_E_UNSUPPORTED: return "unsupported record size or record count";
+    case RADULS_E_HIP: return "HIP runtime error";
+    case RADULS_E_DEVICE: return "device reported an error";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,6 @@
+// Kernels for records of 48 bytes (every key width up to the record).
+#include "raduls_kernels.hpp"
+
+namespace raduls {
+hipError_t run_rw6(const Params& P, uint32_t kw, hipStream_t s) { return run_rw<6>(P, kw, s); }
+}  // namespace raduls

@@ -1,0 +1,6 @@
+// Kernels for records of 56 bytes (every key width up to the record).
+#include "raduls_kernels.hpp"
+
+namespace raduls {
+hipError_t run_rw7(const Params& P, uint32_t kw, hipStream_t s) { return run_rw<7>(P, kw, s); }
+}  // namespace raduls

@@ -1,0 +1,118 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/raduls.h declares, and rejects bad arguments before touching HIP."""
+
+import os
+import re
+
+import pytest
+
+from paper_1703_00687_amd import binding as b
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "raduls.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(raduls_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    syms = declared_symbols()
+    for name in ("raduls_sort", "raduls_sort_batch", "raduls_tmp_bytes", "raduls_batch_ws_bytes",
+                 "raduls_histogram", "raduls_partition", "raduls_strerror"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = b.load()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert sorted(b.exported_symbols()) == declared_symbols()
+
+
+def test_bad_record_and_key_sizes():
+    for r in (0, 4, 12, 72, 128):
+        assert b.raduls_sort(0, 0, 100, r, 8, raise_on_error=False) == b.E_UNSUPPORTED
+    assert b.raduls_sort(0, 0, 100, 16, 0, raise_on_error=False) == b.E_INVALID
+    assert b.raduls_sort(0, 0, 100, 16, 17, raise_on_error=False) == b.E_INVALID
+    assert b.raduls_sort(0, 0, 1 << 32, 16, 8, raise_on_error=False) == b.E_UNSUPPORTED
+
+
+def test_trivial_sizes_are_noops():
+    for n in (0, 1):
+        assert b.raduls_sort(0, 0, n, 16, 8, raise_on_error=False) == b.OK
+
+
+def test_pointer_errors_rejected_on_host():
+    assert b.raduls_sort(0, 4096, 100, 16, 8, raise_on_error=False) == b.E_INVALID
+    assert b.raduls_sort(4096, 0, 100, 16, 8, raise_on_error=False) == b.E_INVALID
+    assert b.raduls_sort(4096 + 8, 1 << 30, 100, 16, 8, raise_on_error=False) == b.E_ALIGN
+    assert b.raduls_sort(4096, (1 << 30) + 4, 100, 16, 8, raise_on_error=False) == b.E_ALIGN
+    # tmp overlapping recs
+    assert b.raduls_sort(1 << 20, (1 << 20) + 256, 100, 16, 8, raise_on_error=False) == b.E_INVALID
+    assert b.raduls_sort(1 << 20, (1 << 20) - 256, 100, 16, 8, raise_on_error=False) == b.E_INVALID
+
+
+def test_step_argument_errors():
+    ws = b.raduls_step_ws_bytes(1000, 16, 8)
+    bad = [
+        (16, 8, 0, 8),    # bits 0
+        (16, 8, 65, 8),   # bits beyond the key
+        (16, 8, 64, 0),   # width 0
+        (16, 8, 64, 9),   # width > 8
+    ]
+    for r, k, bits, width in bad:
+        st = b.raduls_histogram(1 << 20, 1000, r, k, bits, width, 1 << 21, 1 << 24, ws,
+                                raise_on_error=False)
+        assert st == b.E_INVALID
+    st = b.raduls_histogram(1 << 20, 1000, 16, 8, 64, 8, 1 << 21, 1 << 24, ws - 1,
+                            raise_on_error=False)
+    assert st == b.E_TMP_SMALL
+    st = b.raduls_partition(1 << 20, 1 << 20, 1000, 16, 8, 64, 8, 0, 1 << 24, ws,
+                            raise_on_error=False)
+    assert st == b.E_INVALID  # src == dst
+
+
+def test_batch_argument_errors():
+    ws = b.raduls_batch_ws_bytes(4, 1000, 16, 8)
+    assert b.raduls_sort_batch(0, 0, 0, 16, 8, 0, 0, raise_on_error=False) == b.OK
+    assert b.raduls_sort_batch(0, 4, 1000, 16, 8, 1 << 24, ws, raise_on_error=False) == b.E_INVALID
+    assert b.raduls_sort_batch(1 << 20, 4, 1000, 16, 8, 1 << 24, ws - 1,
+                               raise_on_error=False) == b.E_TMP_SMALL
+    assert b.raduls_sort_batch(1 << 20, 4, 1000, 12, 8, 1 << 24, ws,
+                               raise_on_error=False) == b.E_UNSUPPORTED
+
+
+def test_size_queries():
+    prev = 0
+    for n in (2, 100, 10000, 1 << 20, 1 << 24, 1 << 28):
+        t = b.raduls_tmp_bytes(n, 16, 8)
+        assert t >= n * 16 and t >= prev
+        prev = t
+    # auxiliary workspace stays a small fraction of the data at scale
+    assert b.raduls_tmp_bytes(1 << 28, 16, 8) < (1 << 28) * 16 * 1.10
+    for r in range(8, 72, 8):
+        cap = b.raduls_mid_capacity(r)
+        assert cap >= 1024 and cap * r <= 160 * 1024
+    assert b.raduls_mid_capacity(12) == 0
+
+
+def test_tuning_roundtrip_and_rejects():
+    prev = b.raduls_set_tuning(digit_bits=5, tiny_max=64)
+    try:
+        t = b.raduls_get_tuning()
+        assert t["digit_bits"] == 5 and t["tiny_max"] == 64
+        with pytest.raises(b.RadulsError):
+            b.raduls_set_tuning(digit_bits=9)
+        with pytest.raises(b.RadulsError):
+            b.raduls_set_tuning(tiny_max=1000)
+    finally:
+        b.raduls_set_tuning(**prev)
+    assert b.raduls_get_tuning() == prev
+
+
+def test_strerror():
+    for st in (b.OK, b.E_INVALID, b.E_ALIGN, b.E_TMP_SMALL, b.E_UNSUPPORTED, b.E_HIP, b.E_DEVICE):
+        assert b.strerror(st) and b.strerror(st) != "unknown status"

@@ -1,0 +1,113 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+The library's sort is stable, so its output must be byte-identical to the
+oracle's stable sort (which also implies the weaker rule: equal key sequence
+and equal record multiset per run of equal keys)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1703_00687_amd import binding as b
+from paper_1703_00687_amd import workloads as wl
+from gpu_helpers import gpu_sort, tuned
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(8, 8), (8, 3), (16, 8), (16, 16), (16, 12), (24, 8), (24, 20), (32, 16), (40, 8),
+          (48, 33), (56, 8), (64, 64), (64, 9)]
+
+
+def _recs(seed, n, r, k, distinct=None):
+    return wl.random_records(np.random.default_rng(seed), n, r, k, distinct)
+
+
+def _assert_parity(out, inp, k):
+    exp = oracle.sort(inp, k)
+    if not np.array_equal(out, exp):
+        assert oracle.parity(out, exp, k), "key sequence or run multisets differ"
+        raise AssertionError("not byte-identical to the stable oracle")
+
+
+@pytest.mark.parametrize("r,k", SHAPES)
+def test_sizes_and_shapes(r, k):
+    cap = b.raduls_mid_capacity(r)
+    sizes = [0, 1, 2, 3, 31, 32, 33, 100, 1000, cap - 1, cap, cap + 1, 3 * cap + 7, 60000]
+    for i, n in enumerate(sizes):
+        for distinct in (None, 7):
+            inp = _recs(1000 * r + 10 * k + i, n, r, k, distinct)
+            out, _ = gpu_sort(inp, k)
+            _assert_parity(out, inp, k)
+
+
+@pytest.mark.parametrize("digit_bits,tiny_max,mid_max", [
+    (8, 32, 0), (8, 8, 0), (8, 256, 0), (8, 32, 64), (8, 16, 300), (1, 32, 2000),
+    (3, 24, 700), (5, 64, 0), (7, 1, 128), (4, 32, 40)])
+@pytest.mark.parametrize("r,k", [(16, 8), (32, 16), (24, 13)])
+def test_tuning_variants(digit_bits, tiny_max, mid_max, r, k):
+    with tuned(digit_bits=digit_bits, tiny_max=tiny_max, mid_max=mid_max):
+        for seed, distinct in ((1, None), (2, 300), (3, 3)):
+            inp = _recs(seed + r + k + digit_bits, 40000, r, k, distinct)
+            out, _ = gpu_sort(inp, k)
+            _assert_parity(out, inp, k)
+
+
+@pytest.mark.parametrize("nontemporal", [1, 2])
+def test_store_policies(nontemporal):
+    with tuned(nontemporal=nontemporal):
+        inp = wl.uniform16(1 << 20)
+        out, stats = gpu_sort(inp, 8)
+        _assert_parity(out, inp, 8)
+        assert stats["rounds"] >= 1 and stats["moved_records"] >= (1 << 20)
+
+
+@pytest.mark.parametrize("name,n", [("uniform8", 1 << 20), ("uniform16", 1 << 22),
+                                    ("zipf16", 1 << 21), ("deep32", 1 << 20)])
+def test_workloads_reduced(name, n):
+    inp, k = wl.make(name, n)
+    out, _ = gpu_sort(inp, k)
+    _assert_parity(out, inp, k)
+
+
+def _adversarial(r, k, n, seed):
+    rng = np.random.default_rng(seed)
+    base = wl.random_records(rng, n, r, k)
+    cases = {"random": base}
+    eq = base.copy()
+    eq[:, :k] = base[0, :k]
+    cases["all_equal"] = eq
+    two = base.copy()
+    two[:, :k] = np.where(rng.integers(0, 2, size=(n, 1)) == 1, base[0, :k], base[1, :k])
+    cases["two_values"] = two
+    cases["sorted"] = oracle.sort(base, k)
+    cases["reverse"] = cases["sorted"][::-1].copy()
+    last = base.copy()
+    last[:, 1:k] = 0x5A
+    cases["last_byte_only"] = last
+    low = base.copy()
+    low[:, :k] = base[0, :k]
+    low[:, 0] = rng.integers(0, 4, size=n, dtype=np.uint8)
+    cases["low_byte_only"] = low
+    one_off = eq.copy()
+    one_off[n // 2, k - 1] ^= 0x80
+    cases["one_different"] = one_off
+    return cases
+
+
+@pytest.mark.parametrize("r,k", [(16, 8), (32, 16), (24, 13), (8, 8)])
+def test_adversarial_keys(r, k):
+    for name, inp in _adversarial(r, k, 150000, r + k).items():
+        out, _ = gpu_sort(inp, k)
+        try:
+            _assert_parity(out, inp, k)
+        except AssertionError as e:
+            raise AssertionError(f"{name}: {e}")
+
+
+def test_deterministic_reruns():
+    inp = wl.zipf16(1 << 19)
+    a, _ = gpu_sort(inp, 8)
+    for _ in range(2):
+        c, _ = gpu_sort(inp, 8)
+        assert np.array_equal(a, c)
