@@ -35,9 +35,13 @@ constexpr int kMidWaves = kMidBlock / kWave;
 __host__ __device__ constexpr int mid_items(int rw) {
   return rw == 1 ? 12 : rw == 2 ? 8 : rw == 3 ? 6 : rw <= 5 ? 4 : 3;
 }
+// Records per lane of a single-wave LDS pass (a wave handles ranges of up to
+// 64 * mid_wave_items records).
+__host__ __device__ constexpr int mid_wave_items(int rw) { return rw <= 2 ? 8 : rw <= 4 ? 4 : 2; }
 constexpr uint32_t kLdsBytes = 160 * 1024;
-constexpr uint32_t kMidStackCap = 512;
-constexpr uint32_t kMidFixedLds = 8 * 1024;  // scan scratch, stack, flags
+constexpr uint32_t kMidListCap = 384;   // ranges waiting for a wave pass (per round)
+constexpr uint32_t kMidBigCap = 64;     // ranges waiting for a workgroup pass
+constexpr uint32_t kMidFixedLds = 8 * 1024;  // static LDS of the LDS sorter (upper bound)
 
 // Finished bins that sit in tmp are copied back in chunks of this many records.
 constexpr uint32_t kCopyChunk = 1u << 16;

@@ -774,33 +774,257 @@ __device__ __forceinline__ int bm_next(const uint32_t* bm, int p, int hi) {
   }
 }
 
-// Sorts jobs of at most mid_max records entirely in LDS (the small-bin case of
-// Sec. 3.2, with LDS in the role of the cache).  The job is loaded once; then
-// ranges larger than tiny_max are split by stable LDS radix passes, each on
-// the highest digit in which the range's keys differ; ranges of at most
-// tiny_max records are finished by enumeration sort (Sec. 2.2, 3.3): each
-// record's final place is the number of smaller keys plus the number of equal
-// keys before it.  The sorted job is written to recs in one coalesced pass.
-template <int RW, int KW>
-__global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
+// LDS state of one LDS-sort workgroup.
+struct MidLds {
+  uint64_t* rec;    // [T * RW] records of the job
+  uint16_t* perm;   // [T] final order (aliases the ranking counters)
+  uint16_t* cnt;    // [kMidWaves * kRadix] per-wave ranking counters
+  uint32_t* bm;     // boundary bitmap: bit p set where a sub-range starts
+  uint32_t* big;    // ranges waiting for a workgroup pass (start | size << 16)
+  uint32_t* list0;    // ranges waiting for a wave pass, double-buffered by round
+  uint32_t* list1;
+  uint32_t* nbig;
+  uint32_t* nlist;    // [2]
+  uint32_t* claim;    // next entry of the current list to claim
+  uint32_t* tot;      // [kRadix]
+  uint32_t* off;      // [kRadix]
+  uint32_t* scan;     // [8]
+  unsigned long long* diff;  // [kMidWaves * KW]
+};
+
+// Route a sub-range by size: > wave capacity -> workgroup pass, > tiny ->
+// wave pass, else enumeration sort later.  Its start is always marked.
+__device__ __forceinline__ void mid_route(const Params& P, MidLds& L, uint32_t st, uint32_t cnt,
+                                          uint32_t bits_left, uint32_t wave_cap, uint32_t lst) {
+  atomicOr(&L.bm[st >> 5], 1u << (st & 31));
+  if (cnt <= P.tiny_max || bits_left == 0) return;
+  const uint32_t e = st | (cnt << 16);
+  if (cnt > wave_cap) {
+    const uint32_t k = atomicAdd(L.nbig, 1u);
+    if (k < kMidBigCap) L.big[k] = e;
+    else atomicOr(&P.L.ctrl->error, kErrCapacity);
+  } else {
+    const uint32_t k = atomicAdd(&L.nlist[lst], 1u);
+    if (k < kMidListCap) (lst ? L.list1 : L.list0)[k] = e;
+    else atomicOr(&P.L.ctrl->error, kErrCapacity);
+  }
+}
+
+// Stable radix pass of the whole workgroup over records [s, s + m): reads them
+// (from global memory for the first pass of a job, else from LDS), finds the
+// highest digit in which their keys differ, writes them to LDS [s, s + m) in
+// digit order and routes the non-empty sub-ranges.  All threads call it.
+template <int RW, int KW, bool FROM_GLOBAL>
+__device__ __forceinline__ void mid_wg_pass(const Params& P, MidLds& L, const uint64_t* gsrc, uint32_t s,
+                            uint32_t m, uint32_t wave_cap) {
   constexpr int ITEMS = mid_items(RW);
   constexpr int W = kMidWaves;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t ipw = (m + kWave * W - 1) / (kWave * W);
+  uint64_t rec[ITEMS][RW];
+  bool valid[ITEMS];
+  uint64_t key0[KW], dacc[KW];
+  if constexpr (FROM_GLOBAL) key_of<KW>(gsrc, P.kmask, key0);
+  else key_of<KW>(L.rec + uint64_t(s) * RW, P.kmask, key0);
+#pragma unroll
+  for (int q = 0; q < KW; ++q) dacc[q] = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+    valid[j] = (uint32_t(j) < ipw) && (i < m);
+    if (valid[j]) {
+      if constexpr (FROM_GLOBAL) load_rec<RW>(reinterpret_cast<const uint8_t*>(gsrc), i, rec[j]);
+      else {
+#pragma unroll
+        for (int q = 0; q < RW; ++q) rec[j][q] = L.rec[uint64_t(s + i) * RW + q];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (valid[j]) {
+      uint64_t key[KW];
+      key_of<KW>(rec[j], P.kmask, key);
+#pragma unroll
+      for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KW; ++q) {
+    const uint64_t v = wave_or(dacc[q]);
+    if (lane == 0) L.diff[wave * KW + q] = v;
+  }
+  __syncthreads();
+  uint64_t dall[KW];
+#pragma unroll
+  for (int q = 0; q < KW; ++q) {
+    dall[q] = 0;
+    for (int w2 = 0; w2 < W; ++w2) dall[q] |= L.diff[w2 * KW + q];
+  }
+  const int tb = top_bit<KW>(dall);
+  if (tb < 0) {  // every key equal: the range is in order; only place it
+    if constexpr (FROM_GLOBAL) {
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        if (valid[j]) {
+          const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+#pragma unroll
+          for (int q = 0; q < RW; ++q) L.rec[uint64_t(s + i) * RW + q] = rec[j][q];
+        }
+      }
+    }
+    if (tid == 0) atomicOr(&L.bm[s >> 5], 1u << (s & 31));
+    __syncthreads();
+    return;
+  }
+  const uint32_t hb = uint32_t(tb) + 1;
+  const uint32_t w = min(P.digit_bits, hb);
+  const uint32_t lob = hb - w;
+  const uint32_t nb = 1u << w;
+  uint32_t dg[ITEMS], rank[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    dg[j] = 0;
+    if (valid[j]) {
+      uint64_t key[KW];
+      key_of<KW>(rec[j], P.kmask, key);
+      dg[j] = digit_of<KW>(key, lob, w);
+    }
+  }
+  uint16_t* wc = L.cnt + wave * kRadix;
+  for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
+  wave_rank<ITEMS>(dg, valid, w, wc, rank);
+  __syncthreads();
+  block_digit_scan<W>(L.cnt, L.tot, L.off, L.scan);
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (valid[j]) {
+      const uint32_t pos = s + L.off[dg[j]] + wc[dg[j]] + rank[j];
+#pragma unroll
+      for (int q = 0; q < RW; ++q) L.rec[uint64_t(pos) * RW + q] = rec[j][q];
+    }
+  }
+  if (tid < nb && L.tot[tid]) mid_route(P, L, s + L.off[tid], L.tot[tid], lob, wave_cap, 0);
+  __syncthreads();
+}
+
+// Stable radix pass of one wave over records [s, s + m), m <= 64 * WI, in
+// place in LDS; sub-ranges go to list `nxt` (or are left for enumeration).
+template <int RW, int KW, int WI>
+__device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32_t s, uint32_t m, uint32_t nxt,
+                              uint32_t wave_cap) {
+  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+  uint64_t rec[WI][RW];
+  bool valid[WI];
+  uint64_t key0[KW], dacc[KW];
+  key_of<KW>(L.rec + uint64_t(s) * RW, P.kmask, key0);
+#pragma unroll
+  for (int q = 0; q < KW; ++q) dacc[q] = 0;
+#pragma unroll
+  for (int j = 0; j < WI; ++j) {
+    const uint32_t i = j * kWave + lane;
+    valid[j] = i < m;
+    if (valid[j]) {
+#pragma unroll
+      for (int q = 0; q < RW; ++q) rec[j][q] = L.rec[uint64_t(s + i) * RW + q];
+      uint64_t key[KW];
+      key_of<KW>(rec[j], P.kmask, key);
+#pragma unroll
+      for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KW; ++q) dacc[q] = wave_or(dacc[q]);
+  const int tb = top_bit<KW>(dacc);
+  if (tb < 0) return;  // all keys equal
+  const uint32_t hb = uint32_t(tb) + 1;
+  const uint32_t w = min(P.digit_bits, hb);
+  const uint32_t lob = hb - w;
+  uint32_t dg[WI], rank[WI];
+#pragma unroll
+  for (int j = 0; j < WI; ++j) {
+    dg[j] = 0;
+    if (valid[j]) {
+      uint64_t key[KW];
+      key_of<KW>(rec[j], P.kmask, key);
+      dg[j] = digit_of<KW>(key, lob, w);
+    }
+  }
+  uint16_t* wc = L.cnt + wave * kRadix;
+#pragma unroll
+  for (int q = 0; q < kRadix / kWave; ++q) wc[lane * 4 + q] = 0;
+  __builtin_amdgcn_wave_barrier();
+  wave_rank<WI>(dg, valid, w, wc, rank);
+  __builtin_amdgcn_wave_barrier();
+  // exclusive scan of the 256 counters inside the wave: 4 per lane
+  uint32_t c[4], sum = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    c[q] = wc[lane * 4 + q];
+    sum += c[q];
+  }
+  const uint32_t incl = wave_inclusive_scan(sum);
+  uint32_t run = incl - sum;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    wc[lane * 4 + q] = uint16_t(run);
+    if (c[q]) mid_route(P, L, s + run, c[q], lob, wave_cap, nxt);
+    run += c[q];
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < WI; ++j) {
+    if (valid[j]) {
+      const uint32_t pos = s + wc[dg[j]] + rank[j];
+#pragma unroll
+      for (int q = 0; q < RW; ++q) L.rec[uint64_t(pos) * RW + q] = rec[j][q];
+    }
+  }
+}
+
+// Sorts jobs of at most mid_max records entirely in LDS (the small-bin case of
+// Sec. 3.2, with LDS in the role of the cache).  A first workgroup-wide radix
+// pass reads the job from HBM straight into registers and writes it to LDS in
+// digit order, on the highest digit in which the job's keys differ.  Ranges
+// still larger than tiny_max get further passes: by the whole workgroup when
+// they exceed one wave's capacity, else by single waves in parallel, round by
+// round.  Ranges of at most tiny_max records are finished by enumeration sort
+// (Sec. 2.2, 3.3): each record's place is the number of smaller keys plus the
+// number of equal keys before it.  The job is written back in one coalesced
+// pass.
+template <int RW, int KW>
+__global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
+  constexpr int W = kMidWaves;
+  constexpr int WI = mid_wave_items(RW);
   extern __shared__ __align__(16) uint8_t smem[];
-  const uint32_t T = P.mid_max;
-  uint64_t* s_rec = reinterpret_cast<uint64_t*>(smem);
-  uint16_t* s_perm = reinterpret_cast<uint16_t*>(s_rec + uint64_t(T) * RW);
-  uint16_t* s_cnt = s_perm;  // ranking counters, not live at the same time as s_perm
-  uint32_t* s_bm =
-      reinterpret_cast<uint32_t*>(s_perm + align_up(T > W * kRadix ? T : W * kRadix, 2));
-  __shared__ uint32_t s_stack[kMidStackCap];
-  __shared__ uint32_t s_top, s_cur;
+  __shared__ uint32_t s_big[kMidBigCap];
+  __shared__ uint32_t s_list[2][kMidListCap];
+  __shared__ uint32_t s_nbig, s_nlist[2], s_claim;
   __shared__ uint32_t s_tot[kRadix], s_off[kRadix], s_scan[8];
-  __shared__ unsigned long long s_diff[W][KW];
+  __shared__ unsigned long long s_diff[W * KW];
+
+  const uint32_t T = P.mid_max;
+  MidLds L;
+  L.rec = reinterpret_cast<uint64_t*>(smem);
+  L.perm = reinterpret_cast<uint16_t*>(L.rec + uint64_t(T) * RW);
+  L.cnt = L.perm;
+  L.bm = reinterpret_cast<uint32_t*>(L.perm + align_up(T > W * kRadix ? T : W * kRadix, 2));
+  L.big = s_big;
+  L.list0 = s_list[0];
+  L.list1 = s_list[1];
+  L.nbig = &s_nbig;
+  L.nlist = s_nlist;
+  L.claim = &s_claim;
+  L.tot = s_tot;
+  L.off = s_off;
+  L.scan = s_scan;
+  L.diff = s_diff;
 
   Ctrl* c = P.L.ctrl;
   const uint32_t njobs = min(c->mid_count, P.L.cap_mid);
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const uint32_t tiny = P.tiny_max;
+  const uint32_t wave_cap = kWave * WI;
 
   for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
     const Bin job = P.L.mid[jb];
@@ -814,132 +1038,78 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
                          uint64_t(job.start) * RW;
     uint64_t* dw = reinterpret_cast<uint64_t*>(arr.recs) + uint64_t(job.start) * RW;
 
-    for (uint32_t q = tid; q < m * RW; q += kMidBlock) s_rec[q] = sw[q];
-    for (uint32_t q = tid; q < (m >> 5) + 2; q += kMidBlock) s_bm[q] = 0;
-    if (tid == 0) s_top = 0;
-    __syncthreads();
+    for (uint32_t q = tid; q < (m >> 5) + 2; q += kMidBlock) L.bm[q] = 0;
     if (tid == 0) {
-      s_bm[0] = 1u;
-      if (m > tiny) {
-        s_stack[0] = m << 16;
-        s_top = 1;
-      }
+      s_nbig = 0;
+      s_nlist[0] = 0;
+      s_nlist[1] = 0;
     }
-
-    // ---- radix passes over ranges larger than tiny
+    __syncthreads();
+    if (m > tiny) {
+      mid_wg_pass<RW, KW, true>(P, L, sw, 0, m, wave_cap);
+    } else {
+      for (uint32_t q = tid; q < m * RW; q += kMidBlock) L.rec[q] = sw[q];
+      if (tid == 0) L.bm[0] = 1u;
+      __syncthreads();
+    }
+    // ranges too large for one wave
     for (;;) {
+      const uint32_t nbig = min(s_nbig, kMidBigCap);
+      if (nbig == 0) break;
+      const uint32_t e = s_big[nbig - 1];
       __syncthreads();
-      if (tid == 0) {
-        const uint32_t top = s_top;
-        s_cur = top ? s_stack[top - 1] : 0xFFFFFFFFu;
-        if (top) s_top = top - 1;
-      }
+      if (tid == 0) s_nbig = nbig - 1;
       __syncthreads();
-      const uint32_t e = s_cur;
-      if (e == 0xFFFFFFFFu) break;
-      const uint32_t rs = e & 0xFFFFu, rn = e >> 16;
-
-      const uint32_t ipw = (rn + kWave * W - 1) / (kWave * W);
-      uint64_t rec[ITEMS][RW];
-      uint32_t dg[ITEMS], rank[ITEMS];
-      bool valid[ITEMS];
-      uint64_t key0[KW], dacc[KW];
-      key_of<KW>(s_rec + uint64_t(rs) * RW, P.kmask, key0);
-#pragma unroll
-      for (int q = 0; q < KW; ++q) dacc[q] = 0;
-#pragma unroll
-      for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t i = wave * ipw * kWave + j * kWave + lane;
-        valid[j] = (uint32_t(j) < ipw) && (i < rn);
-        if (valid[j]) {
-#pragma unroll
-          for (int q = 0; q < RW; ++q) rec[j][q] = s_rec[uint64_t(rs + i) * RW + q];
-          uint64_t key[KW];
-          key_of<KW>(rec[j], P.kmask, key);
-#pragma unroll
-          for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < KW; ++q) {
-        const uint64_t v = wave_or(dacc[q]);
-        if (lane == 0) s_diff[wave][q] = v;
-      }
-      __syncthreads();
-      uint64_t dall[KW];
-#pragma unroll
-      for (int q = 0; q < KW; ++q) {
-        dall[q] = 0;
-        for (int w2 = 0; w2 < W; ++w2) dall[q] |= s_diff[w2][q];
-      }
-      const int tb = top_bit<KW>(dall);
-      if (tb < 0) continue;  // all keys of the range equal: already in order
-      const uint32_t hb = uint32_t(tb) + 1;
-      const uint32_t w = min(P.digit_bits, hb);
-      const uint32_t lob = hb - w;
-      const uint32_t nb = 1u << w;
-#pragma unroll
-      for (int j = 0; j < ITEMS; ++j) {
-        dg[j] = 0;
-        if (valid[j]) {
-          uint64_t key[KW];
-          key_of<KW>(rec[j], P.kmask, key);
-          dg[j] = digit_of<KW>(key, lob, w);
-        }
-      }
-      uint16_t* wc = s_cnt + wave * kRadix;
-      for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
-      wave_rank<ITEMS>(dg, valid, w, wc, rank);
-      __syncthreads();
-      block_digit_scan<W>(s_cnt, s_tot, s_off, s_scan);
-#pragma unroll
-      for (int j = 0; j < ITEMS; ++j) {
-        if (valid[j]) {
-          const uint32_t pos = rs + s_off[dg[j]] + wc[dg[j]] + rank[j];
-#pragma unroll
-          for (int q = 0; q < RW; ++q) s_rec[uint64_t(pos) * RW + q] = rec[j][q];
-        }
-      }
-      if (tid < nb) {
-        const uint32_t cnt = s_tot[tid];
-        if (cnt) {
-          const uint32_t st = rs + s_off[tid];
-          atomicOr(&s_bm[st >> 5], 1u << (st & 31));
-          if (cnt > tiny && lob > 0) {
-            const uint32_t slot = atomicAdd(&s_top, 1u);
-            if (slot < kMidStackCap) s_stack[slot] = st | (cnt << 16);
-            else atomicOr(&c->error, kErrCapacity);
-          }
-        }
-      }
+      mid_wg_pass<RW, KW, false>(P, L, nullptr, e & 0xFFFFu, e >> 16, wave_cap);
     }
+    // medium ranges: one wave each, round by round
+    for (uint32_t cur = 0;; cur ^= 1) {
+      const uint32_t nl = min(s_nlist[cur], kMidListCap);
+      if (nl == 0) break;
+      if (tid == 0) {
+        s_claim = 0;
+        s_nlist[cur ^ 1] = 0;
+      }
+      __syncthreads();
+      for (;;) {
+        uint32_t k = 0;
+        if (lane == 0) k = atomicAdd(&s_claim, 1u);
+        k = __shfl(k, 0);
+        if (k >= nl) break;
+        const uint32_t e = s_list[cur][k];
+        mid_wave_pass<RW, KW, WI>(P, L, e & 0xFFFFu, e >> 16, cur ^ 1, wave_cap);
+      }
+      __syncthreads();
+      if (tid == 0) s_nlist[cur] = 0;
+    }
+    __syncthreads();
 
     // ---- tiny ranges: enumeration sort; everything else stays in place
     for (uint32_t p = tid; p < m; p += kMidBlock) {
       uint32_t dest = p;
       const int lo = int(p) > int(tiny) ? int(p - tiny) : 0;
-      const int s = bm_prev(s_bm, int(p), lo);
+      const int s = bm_prev(L.bm, int(p), lo);
       if (s >= 0) {
         const int hi = min(s + int(tiny), int(m) - 1);
-        int e = bm_next(s_bm, int(p), hi);
+        int e = bm_next(L.bm, int(p), hi);
         if (e < 0 && s + int(tiny) >= int(m)) e = int(m);
         if (e > 0 && e - s >= 2) {
           uint64_t kp[KW];
-          key_of<KW>(s_rec + uint64_t(p) * RW, P.kmask, kp);
+          key_of<KW>(L.rec + uint64_t(p) * RW, P.kmask, kp);
           uint32_t r = 0;
           for (int q = s; q < e; ++q) {
             uint64_t kq[KW];
-            key_of<KW>(s_rec + uint64_t(q) * RW, P.kmask, kq);
+            key_of<KW>(L.rec + uint64_t(q) * RW, P.kmask, kq);
             r += (key_lt<KW>(kq, kp) || (q < int(p) && key_eq<KW>(kq, kp))) ? 1u : 0u;
           }
           dest = uint32_t(s) + r;
         }
       }
-      s_perm[dest] = uint16_t(p);
+      L.perm[dest] = uint16_t(p);
     }
     __syncthreads();
     for (uint32_t p = tid; p < m; p += kMidBlock) {
-      const uint64_t* r = s_rec + uint64_t(s_perm[p]) * RW;
+      const uint64_t* r = L.rec + uint64_t(L.perm[p]) * RW;
       uint64_t* o = dw + uint64_t(p) * RW;
       if constexpr (RW % 2 == 0) {
 #pragma unroll

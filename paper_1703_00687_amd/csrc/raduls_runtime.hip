@@ -59,10 +59,11 @@ Eff effective(const raduls_tuning& t, uint32_t R) {
   e.digit_bits = t.digit_bits ? std::min<uint32_t>(std::max<uint32_t>(t.digit_bits, 1), 8) : 8;
   const uint32_t cap = mid_capacity_rw(rw);
   e.mid_max = t.mid_max ? std::min(t.mid_max, cap) : cap;
-  e.tiny_max = t.tiny_max ? std::min<uint32_t>(std::max<uint32_t>(t.tiny_max, 1), 256) : 32;
-  // ranges waiting for an LDS pass are disjoint and larger than tiny_max,
-  // so this bounds their number by the LDS stack capacity
-  e.tiny_max = std::max<uint32_t>(e.tiny_max, (e.mid_max + kMidStackCap - 1) / kMidStackCap);
+  e.tiny_max = t.tiny_max ? std::min<uint32_t>(std::max<uint32_t>(t.tiny_max, 1), 256) : 64;
+  // ranges waiting for an LDS pass are disjoint and larger than tiny_max
+  // (wave passes) or than one wave's capacity (workgroup passes), so these
+  // bound their number by the LDS list capacities
+  e.tiny_max = std::max<uint32_t>(e.tiny_max, (e.mid_max + kMidListCap - 1) / kMidListCap);
   e.tile = uint32_t(kScatterBlock) * uint32_t(scatter_items(int(rw)));
   e.nontemporal = t.nontemporal ? t.nontemporal : 1;
   e.grid_blocks = t.grid_blocks;
