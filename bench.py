@@ -216,7 +216,7 @@ def main() -> int:
     traffic = load_traffic(n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "k_scatter<2,1,1> (top-level scatter)",
+                "traffic": traffic, "kernel": "k_scatter_carry<2,1,1> (top-level scatter)",
                 "bytes_per_launch": pass_bytes, "mean_launch_ms": round(scat_ms, 4)}
     phase_gbs = {
         "top_hist": n * R / (phases["top_hist"] * 1e-3) / 1e9,

@@ -65,7 +65,11 @@ typedef struct raduls_tuning {
   uint32_t grid_blocks;  /* workgroups of the persistent kernels (default 2 per CU) */
   uint32_t nontemporal;  /* 1: scatter stores use the nontemporal (streaming) cache
                             policy, 2: ordinary stores (default 1) */
-  uint32_t reserved[11];
+  uint32_t lookback;     /* 0 (default): each scatter workgroup walks the contiguous tile
+                            range of the histogram pass and starts from a carry computed
+                            from the per-range counts; 1: tiles taken in ticket order get
+                            their prefix by decoupled look-back over earlier tiles */
+  uint32_t reserved[10];
 } raduls_tuning;
 
 /* Device-side counters left in the workspace by the last sort that used it. */

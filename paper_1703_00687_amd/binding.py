@@ -39,7 +39,8 @@ class raduls_tuning(ctypes.Structure):
         ("mid_max", ctypes.c_uint32),
         ("grid_blocks", ctypes.c_uint32),
         ("nontemporal", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 11),
+        ("lookback", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 10),
     ]
 
 
@@ -63,7 +64,7 @@ class raduls_array(ctypes.Structure):
     _fields_ = [("recs", ctypes.c_void_p), ("tmp", ctypes.c_void_p), ("n", ctypes.c_uint64)]
 
 
-TUNING_FIELDS = ("digit_bits", "tiny_max", "mid_max", "grid_blocks", "nontemporal")
+TUNING_FIELDS = ("digit_bits", "tiny_max", "mid_max", "grid_blocks", "nontemporal", "lookback")
 
 _lib = None
 

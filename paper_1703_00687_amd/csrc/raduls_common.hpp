@@ -43,6 +43,9 @@ constexpr uint32_t kMidListCap = 384;   // ranges waiting for a wave pass (per r
 constexpr uint32_t kMidBigCap = 64;     // ranges waiting for a workgroup pass
 constexpr uint32_t kMidFixedLds = 8 * 1024;  // static LDS of the LDS sorter (upper bound)
 
+// Most workgroups of the histogram / carry-scan scatter grid.
+constexpr uint32_t kMaxRanges = 4096;
+
 // Finished bins that sit in tmp are copied back in chunks of this many records.
 constexpr uint32_t kCopyChunk = 1u << 16;
 
@@ -65,6 +68,8 @@ constexpr uint32_t kProfileSlots = 5;
 constexpr uint64_t kFlagAggregate = 1ull << 62;
 constexpr uint64_t kFlagPrefix = 2ull << 62;
 constexpr uint64_t kValueMask = (1ull << 62) - 1;
+// Earlier tiles read per look-back round trip.
+constexpr int kLookback = 8;
 
 // ---------------------------------------------------------------- descriptors
 
@@ -112,10 +117,13 @@ struct Layout {
   uint64_t* diff[2];      // [cap_large][8]
   uint32_t* tile_prefix;  // [cap_large + 1]
   uint32_t* tile_bin;     // [cap_tiles]: bin index of each tile of the round
-  uint64_t* status;       // [cap_tiles][kRadix]
+  uint64_t* status;       // [cap_tiles][kRadix] look-back status words
+  uint32_t* wg_tail;      // [cap_ranges][kRadix] counts of each range's last bin segment
+  uint32_t* wg_carry;     // [cap_ranges][kRadix] prefix carried into each range
+  uint32_t* wg_flag;      // [cap_ranges] range starts a bin (1) / lies in one bin (2)
   Bin* mid;
   Bin* copy;
-  uint32_t cap_large, cap_tiles, cap_mid, cap_copy;
+  uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges;
 };
 
 enum Mode : uint32_t { kModeSort = 0, kModeBatch = 1, kModeHist = 2, kModePartition = 3 };
@@ -130,6 +138,7 @@ struct Params {
   uint32_t mid_max;       // <= LDS capacity
   uint32_t tile;          // records per scatter tile
   uint32_t nontemporal;
+  uint32_t lookback;      // 1: decoupled look-back scatter, 0: carry scan
   uint32_t rounds;
   uint32_t mode;
   uint32_t count;          // arrays

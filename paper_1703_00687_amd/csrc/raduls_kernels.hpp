@@ -18,9 +18,36 @@ namespace raduls {
 
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
+// Record buffers are reached through pointers stored in descriptors, so the
+// compiler cannot infer their address space and would emit FLAT accesses,
+// which also count against the LDS wait counter and stall every LDS wait
+// behind outstanding HBM traffic.  These casts make them global accesses.
+#define RADULS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const RADULS_GLOBAL T* gmem(const T* p) {
+  return (const RADULS_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ RADULS_GLOBAL T* gmem(T* p) {
+  return (RADULS_GLOBAL T*)p;
+}
+
 // ------------------------------------------------------------ small helpers
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Workgroup barrier for LDS hand-offs.  __syncthreads() also orders global
+// memory, which makes every wave wait for all of its outstanding global loads
+// and stores (vmcnt 0) at each barrier; no barrier in these kernels publishes
+// global data to other threads, so waiting for LDS operations (lgkmcnt 0) is
+// enough and keeps prefetched loads and write-out stores in flight.  The empty
+// asm statements keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // gfx9 encoding: lgkmcnt(0), vmcnt/expcnt not waited
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const uint32_t l = lane_id();
@@ -29,9 +56,9 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 template <int RW>
 __device__ __forceinline__ void load_rec(const uint8_t* base, uint64_t idx, uint64_t (&w)[RW]) {
-  const uint64_t* p = reinterpret_cast<const uint64_t*>(base) + idx * RW;
+  const RADULS_GLOBAL uint64_t* p = gmem(reinterpret_cast<const uint64_t*>(base)) + idx * RW;
   if constexpr (RW % 2 == 0) {
-    const u64x2* q = reinterpret_cast<const u64x2*>(p);
+    const RADULS_GLOBAL u64x2* q = reinterpret_cast<const RADULS_GLOBAL u64x2*>(p);
 #pragma unroll
     for (int i = 0; i < RW / 2; ++i) {
       u64x2 v = q[i];
@@ -46,9 +73,9 @@ __device__ __forceinline__ void load_rec(const uint8_t* base, uint64_t idx, uint
 
 template <int RW>
 __device__ __forceinline__ void store_rec(uint8_t* base, uint64_t idx, const uint64_t* w, bool nt) {
-  uint64_t* p = reinterpret_cast<uint64_t*>(base) + idx * RW;
+  RADULS_GLOBAL uint64_t* p = gmem(reinterpret_cast<uint64_t*>(base)) + idx * RW;
   if constexpr (RW % 2 == 0) {
-    u64x2* q = reinterpret_cast<u64x2*>(p);
+    RADULS_GLOBAL u64x2* q = reinterpret_cast<RADULS_GLOBAL u64x2*>(p);
 #pragma unroll
     for (int i = 0; i < RW / 2; ++i) {
       u64x2 v;
@@ -60,7 +87,7 @@ __device__ __forceinline__ void store_rec(uint8_t* base, uint64_t idx, const uin
   } else {
 #pragma unroll
     for (int i = 0; i < RW; ++i) {
-      if (nt) __builtin_nontemporal_store((unsigned long long)w[i], (unsigned long long*)p + i);
+      if (nt) __builtin_nontemporal_store((unsigned long long)w[i], (RADULS_GLOBAL unsigned long long*)p + i);
       else p[i] = w[i];
     }
   }
@@ -68,8 +95,8 @@ __device__ __forceinline__ void store_rec(uint8_t* base, uint64_t idx, const uin
 
 // Key words of a record (word KW-1 most significant), top word masked to the
 // key bytes it holds.
-template <int KW>
-__device__ __forceinline__ void key_of(const uint64_t* w, uint64_t kmask, uint64_t (&k)[KW]) {
+template <int KW, class Ptr>
+__device__ __forceinline__ void key_of(Ptr w, uint64_t kmask, uint64_t (&k)[KW]) {
 #pragma unroll
   for (int i = 0; i < KW; ++i) k[i] = w[i];
   k[KW - 1] &= kmask;
@@ -146,13 +173,13 @@ __device__ __forceinline__ void block_exclusive_scan256(uint32_t v, uint32_t* ou
     inc = wave_inclusive_scan(v);
     if ((t & 63) == 63) scratch[t >> 6] = inc;
   }
-  __syncthreads();
+  lds_barrier();
   if (t < 256) {
     uint32_t add = 0;
     for (uint32_t w = 0; w < (t >> 6); ++w) add += scratch[w];
     out[t] = inc - v + add;
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Peers of each lane: the valid lanes of this wave holding the same digit,
@@ -408,8 +435,8 @@ __global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) 
   if (t0 >= t1) return;
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 
-  // clear look-back rows of this range
-  {
+  // clear look-back rows of this range (only that scatter uses them)
+  if (P.lookback) {
     uint4* st = reinterpret_cast<uint4*>(P.L.status + uint64_t(t0) * kRadix);
     const uint64_t nq = uint64_t(t1 - t0) * kRadix / 2;
     for (uint64_t q = tid; q < nq; q += kScatterBlock) st[q] = make_uint4(0, 0, 0, 0);
@@ -424,12 +451,13 @@ __global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) 
     else hi = mid;
   }
   uint32_t b = lo;
+  const uint32_t b_first = lo;
 
   uint64_t dacc[KW];
 #pragma unroll
   for (int i = 0; i < KW; ++i) dacc[i] = 0;
 
-  auto flush = [&](uint32_t bb) {
+  auto flush = [&](uint32_t bb, bool last) {
 #pragma unroll
     for (int i = 0; i < KW; ++i) {
       const uint64_t v = wave_or(dacc[i]);
@@ -445,6 +473,8 @@ __global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) 
         s_cnt[w * kRadix + tid] = 0;
       }
       if (s) atomicAdd(P.L.hist[cur] + uint64_t(bb) * kRadix + tid, s);
+      // counts of the range's last bin segment, for the carry scan
+      if (last) P.L.wg_tail[uint64_t(blockIdx.x) * kRadix + tid] = s;
     }
     if (tid < KW) {
       unsigned long long v = 0;
@@ -458,16 +488,16 @@ __global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) 
   ArrayDesc arr = P.L.arrays[bin.array];
   const uint8_t* src = bin.side ? arr.tmp : arr.recs;
   uint64_t key0[KW];
-  key_of<KW>(reinterpret_cast<const uint64_t*>(src) + uint64_t(bin.start) * RW, P.kmask, key0);
+  key_of<KW>(gmem(reinterpret_cast<const uint64_t*>(src)) + uint64_t(bin.start) * RW, P.kmask, key0);
 
   for (uint32_t t = t0; t < t1; ++t) {
     while (b + 1 < nbins && t >= tp[b + 1]) {
-      flush(b);
+      flush(b, false);
       ++b;
       bin = P.L.large[cur][b];
       arr = P.L.arrays[bin.array];
       src = bin.side ? arr.tmp : arr.recs;
-      key_of<KW>(reinterpret_cast<const uint64_t*>(src) + uint64_t(bin.start) * RW, P.kmask, key0);
+      key_of<KW>(gmem(reinterpret_cast<const uint64_t*>(src)) + uint64_t(bin.start) * RW, P.kmask, key0);
     }
     if (tid == 0) P.L.tile_bin[t] = b;
     const uint32_t k = t - tp[b];
@@ -476,7 +506,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) 
     const uint32_t ipw = (tn + kWave * W - 1) / (kWave * W);
     const uint32_t w = min(P.digit_bits, uint32_t(bin.bits));
     const uint32_t lob = bin.bits - w;
-    const uint64_t* sw = reinterpret_cast<const uint64_t*>(src);
+    const RADULS_GLOBAL uint64_t* sw = gmem(reinterpret_cast<const uint64_t*>(src));
     uint32_t dg[ITEMS];
     bool valid[ITEMS];
 #pragma unroll
@@ -499,18 +529,46 @@ __global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) 
       if (valid[j] && __popcll(peers & lanemask_lt()) == 0) wc[dg[j]] += __popcll(peers);
     }
   }
-  flush(b);
+  flush(b, true);
+  if (tid == 0) {
+    // bit 0: the range starts a bin; bit 1: the whole range lies in one bin
+    P.L.wg_flag[blockIdx.x] = (t0 == tp[b_first] ? 1u : 0u) | (b_first == b ? 2u : 0u);
+  }
+}
+
+// Carry of every histogram range: the per-digit count of records of the
+// range's first bin that lie in earlier ranges (the blocked form of the
+// exclusive scan over tiles).  One workgroup, one thread per digit.
+static __global__ void __launch_bounds__(256) k_carry(Params P, uint32_t nranges) {
+  const Ctrl* c = P.L.ctrl;
+  const uint32_t total = c->round_tiles;
+  if (total == 0) return;
+  const uint32_t d = threadIdx.x;
+  uint32_t carry = 0, tail = 0, single = 0;
+  for (uint32_t g = 0; g < nranges; ++g) {
+    const uint32_t t0 = uint32_t(uint64_t(total) * g / nranges);
+    const uint32_t t1 = uint32_t(uint64_t(total) * (g + 1) / nranges);
+    if (t0 >= t1) continue;
+    const uint32_t f = P.L.wg_flag[g];
+    carry = (f & 1u) ? 0u : tail + (single ? carry : 0u);
+    P.L.wg_carry[uint64_t(g) * kRadix + d] = carry;
+    tail = P.L.wg_tail[uint64_t(g) * kRadix + d];
+    single = f & 2u;
+  }
 }
 
 // ------------------------------------------------------------ round: scatter
 
 // Stable scatter of every active large bin (Sec. 3.2 buffered scatter, done
-// the GPU way).  Tiles are taken in ticket order; each tile ranks its records
-// by digit inside the wave (ballot matching) and across waves (LDS counters),
-// publishes its per-digit counts, looks back over earlier tiles of the same
-// bin for the exclusive prefix, stages the tile in LDS in digit order and
-// writes every digit's run as consecutive, coalesced records.
-template <int RW, int KW, int TOP>
+// the GPU way).  Each tile ranks its records by digit inside the wave (ballot
+// matching) and across waves (LDS counters), gets the exclusive prefix of its
+// digit counts over the earlier tiles of its bin, stages the tile in LDS in
+// digit order and writes every digit's run as consecutive, coalesced records.
+// The prefix comes either from the carry scan (LOOKBACK = 0: the workgroup
+// walks the same contiguous tile range the histogram pass used, starting
+// from that range's carry) or from a decoupled look-back over tiles taken in
+// ticket order (LOOKBACK = 1).
+template <int RW, int KW, int TOP, int LOOKBACK>
 __global__ void __launch_bounds__(kScatterBlock) k_scatter(Params P, uint32_t cur) {
   constexpr int ITEMS = scatter_items(RW);
   constexpr int W = kScatterWaves;
@@ -531,11 +589,24 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(Params P, uint32_t cu
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const bool nt = P.nontemporal != 2;
 
-  for (;;) {
-    if (tid == 0) s_ticket = atomicAdd(&c->ticket, 1u);
-    __syncthreads();
-    const uint32_t t = s_ticket;
-    if (t >= total) break;
+  // carry mode: this workgroup's tile range and running prefix (thread d)
+  const uint32_t r0 = LOOKBACK ? 0u : uint32_t(uint64_t(total) * blockIdx.x / gridDim.x);
+  const uint32_t r1 = LOOKBACK ? 0u : uint32_t(uint64_t(total) * (blockIdx.x + 1) / gridDim.x);
+  uint32_t running = 0;
+  if (!LOOKBACK && tid < kRadix && r0 < r1)
+    running = P.L.wg_carry[uint64_t(blockIdx.x) * kRadix + tid];
+
+  for (uint32_t it = r0;; ++it) {
+    uint32_t t;
+    if constexpr (LOOKBACK) {
+      if (tid == 0) s_ticket = atomicAdd(&c->ticket, 1u);
+      __syncthreads();
+      t = s_ticket;
+      if (t >= total) break;
+    } else {
+      t = it;
+      if (t >= r1) break;
+    }
     const uint32_t b = P.L.tile_bin[t];
     const Bin bin = P.L.large[cur][b];
     const uint32_t k = t - P.L.tile_prefix[b];
@@ -546,6 +617,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(Params P, uint32_t cu
     const uint32_t lob = bin.bits - w;
     const uint32_t nb = 1u << w;
 
+    if (!LOOKBACK && k == 0) running = 0;  // a new bin starts inside the range
     const uint32_t h = tid < nb ? P.L.hist[cur][uint64_t(b) * kRadix + tid] : 0;
     bool active = true;
     if (P.mode != kModePartition) {
@@ -586,8 +658,12 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(Params P, uint32_t cu
     __syncthreads();
     block_digit_scan<W>(s_cnt, s_tot, s_off, s_scan);
 
+    if (!LOOKBACK && tid < nb) {
+      s_gbase[tid] = uint64_t(bin.start) + s_binoff[tid] + running - s_off[tid];
+      running += s_tot[tid];
+    }
     // publish this tile's counts, then look back for the exclusive prefix
-    if (tid < nb) {
+    if (LOOKBACK && tid < nb) {
       uint64_t* row = P.L.status + uint64_t(t) * kRadix;
       const uint64_t cnt = s_tot[tid];
       uint64_t excl = 0;
@@ -596,14 +672,34 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(Params P, uint32_t cu
       } else {
         __hip_atomic_store(row + tid, kFlagAggregate | cnt, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
+        // walk back over earlier tiles of the bin, reading kLookback of them
+        // per round trip; stop at the first inclusive prefix
+        const uint32_t first = P.L.tile_prefix[b];
         uint32_t j = t - 1;
         const uint64_t t_start = wall_clock64();
         uint32_t spins = 0;
-        for (;;) {
-          const uint64_t v = __hip_atomic_load(P.L.status + uint64_t(j) * kRadix + tid,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const uint64_t flag = v >> 62;
-          if (flag == 0) {
+        bool done = false;
+        while (!done) {
+          const uint32_t nr = min(uint32_t(kLookback), j - first + 1);
+          uint64_t v[kLookback];
+#pragma unroll
+          for (int i = 0; i < kLookback; ++i)
+            v[i] = uint32_t(i) < nr ? __hip_atomic_load(P.L.status + uint64_t(j - i) * kRadix + tid,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                    : 0;
+          uint32_t used = 0;
+#pragma unroll
+          for (int i = 0; i < kLookback; ++i) {
+            if (done || uint32_t(i) >= nr || used != uint32_t(i)) continue;
+            const uint64_t flag = v[i] >> 62;
+            if (flag == 0) continue;  // not published yet: re-read from here
+            excl += v[i] & kValueMask;
+            ++used;
+            if (flag == 2) done = true;
+          }
+          if (done) break;
+          j -= used;
+          if (used == 0) {
             __builtin_amdgcn_s_sleep(1);
             if ((++spins & 255) == 0) {
               // bounded wait: 0.2 s at the 100 MHz constant clock, or another
@@ -615,11 +711,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(Params P, uint32_t cu
                 break;
               }
             }
-            continue;
           }
-          excl += v & kValueMask;
-          if (flag == 2) break;
-          --j;
         }
         __hip_atomic_store(row + tid, kFlagPrefix | (excl + cnt), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -648,6 +740,146 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(Params P, uint32_t cu
     }
     if (oob) atomicOr(&c->error, kErrBounds);
     __syncthreads();
+  }
+}
+
+// Stable scatter in carry mode (Sec. 3.2 buffered scatter, done the GPU way).
+// The workgroup walks the same contiguous tile range the histogram pass gave
+// it, starting from that range's carry.  Each tile ranks its records by digit
+// inside the wave (ballot matching) and across waves (LDS counters), stages
+// them in LDS in digit order and writes every digit's run as consecutive,
+// coalesced records.  The next tile's loads are issued as soon as the current
+// tile is staged, so they overlap its write-out.
+template <int RW, int KW, int TOP>
+__global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint32_t cur) {
+  constexpr int ITEMS = scatter_items(RW);
+  constexpr int W = kScatterWaves;
+  constexpr uint32_t TILE = kScatterBlock * ITEMS;
+  extern __shared__ __align__(16) uint8_t smem[];
+  uint64_t* s_rec = reinterpret_cast<uint64_t*>(smem);
+  uint8_t* s_dig = reinterpret_cast<uint8_t*>(s_rec + TILE * RW);
+  uint16_t* s_cnt = reinterpret_cast<uint16_t*>(s_dig + TILE);
+  uint32_t* s_tot = reinterpret_cast<uint32_t*>(s_cnt + W * kRadix);
+  uint32_t* s_off = s_tot + kRadix;
+  uint32_t* s_binoff = s_off + kRadix;
+  uint64_t* s_gbase = reinterpret_cast<uint64_t*>(s_binoff + kRadix);
+  __shared__ uint32_t s_scan[8];
+
+  Ctrl* c = P.L.ctrl;
+  const uint32_t total = c->round_tiles;
+  const uint32_t r0 = uint32_t(uint64_t(total) * blockIdx.x / gridDim.x);
+  const uint32_t r1 = uint32_t(uint64_t(total) * (blockIdx.x + 1) / gridDim.x);
+  if (r0 >= r1) return;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const bool nt = P.nontemporal != 2;
+  uint32_t running = tid < kRadix ? P.L.wg_carry[uint64_t(blockIdx.x) * kRadix + tid] : 0;
+
+  // state of the bin the current tile belongs to (uniform)
+  uint32_t b = 0, w = 0, lob = 0, nb = 0;
+  Bin bin{};
+  const uint8_t* src = nullptr;
+  uint8_t* dst = nullptr;
+  bool active = false;
+  auto enter_bin = [&](uint32_t t) {
+    b = P.L.tile_bin[t];
+    bin = P.L.large[cur][b];
+    const ArrayDesc arr = P.L.arrays[bin.array];
+    src = bin.side ? arr.tmp : arr.recs;
+    dst = bin.side ? arr.recs : arr.tmp;
+    w = min(P.digit_bits, uint32_t(bin.bits));
+    lob = bin.bits - w;
+    nb = 1u << w;
+    const uint32_t h = tid < nb ? P.L.hist[cur][uint64_t(b) * kRadix + tid] : 0;
+    active = true;
+    if (P.mode != kModePartition) {
+      uint64_t any = 0;
+#pragma unroll
+      for (int i = 0; i < KW; ++i) any |= P.L.diff[cur][uint64_t(b) * 8 + i];
+      // all keys equal, or a digit shared by the whole bin: nothing moves
+      active = any != 0 && !__syncthreads_or(tid < nb && h == bin.size);
+    }
+    if (active) block_exclusive_scan256(h, s_binoff, s_scan);
+  };
+
+  uint64_t rec[ITEMS][RW];
+  auto tile_span = [&](uint32_t t, uint32_t& tbeg, uint32_t& tn, uint32_t& ipw) {
+    const uint32_t k = t - P.L.tile_prefix[b];
+    tbeg = bin.start + k * TILE;
+    tn = min(TILE, bin.size - k * TILE);
+    ipw = (tn + kWave * W - 1) / (kWave * W);
+  };
+  auto issue_loads = [&](uint32_t t) {
+    uint32_t tbeg, tn, ipw;
+    tile_span(t, tbeg, tn, ipw);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+      if (uint32_t(j) < ipw && i < tn) load_rec<RW>(src, uint64_t(tbeg) + i, rec[j]);
+    }
+  };
+
+  uint32_t t = r0;
+  enter_bin(t);
+  if (active) issue_loads(t);
+  while (t < r1) {
+    if (t == P.L.tile_prefix[b]) running = 0;  // a new bin starts inside the range
+    uint32_t tbeg, tn, ipw;
+    tile_span(t, tbeg, tn, ipw);
+    uint32_t dg[ITEMS];
+    bool valid[ITEMS];
+    if (active) {
+      uint32_t rank[ITEMS];
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+        valid[j] = (uint32_t(j) < ipw) && (i < tn);
+        dg[j] = 0;
+        if (valid[j]) {
+          uint64_t key[KW];
+          key_of<KW>(rec[j], P.kmask, key);
+          dg[j] = digit_of<KW>(key, lob, w);
+        }
+      }
+      uint16_t* wc = s_cnt + wave * kRadix;
+      for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
+      wave_rank<ITEMS>(dg, valid, w, wc, rank);
+      lds_barrier();
+      block_digit_scan<W>(s_cnt, s_tot, s_off, s_scan);
+      if (tid < nb) {
+        s_gbase[tid] = uint64_t(bin.start) + s_binoff[tid] + running - s_off[tid];
+        running += s_tot[tid];
+      }
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        if (valid[j]) {
+          const uint32_t pos = s_off[dg[j]] + wc[dg[j]] + rank[j];
+#pragma unroll
+          for (int q = 0; q < RW; ++q) s_rec[pos * RW + q] = rec[j][q];
+          s_dig[pos] = uint8_t(dg[j]);
+        }
+      }
+      lds_barrier();
+    }
+    const uint32_t next = t + 1;
+    const bool same = next < r1 && P.L.tile_bin[next] == b;
+    if (active && same) issue_loads(next);  // registers are free once staged
+    if (active) {
+      bool oob = false;
+      for (uint32_t p = tid; p < tn; p += kScatterBlock) {
+        const uint32_t d = s_dig[p];
+        const uint64_t at = s_gbase[d] + p;
+        // never write outside the bin, whatever the counts say
+        if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_rec + uint64_t(p) * RW, nt);
+        else oob = true;
+      }
+      if (oob) atomicOr(&c->error, kErrBounds);
+    }
+    lds_barrier();
+    t = next;
+    if (t < r1 && !same) {
+      enter_bin(t);
+      if (active) issue_loads(t);
+    }
   }
 }
 
@@ -824,7 +1056,7 @@ __device__ __forceinline__ void mid_wg_pass(const Params& P, MidLds& L, const ui
   uint64_t rec[ITEMS][RW];
   bool valid[ITEMS];
   uint64_t key0[KW], dacc[KW];
-  if constexpr (FROM_GLOBAL) key_of<KW>(gsrc, P.kmask, key0);
+  if constexpr (FROM_GLOBAL) key_of<KW>(gmem(gsrc), P.kmask, key0);
   else key_of<KW>(L.rec + uint64_t(s) * RW, P.kmask, key0);
 #pragma unroll
   for (int q = 0; q < KW; ++q) dacc[q] = 0;
@@ -982,6 +1214,154 @@ __device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32
   }
 }
 
+// Stable placement of a workgroup's register-held records into LDS [0, m) by
+// the digit [lob, lob + w) (w <= 8), records ordered by (digit, input order).
+template <int RW, int KW, int ITEMS>
+__device__ __forceinline__ void mid_rank_write(const Params& P, MidLds& L,
+                                               const uint64_t (&rec)[ITEMS][RW],
+                                               const bool (&valid)[ITEMS], uint32_t lob,
+                                               uint32_t w) {
+  constexpr int W = kMidWaves;
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t dg[ITEMS], rank[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    dg[j] = 0;
+    if (valid[j]) {
+      uint64_t key[KW];
+      key_of<KW>(rec[j], P.kmask, key);
+      dg[j] = digit_of<KW>(key, lob, w);
+    }
+  }
+  uint16_t* wc = L.cnt + wave * kRadix;
+  for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
+  wave_rank<ITEMS>(dg, valid, w, wc, rank);
+  lds_barrier();
+  block_digit_scan<W>(L.cnt, L.tot, L.off, L.scan);
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (valid[j]) {
+      const uint32_t pos = L.off[dg[j]] + wc[dg[j]] + rank[j];
+#pragma unroll
+      for (int q = 0; q < RW; ++q) L.rec[uint64_t(pos) * RW + q] = rec[j][q];
+    }
+  }
+}
+
+// First split of an LDS job.  The job is read from HBM into registers once;
+// the highest key bit in which its records differ gives the top of the next
+// two digits, and two stable digit passes (lower digit first, so the pair
+// acts as one 2*digit_bits-bit digit) leave the job in LDS ordered by those
+// bits.  Runs of records equal in them are marked in the boundary bitmap;
+// runs longer than tiny_max that still have key bits below are routed to
+// further passes, the rest are finished by enumeration sort.
+template <int RW, int KW>
+__device__ __forceinline__ void mid_first_split(const Params& P, MidLds& L, const uint64_t* gsrc,
+                                                uint32_t m, uint32_t wave_cap) {
+  constexpr int ITEMS = mid_items(RW);
+  constexpr int W = kMidWaves;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t ipw = (m + kWave * W - 1) / (kWave * W);
+  uint64_t rec[ITEMS][RW];
+  bool valid[ITEMS];
+  uint64_t key0[KW], dacc[KW];
+  key_of<KW>(gmem(gsrc), P.kmask, key0);
+#pragma unroll
+  for (int q = 0; q < KW; ++q) dacc[q] = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+    valid[j] = (uint32_t(j) < ipw) && (i < m);
+    if (valid[j]) load_rec<RW>(reinterpret_cast<const uint8_t*>(gsrc), i, rec[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (valid[j]) {
+      uint64_t key[KW];
+      key_of<KW>(rec[j], P.kmask, key);
+#pragma unroll
+      for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KW; ++q) {
+    const uint64_t v = wave_or(dacc[q]);
+    if (lane == 0) L.diff[wave * KW + q] = v;
+  }
+  lds_barrier();
+  uint64_t dall[KW];
+#pragma unroll
+  for (int q = 0; q < KW; ++q) {
+    dall[q] = 0;
+    for (int w2 = 0; w2 < W; ++w2) dall[q] |= L.diff[w2 * KW + q];
+  }
+  const int tb = top_bit<KW>(dall);
+  if (tb < 0) {  // the whole job holds one key: it stays in input order
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (valid[j]) {
+        const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+#pragma unroll
+        for (int q = 0; q < RW; ++q) L.rec[uint64_t(i) * RW + q] = rec[j][q];
+      }
+    }
+    if (tid == 0) L.bm[0] = 1u;
+    lds_barrier();
+    return;
+  }
+  const uint32_t hb = uint32_t(tb) + 1;
+  const uint32_t dw = P.digit_bits;
+  const uint32_t lo2 = hb > 2 * dw ? hb - 2 * dw : 0;
+  const uint32_t wa = min(dw, hb - lo2);
+  mid_rank_write<RW, KW, ITEMS>(P, L, rec, valid, lo2, wa);
+  if (hb > lo2 + wa) {
+    lds_barrier();
+    // reread in LDS order (stable), then place by the upper digit
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+      if (valid[j]) {
+#pragma unroll
+        for (int q = 0; q < RW; ++q) rec[j][q] = L.rec[uint64_t(i) * RW + q];
+      }
+    }
+    mid_rank_write<RW, KW, ITEMS>(P, L, rec, valid, lo2 + wa, hb - lo2 - wa);
+  }
+  lds_barrier();
+  // run starts: the key bits [lo2, hb) differ from the previous record's
+  const uint32_t fw = hb - lo2;
+  for (uint32_t base = wave * kWave; base < m; base += kMidBlock) {
+    const uint32_t p = base + lane;
+    bool start = false;
+    if (p < m) {
+      uint64_t kp[KW];
+      key_of<KW>(L.rec + uint64_t(p) * RW, P.kmask, kp);
+      start = p == 0;
+      if (p > 0) {
+        uint64_t kq[KW];
+        key_of<KW>(L.rec + uint64_t(p - 1) * RW, P.kmask, kq);
+        start = digit_of<KW>(kp, lo2, fw) != digit_of<KW>(kq, lo2, fw);
+      }
+    }
+    const uint64_t bal = __ballot(start);
+    if (lane == 0) {
+      L.bm[base >> 5] = uint32_t(bal);
+      L.bm[(base >> 5) + 1] = uint32_t(bal >> 32);
+    }
+  }
+  lds_barrier();
+  if (lo2 > 0) {
+    for (uint32_t p = tid; p < m; p += kMidBlock) {
+      if (L.bm[p >> 5] & (1u << (p & 31))) {
+        const int e = bm_next(L.bm, int(p), int(m) - 1);
+        const uint32_t len = (e < 0 ? m : uint32_t(e)) - p;
+        if (len > P.tiny_max) mid_route(P, L, p, len, lo2, wave_cap, 0);
+      }
+    }
+  }
+  lds_barrier();
+}
+
 // Sorts jobs of at most mid_max records entirely in LDS (the small-bin case of
 // Sec. 3.2, with LDS in the role of the cache).  A first workgroup-wide radix
 // pass reads the job from HBM straight into registers and writes it to LDS in
@@ -1046,9 +1426,9 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
     }
     __syncthreads();
     if (m > tiny) {
-      mid_wg_pass<RW, KW, true>(P, L, sw, 0, m, wave_cap);
+      mid_first_split<RW, KW>(P, L, sw, m, wave_cap);
     } else {
-      for (uint32_t q = tid; q < m * RW; q += kMidBlock) L.rec[q] = sw[q];
+      for (uint32_t q = tid; q < m * RW; q += kMidBlock) L.rec[q] = gmem(sw)[q];
       if (tid == 0) L.bm[0] = 1u;
       __syncthreads();
     }
@@ -1110,14 +1490,14 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
     __syncthreads();
     for (uint32_t p = tid; p < m; p += kMidBlock) {
       const uint64_t* r = L.rec + uint64_t(L.perm[p]) * RW;
-      uint64_t* o = dw + uint64_t(p) * RW;
+      RADULS_GLOBAL uint64_t* o = gmem(dw) + uint64_t(p) * RW;
       if constexpr (RW % 2 == 0) {
 #pragma unroll
         for (int q = 0; q < RW; q += 2) {
           u64x2 v;
           v.x = r[q];
           v.y = r[q + 1];
-          *reinterpret_cast<u64x2*>(o + q) = v;
+          *reinterpret_cast<RADULS_GLOBAL u64x2*>(o + q) = v;
         }
       } else {
 #pragma unroll
@@ -1137,12 +1517,13 @@ __global__ void __launch_bounds__(256) k_copy(Params P) {
   for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
     const Bin job = P.L.copy[jb];
     const ArrayDesc arr = P.L.arrays[job.array];
-    const uint64_t* s = reinterpret_cast<const uint64_t*>(arr.tmp) + uint64_t(job.start) * RW;
-    uint64_t* d = reinterpret_cast<uint64_t*>(arr.recs) + uint64_t(job.start) * RW;
+    const RADULS_GLOBAL uint64_t* s =
+        gmem(reinterpret_cast<const uint64_t*>(arr.tmp)) + uint64_t(job.start) * RW;
+    RADULS_GLOBAL uint64_t* d = gmem(reinterpret_cast<uint64_t*>(arr.recs)) + uint64_t(job.start) * RW;
     const uint64_t words = uint64_t(job.size) * RW;
     if ((reinterpret_cast<uintptr_t>(s) & 15) == 0 && (reinterpret_cast<uintptr_t>(d) & 15) == 0) {
-      const u64x2* s2 = reinterpret_cast<const u64x2*>(s);
-      u64x2* d2 = reinterpret_cast<u64x2*>(d);
+      const RADULS_GLOBAL u64x2* s2 = reinterpret_cast<const RADULS_GLOBAL u64x2*>(s);
+      RADULS_GLOBAL u64x2* d2 = reinterpret_cast<RADULS_GLOBAL u64x2*>(d);
       for (uint64_t q = threadIdx.x; q < words / 2; q += 256) d2[q] = s2[q];
       if ((words & 1) && threadIdx.x == 0) d[words - 1] = s[words - 1];
     } else {
@@ -1193,10 +1574,22 @@ inline void prof_mark(uint32_t slot, int end, hipStream_t s) {
   if (i < g_profile.count && g_profile.ev[i]) (void)hipEventRecord(g_profile.ev[i], s);
 }
 
+template <int RW, int KW, int TOP>
+inline void launch_scatter(const Params& P, uint32_t cur, hipStream_t s) {
+  if (P.lookback) {
+    k_scatter<RW, KW, TOP, 1><<<P.grid_scatter, kScatterBlock, P.scatter_lds_bytes, s>>>(P, cur);
+  } else {
+    k_carry<<<1, 256, 0, s>>>(P, P.grid_hist);
+    k_scatter_carry<RW, KW, TOP><<<P.grid_hist, kScatterBlock, P.scatter_lds_bytes, s>>>(P, cur);
+  }
+}
+
 template <int RW, int KW>
 hipError_t run_sequence(const Params& P, hipStream_t s) {
-  set_lds_limit<k_scatter<RW, KW, 1>>(P.scatter_lds_bytes);
-  set_lds_limit<k_scatter<RW, KW, 0>>(P.scatter_lds_bytes);
+  set_lds_limit<k_scatter_carry<RW, KW, 1>>(P.scatter_lds_bytes);
+  set_lds_limit<k_scatter_carry<RW, KW, 0>>(P.scatter_lds_bytes);
+  set_lds_limit<k_scatter<RW, KW, 1, 1>>(P.scatter_lds_bytes);
+  set_lds_limit<k_scatter<RW, KW, 0, 1>>(P.scatter_lds_bytes);
   set_lds_limit<k_mid<RW, KW>>(P.mid_lds_bytes);
   if (P.mode == kModeBatch) {
     k_zero_ctrl<<<1, 64, 0, s>>>(P);
@@ -1208,8 +1601,7 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
   if (P.mode == kModeHist || P.mode == kModePartition) {
     k_prep<<<1, 1024, 0, s>>>(P, 0);
     k_hist<RW, KW, 1><<<P.grid_hist, kScatterBlock, 0, s>>>(P, 0);
-    if (P.mode == kModePartition)
-      k_scatter<RW, KW, 1><<<P.grid_scatter, kScatterBlock, P.scatter_lds_bytes, s>>>(P, 0);
+    if (P.mode == kModePartition) launch_scatter<RW, KW, 1>(P, 0, s);
     k_step_out<<<1, 256, 0, s>>>(P);
     return hipGetLastError();
   }
@@ -1222,8 +1614,8 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
     else k_hist<RW, KW, 0><<<P.grid_hist, kScatterBlock, 0, s>>>(P, cur);
     if (r <= 1) prof_mark(slot, 1, s);
     if (r <= 1) prof_mark(slot + 1, 0, s);
-    if (r == 0) k_scatter<RW, KW, 1><<<P.grid_scatter, kScatterBlock, P.scatter_lds_bytes, s>>>(P, cur);
-    else k_scatter<RW, KW, 0><<<P.grid_scatter, kScatterBlock, P.scatter_lds_bytes, s>>>(P, cur);
+    if (r == 0) launch_scatter<RW, KW, 1>(P, cur, s);
+    else launch_scatter<RW, KW, 0>(P, cur, s);
     if (r <= 1) prof_mark(slot + 1, 1, s);
     k_classify<KW><<<P.grid_classify, 256, 0, s>>>(P, cur);
   }

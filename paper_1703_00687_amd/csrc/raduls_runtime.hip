@@ -50,7 +50,7 @@ uint32_t mid_capacity_rw(uint32_t rw) {
 }
 
 struct Eff {  // tuning after defaults and clamps, for one record width
-  uint32_t digit_bits, tiny_max, mid_max, tile, nontemporal, grid_blocks;
+  uint32_t digit_bits, tiny_max, mid_max, tile, nontemporal, grid_blocks, lookback;
 };
 
 Eff effective(const raduls_tuning& t, uint32_t R) {
@@ -67,13 +67,14 @@ Eff effective(const raduls_tuning& t, uint32_t R) {
   e.tile = uint32_t(kScatterBlock) * uint32_t(scatter_items(int(rw)));
   e.nontemporal = t.nontemporal ? t.nontemporal : 1;
   e.grid_blocks = t.grid_blocks;
+  e.lookback = t.lookback ? 1 : 0;
   return e;
 }
 
 struct Shape {
-  uint32_t cap_large, cap_tiles, cap_mid, cap_copy, rounds;
+  uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges, rounds;
   uint64_t off_ctrl, off_arrays, off_large[2], off_hist[2], off_diff[2], off_tp, off_tb, off_status,
-      off_mid, off_copy, bytes;
+      off_tail, off_carry, off_flag, off_mid, off_copy, bytes;
 };
 
 // Capacities of the device lists.  Large bins of one round are disjoint and
@@ -94,6 +95,9 @@ Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const
   s.cap_tiles = uint32_t(std::min<uint64_t>(tiles, 0xFFFFFFFFull));
   s.cap_mid = uint32_t(std::min<uint64_t>(mid, 0xFFFFFFFFull));
   s.cap_copy = uint32_t(std::min<uint64_t>(copy, 0xFFFFFFFFull));
+  s.cap_ranges = uint32_t(std::min<uint64_t>(tiles, kMaxRanges));
+  // look-back status rows are needed only when that scatter is selected
+  const uint64_t status_rows = e.lookback ? s.cap_tiles : 1;
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) {
     const uint64_t at = o;
@@ -107,7 +111,10 @@ Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const
   for (int i = 0; i < 2; ++i) s.off_diff[i] = take(uint64_t(s.cap_large) * 8 * 8);
   s.off_tp = take((uint64_t(s.cap_large) + 1) * 4);
   s.off_tb = take(uint64_t(s.cap_tiles) * 4);
-  s.off_status = take(uint64_t(s.cap_tiles) * kRadix * 8);
+  s.off_status = take(status_rows * kRadix * 8);
+  s.off_tail = take(uint64_t(s.cap_ranges) * kRadix * 4);
+  s.off_carry = take(uint64_t(s.cap_ranges) * kRadix * 4);
+  s.off_flag = take(uint64_t(s.cap_ranges) * 4);
   s.off_mid = take(uint64_t(s.cap_mid) * sizeof(Bin));
   s.off_copy = take(uint64_t(s.cap_copy) * sizeof(Bin));
   s.bytes = o;
@@ -126,6 +133,10 @@ Layout make_layout(uint8_t* aux, const Shape& s) {
   L.tile_prefix = reinterpret_cast<uint32_t*>(aux + s.off_tp);
   L.tile_bin = reinterpret_cast<uint32_t*>(aux + s.off_tb);
   L.status = reinterpret_cast<uint64_t*>(aux + s.off_status);
+  L.wg_tail = reinterpret_cast<uint32_t*>(aux + s.off_tail);
+  L.wg_carry = reinterpret_cast<uint32_t*>(aux + s.off_carry);
+  L.wg_flag = reinterpret_cast<uint32_t*>(aux + s.off_flag);
+  L.cap_ranges = s.cap_ranges;
   L.mid = reinterpret_cast<Bin*>(aux + s.off_mid);
   L.copy = reinterpret_cast<Bin*>(aux + s.off_copy);
   L.cap_large = s.cap_large;
@@ -194,12 +205,13 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
   P.mid_max = e.mid_max;
   P.tile = e.tile;
   P.nontemporal = e.nontemporal;
+  P.lookback = e.lookback;
   P.rounds = s.rounds;
   P.mode = mode;
   P.count = count;
   const DevInfo d = device_info();
   const uint32_t cus = uint32_t(d.cus);
-  P.grid_hist = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_tiles, 4 * cus));
+  P.grid_hist = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_ranges, 4 * cus));
   P.grid_scatter = e.grid_blocks ? e.grid_blocks
                                  : std::max<uint32_t>(1, std::min<uint32_t>(s.cap_tiles, 2 * cus));
   P.grid_classify = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_large, 4 * cus));

@@ -46,16 +46,17 @@ def test_sizes_and_shapes(r, k):
     (3, 24, 700), (5, 64, 0), (7, 1, 128), (4, 32, 40)])
 @pytest.mark.parametrize("r,k", [(16, 8), (32, 16), (24, 13)])
 def test_tuning_variants(digit_bits, tiny_max, mid_max, r, k):
-    with tuned(digit_bits=digit_bits, tiny_max=tiny_max, mid_max=mid_max):
+    lookback = (digit_bits + tiny_max) % 2  # both scatter scans across the grid
+    with tuned(digit_bits=digit_bits, tiny_max=tiny_max, mid_max=mid_max, lookback=lookback):
         for seed, distinct in ((1, None), (2, 300), (3, 3)):
             inp = _recs(seed + r + k + digit_bits, 40000, r, k, distinct)
             out, _ = gpu_sort(inp, k)
             _assert_parity(out, inp, k)
 
 
-@pytest.mark.parametrize("nontemporal", [1, 2])
-def test_store_policies(nontemporal):
-    with tuned(nontemporal=nontemporal):
+@pytest.mark.parametrize("nontemporal,lookback", [(1, 0), (2, 0), (1, 1), (2, 1)])
+def test_store_policies_and_scans(nontemporal, lookback):
+    with tuned(nontemporal=nontemporal, lookback=lookback):
         inp = wl.uniform16(1 << 20)
         out, stats = gpu_sort(inp, 8)
         _assert_parity(out, inp, 8)

@@ -64,8 +64,16 @@ def test_partition_step(bits, width, n):
     assert np.array_equal(src.cpu().numpy().reshape(n, r), inp)
 
 
-def test_partition_full_tile_grid_uniform():
-    """Several thousand tiles with ragged tail: the look-back across tiles."""
+@pytest.mark.parametrize("lookback", [0, 1])
+def test_partition_full_tile_grid_uniform(lookback):
+    """Several thousand tiles with ragged tail: the prefix across tiles, by
+    carry scan and by look-back."""
+    from gpu_helpers import tuned
+    with tuned(lookback=lookback):
+        _partition_full_tile_grid()
+
+
+def _partition_full_tile_grid():
     n = (1 << 22) + 123
     inp = wl.uniform16(n)
     src = torch.from_numpy(inp.reshape(-1).copy()).cuda()
