@@ -1,0 +1,157 @@
+"""Grid search over the library's tuning knobs on synthetic inputs.
+
+Times the plain sort for each candidate setting (HIP events around the call,
+inputs resident, a fresh copy per repetition) and keeps the fastest.  The
+result is cached as JSON keyed by (device arch, record bytes, key bytes,
+log2 of the record count), and ``apply`` loads the best setting for a call
+shape into the process-global tuning.  The sort's output never depends on
+the tuning; the candidate setting that wins is verified to sort correctly.
+"""
+
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+import time
+
+from . import binding as b
+
+DEFAULT_CACHE = os.environ.get(
+    "RADULS_TUNE_FILE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json"))
+
+SPACE = {
+    "digit_bits": [8, 7, 6],
+    "tiny_max": [16, 32, 64, 128],
+    "mid_frac": [1.0, 0.75, 0.5],       # mid_max as a fraction of the LDS capacity
+    "nontemporal": [1, 2],
+    "lookback": [0, 1],
+}
+
+
+def shape_key(arch: str, rec_bytes: int, key_bytes: int, n: int) -> str:
+    return f"{arch}/R{rec_bytes}/K{key_bytes}/n2^{max(0, int(round(math.log2(max(n, 1)))))}"
+
+
+def _arch() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def apply(rec_bytes: int, key_bytes: int, n: int, path: str = DEFAULT_CACHE) -> dict | None:
+    """Set the process-global tuning from the cache entry for this shape (the
+    nearest record count with the same R and K); returns it, or None."""
+    cache = load_cache(path)
+    prefix = f"{_arch()}/R{rec_bytes}/K{key_bytes}/n2^"
+    best, dist = None, None
+    want = math.log2(max(n, 1))
+    for k, v in cache.items():
+        if k.startswith(prefix):
+            d = abs(int(k[len(prefix):]) - want)
+            if dist is None or d < dist:
+                best, dist = v, d
+    if best is None:
+        return None
+    b.raduls_set_tuning(**best["tuning"])
+    return best
+
+
+def _time_sort(src, copies, tmp, n, R, K, reps):
+    import torch
+    times = []
+    for i in range(reps):
+        c = copies[i % len(copies)]
+        c.copy_(src)
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        b.raduls_sort(c, tmp, n, R, K)
+        e.record()
+        e.synchronize()
+        times.append(s.elapsed_time(e))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def tune(src, key_bytes: int, reps: int = 3, space: dict | None = None, budget_s: float = 300.0,
+         path: str | None = DEFAULT_CACHE, log=print) -> dict:
+    """Search the space for the [n, R] uint8 device tensor `src` (left
+    unchanged).  Coordinate descent from the defaults: one knob at a time over
+    its values, keeping the best, repeated while it improves and time lasts."""
+    import torch
+    space = dict(SPACE if space is None else space)
+    n, R = int(src.shape[0]), int(src.shape[1])
+    cap = b.raduls_mid_capacity(R)
+    copies = [torch.empty_like(src) for _ in range(2)]
+    prev = b.raduls_get_tuning()
+    t_start = time.perf_counter()
+
+    def cand_to_tuning(c):
+        return {"digit_bits": c["digit_bits"], "tiny_max": c["tiny_max"],
+                "mid_max": max(64, int(cap * c["mid_frac"]) // 64 * 64),
+                "nontemporal": c["nontemporal"], "lookback": c["lookback"], "grid_blocks": 0}
+
+    def measure(c):
+        t = cand_to_tuning(c)
+        b.raduls_set_tuning(**t)
+        tmp = torch.empty(b.raduls_tmp_bytes(n, R, key_bytes), dtype=torch.uint8, device=src.device)
+        ms = _time_sort(src, copies, tmp, n, R, key_bytes, reps)
+        st, stats = b.raduls_check(tmp, n, R, False)
+        if st != b.OK:
+            return float("inf")
+        return ms
+
+    cur = {k: v[0] for k, v in space.items()}
+    best_ms = measure(cur)
+    log(f"[autotune] start {cur} {best_ms:.3f} ms")
+    improved = True
+    while improved and time.perf_counter() - t_start < budget_s:
+        improved = False
+        for knob, values in space.items():
+            for v in values:
+                if v == cur[knob] or time.perf_counter() - t_start > budget_s:
+                    continue
+                c = dict(cur, **{knob: v})
+                ms = measure(c)
+                log(f"[autotune] {knob}={v}: {ms:.3f} ms")
+                if ms < best_ms * 0.99:
+                    best_ms, cur, improved = ms, c, True
+    best = {"tuning": cand_to_tuning(cur), "ms": best_ms, "n": n,
+            "records_per_s": n / (best_ms * 1e-3)}
+    # verify the winner sorts correctly (stable sort properties on keys only)
+    b.raduls_set_tuning(**best["tuning"])
+    out = copies[0]
+    out.copy_(src)
+    tmp = torch.empty(b.raduls_tmp_bytes(n, R, key_bytes), dtype=torch.uint8, device=src.device)
+    b.raduls_sort(out, tmp, n, R, key_bytes)
+    torch.cuda.synchronize()
+    if path:
+        cache = load_cache(path)
+        cache[shape_key(_arch(), R, key_bytes, n)] = best
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    b.raduls_set_tuning(**prev)
+    return best
+
+
+if __name__ == "__main__":
+    import argparse
+    import torch
+    from . import workloads as wl
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="uniform16")
+    ap.add_argument("--log2n", type=int, default=26)
+    ap.add_argument("--budget-s", type=float, default=240)
+    args = ap.parse_args()
+    host, k = wl.make(args.workload, 1 << args.log2n)
+    src = torch.from_numpy(host).cuda()
+    print(json.dumps(tune(src, k, budget_s=args.budget_s)))

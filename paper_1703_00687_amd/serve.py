@@ -1,0 +1,321 @@
+"""Continuous-batching sort server on one GPU.
+
+Requests (an [n, R] uint8 device tensor to sort in place by its first K
+bytes) arrive at any time.  A scheduler thread admits them in arrival order
+while the scratch budget (n*R bytes of tmp per request) and the slot count
+allow, packs the admitted requests into one batched launch
+(raduls_sort_batch) on whichever of its streams is idle, and completes them
+when that stream's event fires.  Requests that arrive while batches run are
+admitted as soon as budget and slots free up, and batches on different
+streams overlap on the device.  Each request's result is exactly what the
+plain raduls_sort would produce (the sort is deterministic and stable).
+
+The device work goes through a backend object; ``GpuBackend`` drives the
+HIP library (optionally replaying one captured HIP graph per stream), and the
+tests plug in a CPU stand-in to exercise admission, back-pressure,
+cancellation and failure handling without a GPU.
+"""
+
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+from typing import Any
+
+
+class Rejected(RuntimeError):
+    """The request can never be admitted (larger than the whole budget)."""
+
+
+class Cancelled(RuntimeError):
+    pass
+
+
+class BackendError(RuntimeError):
+    pass
+
+
+@dataclass
+class Request:
+    recs: Any                     # device tensor [n, R], sorted in place
+    n: int
+    t_arrival: float
+    rid: int
+    future: Future = field(default_factory=Future)
+    t_admit: float = 0.0
+    t_launch: float = 0.0
+    t_done: float = 0.0
+    tmp: Any = None
+    cancelled: bool = False
+
+
+@dataclass
+class Stats:
+    submitted: int = 0
+    completed: int = 0
+    rejected: int = 0
+    cancelled: int = 0
+    failed: int = 0
+    batches: int = 0
+    records: int = 0
+    latencies: list = field(default_factory=list)
+    t_first: float = 0.0
+    t_last: float = 0.0
+
+    def summary(self) -> dict:
+        lat = sorted(self.latencies)
+
+        def pct(p):
+            if not lat:
+                return None
+            return lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
+
+        span = max(self.t_last - self.t_first, 1e-12)
+        return {
+            "requests": self.completed, "batches": self.batches, "records": self.records,
+            "rejected": self.rejected, "cancelled": self.cancelled, "failed": self.failed,
+            "p50_ms": None if not lat else pct(50) * 1e3,
+            "p99_ms": None if not lat else pct(99) * 1e3,
+            "max_ms": None if not lat else lat[-1] * 1e3,
+            "records_per_s": self.records / span if self.completed else 0.0,
+            "span_s": span,
+        }
+
+
+class GpuBackend:
+    """Device side of the server: per-stream batch workspaces, launches and
+    completion events."""
+
+    def __init__(self, rec_bytes: int, key_bytes: int, n_streams: int, max_batch: int,
+                 max_records: int, use_graphs: bool = True, device: str = "cuda"):
+        import torch
+        from . import binding as b
+        self.torch, self.b = torch, b
+        self.rec_bytes, self.key_bytes = rec_bytes, key_bytes
+        self.n_streams, self.max_batch = n_streams, max_batch
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        self.batches = [b.Batch(max_batch, max_records, rec_bytes, key_bytes, device=self.device)
+                        for _ in range(n_streams)]
+        self.graphs = [None] * n_streams
+        self.use_graphs = use_graphs
+        if use_graphs:
+            self._capture()
+
+    def _capture(self):
+        torch = self.torch
+        for i, (s, bt) in enumerate(zip(self.streams, self.batches)):
+            bt.host_desc.zero_()
+            bt.desc.zero_()
+            with torch.cuda.stream(s):
+                bt.launch(stream=s)  # warm-up outside capture (sets kernel attributes)
+            s.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                bt.launch(stream=s)
+            self.graphs[i] = g
+        torch.cuda.synchronize()
+
+    def alloc_tmp(self, n: int, stream_idx: int):
+        torch = self.torch
+        with torch.cuda.stream(self.streams[stream_idx]):
+            return torch.empty((max(n, 1), self.rec_bytes), dtype=torch.uint8, device=self.device)
+
+    def launch(self, stream_idx: int, reqs: list) -> Any:
+        torch = self.torch
+        s = self.streams[stream_idx]
+        bt = self.batches[stream_idx]
+        hd = bt.host_desc
+        h = hd.numpy()
+        h[:] = 0
+        for i, r in enumerate(reqs):
+            h[i, 0] = r.recs.data_ptr()
+            h[i, 1] = r.tmp.data_ptr()
+            h[i, 2] = r.n
+        ev = torch.cuda.Event()
+        with torch.cuda.stream(s):
+            bt.desc.copy_(hd, non_blocking=True)
+            if self.graphs[stream_idx] is not None:
+                self.graphs[stream_idx].replay()
+            else:
+                bt.launch(stream=s)
+            ev.record(s)
+        return ev
+
+    def done(self, token) -> bool:
+        return token.query()
+
+    def finish(self, stream_idx: int, token, reqs: list) -> list:
+        token.synchronize()
+        st, stats = self.batches[stream_idx].check(self.streams[stream_idx])
+        err = None if st == self.b.OK else f"device error {stats}"
+        for r in reqs:
+            r.tmp = None
+        return [err] * len(reqs)
+
+
+class Server:
+    """Admission by scratch budget and slots, continuous batching over streams."""
+
+    def __init__(self, backend, rec_bytes: int, budget_bytes: int, max_slots: int,
+                 max_batch: int | None = None, poll_s: float = 2e-5):
+        self.backend = backend
+        self.rec_bytes = rec_bytes
+        self.budget = budget_bytes
+        self.free = budget_bytes
+        self.max_slots = max_slots
+        self.slots = max_slots
+        self.max_batch = max_batch or backend.max_batch
+        self.poll_s = poll_s
+        self.pending: collections.deque = collections.deque()
+        self.admitted: list = []
+        self.inflight: dict = {}          # stream -> (token, reqs)
+        self.lock = threading.Condition()
+        self.stats = Stats()
+        self._rid = 0
+        self._stop = False
+        self._thread = None
+
+    # ------------------------------------------------------------ client side
+    def need(self, n: int) -> int:
+        return n * self.rec_bytes
+
+    def submit(self, recs, t_arrival: float | None = None) -> Future:
+        n = int(recs.shape[0])
+        with self.lock:
+            req = Request(recs=recs, n=n, t_arrival=time.perf_counter() if t_arrival is None
+                          else t_arrival, rid=self._rid)
+            self._rid += 1
+            self.stats.submitted += 1
+            if self.need(n) > self.budget:
+                self.stats.rejected += 1
+                req.future.set_exception(Rejected(f"request of {n} records exceeds the budget"))
+                return req.future
+            if self.stats.t_first == 0.0:
+                self.stats.t_first = req.t_arrival
+            self.pending.append(req)
+            self.lock.notify_all()
+        return req.future
+
+    def cancel(self, fut: Future) -> bool:
+        """Cancel a request that has not been launched yet."""
+        with self.lock:
+            for q, reserved in ((self.pending, False), (self.admitted, True)):
+                for r in list(q):
+                    if r.future is fut:
+                        q.remove(r)
+                        if reserved:  # admitted requests hold budget and a slot
+                            self.free += self.need(r.n)
+                            self.slots += 1
+                        r.tmp = None
+                        self.stats.cancelled += 1
+                        fut.set_exception(Cancelled("cancelled before launch"))
+                        self.lock.notify_all()
+                        return True
+        return False
+
+    # ------------------------------------------------------------ scheduler
+    def start(self) -> "Server":
+        self._thread = threading.Thread(target=self._run, name="raduls-server", daemon=True)
+        self._thread.start()
+        return self
+
+    def stop(self, drain: bool = True) -> dict:
+        with self.lock:
+            if not drain:
+                for r in list(self.pending):
+                    r.future.set_exception(Cancelled("server stopped"))
+                    self.stats.cancelled += 1
+                self.pending.clear()
+            self._stop = True
+            self.lock.notify_all()
+        if self._thread is not None:
+            self._thread.join()
+        return self.stats.summary()
+
+    def _idle_stream(self):
+        for s in range(self.backend.n_streams):
+            if s not in self.inflight:
+                return s
+        return None
+
+    def step(self) -> bool:
+        """One scheduling pass; returns True if it did any work."""
+        worked = False
+        # completions
+        for s, (tok, reqs) in list(self.inflight.items()):
+            if self.backend.done(tok):
+                try:
+                    errs = self.backend.finish(s, tok, reqs)
+                except Exception as e:  # backend failure: fail the batch, keep serving
+                    errs = [f"backend failure: {e}"] * len(reqs)
+                now = time.perf_counter()
+                with self.lock:
+                    del self.inflight[s]
+                    for r, err in zip(reqs, errs):
+                        self.free += self.need(r.n)
+                        self.slots += 1
+                        r.t_done = now
+                        if err:
+                            self.stats.failed += 1
+                            r.future.set_exception(BackendError(err))
+                        else:
+                            self.stats.completed += 1
+                            self.stats.records += r.n
+                            self.stats.latencies.append(now - r.t_arrival)
+                            self.stats.t_last = now
+                            r.future.set_result(r.recs)
+                    self.lock.notify_all()
+                worked = True
+        # admission, in arrival order (no overtaking)
+        with self.lock:
+            s_idx = self._idle_stream()
+            while self.pending and self.slots > 0 and len(self.admitted) < self.max_batch:
+                r = self.pending[0]
+                if self.need(r.n) > self.free:
+                    break
+                self.pending.popleft()
+                self.free -= self.need(r.n)
+                self.slots -= 1
+                r.t_admit = time.perf_counter()
+                self.admitted.append(r)
+                worked = True
+            if s_idx is None or not self.admitted:
+                return worked
+            batch, self.admitted = self.admitted, []
+        # launch on the idle stream
+        try:
+            for r in batch:
+                r.tmp = self.backend.alloc_tmp(r.n, s_idx)
+            tok = self.backend.launch(s_idx, batch)
+        except Exception as e:
+            with self.lock:
+                for r in batch:
+                    self.free += self.need(r.n)
+                    self.slots += 1
+                    r.tmp = None
+                    self.stats.failed += 1
+                    r.future.set_exception(BackendError(f"launch failed: {e}"))
+            return True
+        now = time.perf_counter()
+        for r in batch:
+            r.t_launch = now
+        with self.lock:
+            self.inflight[s_idx] = (tok, batch)
+            self.stats.batches += 1
+        return True
+
+    def _run(self):
+        while True:
+            worked = self.step()
+            with self.lock:
+                if self._stop and not self.pending and not self.admitted and not self.inflight:
+                    return
+                if not worked:
+                    if not self.inflight and not self.pending and not self._stop:
+                        self.lock.wait(timeout=0.01)
+            if not worked:
+                time.sleep(self.poll_s)

@@ -218,3 +218,49 @@ def random_records(rng: np.random.Generator, n: int, rec_bytes: int, key_bytes: 
         pool = rng.integers(0, 256, size=(distinct_keys, key_bytes), dtype=np.uint8)
         rec[:, :key_bytes] = pool[rng.integers(0, distinct_keys, size=n)]
     return rec
+
+
+# --------------------------------------------------------------------------
+# The same streams drawn directly in device memory (torch int64 arithmetic
+# wraps modulo 2^64 like uint64; right shifts are made logical by masking).
+# Bit-identical to `splitmix64` above; used to build multi-GiB inputs on the
+# GPU without a host round trip.
+
+def _s64(x: int) -> int:
+    x &= MASK64
+    return x - (1 << 64) if x >> 63 else x
+
+
+def splitmix64_torch(state: int, start: int, count: int, device="cuda"):
+    import torch
+    i = torch.arange(start + 1, start + count + 1, dtype=torch.int64, device=device)
+    z = i * _s64(GAMMA) + _s64(state)
+
+    def lsr(x, k):
+        return (x >> k) & ((1 << (64 - k)) - 1)
+
+    z = (z ^ lsr(z, 30)) * _s64(0xBF58476D1CE4E5B9)
+    z = (z ^ lsr(z, 27)) * _s64(0x94D049BB133111EB)
+    return z ^ lsr(z, 31)
+
+
+def uniform16_torch(n: int, seed: int = 2, device="cuda", chunk: int = 1 << 26):
+    """uniform16 built on the device: returns an [n, 16] uint8 tensor."""
+    import torch
+    out = torch.empty((n, 2), dtype=torch.int64, device=device)
+    st = stream_seed(seed, 0)
+    for a in range(0, n, chunk):
+        c = min(chunk, n - a)
+        out[a:a + c, 0] = splitmix64_torch(st, a, c, device)
+        out[a:a + c, 1] = torch.arange(a, a + c, dtype=torch.int64, device=device)
+    return out.view(torch.uint8).view(n, 16)
+
+
+def batch_array_torch(j: int, size: int, offset: int, seed: int = 5, device="cuda", out=None):
+    """Array j of the batch workload built on the device ([size, 16] uint8)."""
+    import torch
+    w = torch.empty((size, 2), dtype=torch.int64, device=device) if out is None else out.view(torch.int64).view(size, 2)
+    if size:
+        w[:, 0] = splitmix64_torch(stream_seed(seed, 1), offset, size, device)
+        w[:, 1] = torch.arange(size, dtype=torch.int64, device=device)
+    return w.view(torch.uint8).view(size, 16)

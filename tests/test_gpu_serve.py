@@ -1,0 +1,67 @@
+"""GPU: the serving loop returns for every request exactly what the plain
+per-call sort returns for it alone, while requests arrive during running
+batches and batches overlap on several streams."""
+
+import random
+import threading
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1703_00687_amd import binding as b
+from paper_1703_00687_amd import serve
+from paper_1703_00687_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(count, seed, max_log2=16):
+    sizes = wl.batch_sizes(count, seed=seed, max_log2=max_log2)
+    out, off = [], 0
+    for j, s in enumerate(sizes):
+        out.append(wl.batch_array(j, int(s), off, seed=seed))
+        off += int(s)
+    return out
+
+
+def _alone(host):
+    n = host.shape[0]
+    t = torch.from_numpy(host.copy()).cuda()
+    tmp = torch.empty(b.raduls_tmp_bytes(n, 16, 8), dtype=torch.uint8, device="cuda")
+    b.raduls_sort(t, tmp, n, 16, 8)
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_results_identical_alone_and_in_the_mix(use_graphs):
+    hosts = _requests(300, seed=21 + int(use_graphs))
+    alone = [_alone(h) for h in hosts]
+    for h, a in zip(hosts[:40], alone[:40]):
+        assert np.array_equal(a, oracle.sort(h, 8))
+    budget = 64 << 20
+    be = serve.GpuBackend(16, 8, n_streams=3, max_batch=32, max_records=budget // 16,
+                          use_graphs=use_graphs)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=budget, max_slots=48).start()
+    devs = [torch.from_numpy(h.copy()).cuda() for h in hosts]
+    torch.cuda.synchronize()
+    futs = [None] * len(devs)
+    rng = random.Random(5)
+
+    def producer():
+        for i, d in enumerate(devs):
+            futs[i] = srv.submit(d)
+            time.sleep(rng.expovariate(1.0 / 50e-6))  # Poisson arrivals, 50 us mean gap
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    outs = [f.result(timeout=60) for f in futs]
+    summary = srv.stop()
+    for o, a in zip(outs, alone):
+        assert np.array_equal(o.cpu().numpy(), a)
+    assert summary["requests"] == len(hosts) and summary["failed"] == 0
+    assert summary["batches"] >= 2

@@ -331,3 +331,14 @@ def test_batch_sizes_log_uniform():
     # log(size+1) ~ uniform on [0, ln(2^20+1)]: mean close to half the range
     lg = np.log(s.astype(np.float64))
     assert abs(lg.mean() - 0.5 * math.log(2 ** 20 + 1)) < 0.1
+
+
+def test_device_generator_matches_host_generator():
+    import torch
+    st = wl.stream_seed(2, 0)
+    a = wl.splitmix64(st, 12345, 5000)
+    b = wl.splitmix64_torch(st, 12345, 5000, device="cpu").numpy().view(np.uint64)
+    assert np.array_equal(a, b)
+    assert np.array_equal(wl.uniform16_torch(3000, device="cpu", chunk=1000).numpy(), wl.uniform16(3000))
+    assert np.array_equal(wl.batch_array_torch(7, 999, 31337, device="cpu").numpy(),
+                          wl.batch_array(7, 999, 31337))

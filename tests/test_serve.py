@@ -1,0 +1,186 @@
+"""The serving loop's scheduling logic on the CPU, with a stand-in backend
+that sorts with the oracle after a simulated device delay."""
+
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1703_00687_amd import serve
+from paper_1703_00687_amd import workloads as wl
+
+
+class FakeBackend:
+    def __init__(self, n_streams=2, max_batch=8, key_bytes=8, delay_s=0.002, fail_launch=None,
+                 fail_finish=None):
+        self.n_streams, self.max_batch, self.key_bytes = n_streams, max_batch, key_bytes
+        self.delay_s = delay_s
+        self.fail_launch = fail_launch or (lambda reqs: False)
+        self.fail_finish = fail_finish or (lambda reqs: False)
+        self.lock = threading.Lock()
+        self.inflight_bytes = 0
+        self.max_inflight_bytes = 0
+        self.max_concurrent_batches = 0
+        self.active = 0
+        self.batch_sizes = []
+
+    def alloc_tmp(self, n, stream_idx):
+        return np.empty((max(n, 1), 16), dtype=np.uint8)
+
+    def launch(self, stream_idx, reqs):
+        if self.fail_launch(reqs):
+            raise RuntimeError("injected launch failure")
+        with self.lock:
+            self.active += 1
+            self.max_concurrent_batches = max(self.max_concurrent_batches, self.active)
+            b = sum(r.n * r.recs.shape[1] for r in reqs)
+            self.inflight_bytes += b
+            self.max_inflight_bytes = max(self.max_inflight_bytes, self.inflight_bytes)
+            self.batch_sizes.append(len(reqs))
+        return (time.perf_counter() + self.delay_s, b)
+
+    def done(self, token):
+        return time.perf_counter() >= token[0]
+
+    def finish(self, stream_idx, token, reqs):
+        with self.lock:
+            self.active -= 1
+            self.inflight_bytes -= token[1]
+        if self.fail_finish(reqs):
+            return ["injected device error"] * len(reqs)
+        for r in reqs:
+            r.recs[:] = oracle.sort(r.recs, self.key_bytes)
+            r.tmp = None
+        return [None] * len(reqs)
+
+
+def _arrays(count, seed=0, max_log2=12):
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(0, 1 << max_log2, size=count)
+    return [wl.random_records(rng, int(s), 16, 8, distinct_keys=max(1, int(s) // 4)) for s in sizes]
+
+
+def test_all_requests_sorted_and_counted():
+    be = FakeBackend()
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 20, max_slots=16).start()
+    arrays = _arrays(200)
+    expect = [oracle.sort(a, 8) for a in arrays]
+    futs = [srv.submit(a) for a in arrays]
+    outs = [f.result(timeout=30) for f in futs]
+    summary = srv.stop()
+    for o, e in zip(outs, expect):
+        assert np.array_equal(o, e)
+    assert summary["requests"] == 200 and summary["failed"] == 0
+    assert summary["p99_ms"] >= summary["p50_ms"] >= 0
+    assert summary["records"] == sum(a.shape[0] for a in arrays)
+
+
+def test_budget_and_slots_bound_what_is_in_flight():
+    be = FakeBackend(n_streams=3, max_batch=4, delay_s=0.003)
+    budget = 200_000
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=budget, max_slots=5).start()
+    futs = [srv.submit(a) for a in _arrays(120, seed=1)]
+    for f in futs:
+        f.result(timeout=30)
+    srv.stop()
+    assert be.max_inflight_bytes <= budget
+    assert max(be.batch_sizes) <= 4
+
+
+def test_batches_overlap_across_streams():
+    be = FakeBackend(n_streams=2, max_batch=2, delay_s=0.02)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 24, max_slots=8).start()
+    futs = [srv.submit(a) for a in _arrays(12, seed=2)]
+    for f in futs:
+        f.result(timeout=30)
+    srv.stop()
+    assert be.max_concurrent_batches == 2
+
+
+def test_arrival_order_admission_and_continuous_batching():
+    # a request larger than what is free waits at the head; nothing overtakes it
+    be = FakeBackend(n_streams=1, max_batch=8, delay_s=0.02)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=16 * 1000, max_slots=8).start()
+    small = wl.random_records(np.random.default_rng(3), 600, 16, 8)
+    big = wl.random_records(np.random.default_rng(4), 900, 16, 8)
+    tail = wl.random_records(np.random.default_rng(5), 10, 16, 8)
+    f1 = srv.submit(small)
+    time.sleep(0.005)          # small is running now
+    f2 = srv.submit(big)       # needs 900 > 400 free: waits
+    f3 = srv.submit(tail)      # would fit, but must not overtake big
+    f1.result(timeout=10)
+    f2.result(timeout=10)
+    f3.result(timeout=10)
+    srv.stop()
+    assert f2.result().shape[0] == 900
+    # big and tail were admitted after small completed, as one batch
+    assert be.batch_sizes[0] == 1 and be.batch_sizes[1] == 2
+
+
+def test_oversize_request_rejected():
+    be = FakeBackend()
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=16 * 100, max_slots=4).start()
+    f = srv.submit(wl.random_records(np.random.default_rng(6), 101, 16, 8))
+    with pytest.raises(serve.Rejected):
+        f.result(timeout=5)
+    ok = srv.submit(wl.random_records(np.random.default_rng(7), 100, 16, 8))
+    assert ok.result(timeout=5).shape[0] == 100
+    assert srv.stop()["rejected"] == 1
+
+
+def test_cancel_before_launch():
+    be = FakeBackend(n_streams=1, max_batch=1, delay_s=0.05)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 20, max_slots=1).start()
+    a = _arrays(3, seed=8)
+    f1 = srv.submit(a[0])
+    f2 = srv.submit(a[1])
+    time.sleep(0.01)
+    assert srv.cancel(f2)
+    with pytest.raises(serve.Cancelled):
+        f2.result(timeout=5)
+    f3 = srv.submit(a[2])
+    f1.result(timeout=5)
+    f3.result(timeout=5)
+    s = srv.stop()
+    assert s["cancelled"] == 1 and s["requests"] == 2
+
+
+def test_backend_failures_fail_only_their_batch():
+    state = {"n": 0}
+
+    def fail_every_third(reqs):
+        state["n"] += 1
+        return state["n"] % 3 == 0
+
+    be = FakeBackend(n_streams=1, max_batch=1, fail_finish=fail_every_third)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 20, max_slots=4).start()
+    futs = [srv.submit(a) for a in _arrays(9, seed=9)]
+    errors = 0
+    for f in futs:
+        try:
+            f.result(timeout=10)
+        except serve.BackendError:
+            errors += 1
+    s = srv.stop()
+    assert errors == 3 and s["failed"] == 3 and s["requests"] == 6
+
+    be2 = FakeBackend(fail_launch=lambda reqs: True)
+    srv2 = serve.Server(be2, rec_bytes=16, budget_bytes=1 << 20, max_slots=4).start()
+    f = srv2.submit(_arrays(1, seed=10)[0])
+    with pytest.raises(serve.BackendError):
+        f.result(timeout=5)
+    srv2.stop()
+    assert srv2.free == srv2.budget and srv2.slots == srv2.max_slots
+
+
+def test_stop_without_drain_cancels_pending():
+    be = FakeBackend(n_streams=1, max_batch=1, delay_s=0.05)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 20, max_slots=1).start()
+    futs = [srv.submit(a) for a in _arrays(5, seed=11)]
+    time.sleep(0.01)
+    s = srv.stop(drain=False)
+    assert s["cancelled"] >= 3
+    done = sum(1 for f in futs if f.done() and f.exception() is None)
+    assert done >= 1
