@@ -130,6 +130,155 @@ def cpu_baseline(log2n: int) -> dict:
                       f"(std::stable_sort, one thread, {dt:.1f} s)"}
 
 
+def fill_batch(recs, starts, sizes, seed=5):
+    """Write the batch workload into one device buffer holding every array
+    back to back (keys continue one stream across arrays; payload = index
+    inside the array)."""
+    import torch
+    from paper_1703_00687_amd import workloads as wl
+    total = int(sizes.sum())
+    w = recs.view(torch.int64).view(total, 2)
+    st = wl.stream_seed(seed, 1)
+    dstarts = torch.from_numpy(starts).to(recs.device)
+    chunk = 1 << 26
+    for a in range(0, total, chunk):
+        c = min(chunk, total - a)
+        w[a:a + c, 0] = wl.splitmix64_torch(st, a, c, recs.device)
+        idx = torch.arange(a, a + c, dtype=torch.int64, device=recs.device)
+        arr = torch.searchsorted(dstarts, idx, right=True) - 1
+        w[a:a + c, 1] = idx - dstarts[arr]
+
+
+def bench_batch(args) -> dict:
+    """Many uneven arrays: one batched call vs one plain call per array, and
+    the same arrays served as a Poisson request stream."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1703_00687_amd import binding as b
+    from paper_1703_00687_amd import serve
+    from paper_1703_00687_amd import workloads as wl
+
+    count, R, K = args.batch_count, 16, 8
+    sizes = wl.batch_sizes(count, max_log2=args.batch_log2max).astype(np.int64)
+    starts = np.zeros(count, dtype=np.int64)
+    starts[1:] = np.cumsum(sizes)[:-1]
+    total = int(sizes.sum())
+    dev = torch.device("cuda:0")
+    log(f"[batch] {count} arrays, sizes log-uniform in [1, 2^{args.batch_log2max}], "
+        f"{total} records ({total * R / 2**30:.1f} GiB)")
+    recs = torch.empty((total, R), dtype=torch.uint8, device=dev)
+    tmp = torch.empty((total + 64, R), dtype=torch.uint8, device=dev)
+    bt = b.Batch(count, total, R, K, device=dev)
+    h = bt.host_desc.numpy()
+    h[:, 0] = recs.data_ptr() + starts * R
+    h[:, 1] = tmp.data_ptr() + starts * R
+    h[:, 2] = sizes
+    bt.desc.copy_(bt.host_desc)
+
+    def ev_time(fn):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) * 1e-3
+
+    # batched: one call for every array
+    times = []
+    for rep in range(1 + args.batch_reps):
+        fill_batch(recs, starts, sizes)
+        t = ev_time(bt.launch)
+        st, stats = bt.check()
+        if st != b.OK:
+            raise RuntimeError(f"batched sort: device error {stats}")
+        if rep:
+            times.append(t)
+    t_batched = sorted(times)[len(times) // 2]
+    rng = np.random.default_rng(0)
+    for j in rng.choice(count, size=min(48, count), replace=False):
+        a, n = int(starts[j]), int(sizes[j])
+        got = recs[a:a + n].cpu().numpy()
+        if not np.array_equal(got, oracle.sort(wl.batch_array(int(j), n, a), K)):
+            raise RuntimeError(f"batched sort: array {j} differs from the oracle")
+    log(f"[batch] batched: {t_batched * 1e3:.1f} ms, {total / t_batched / 1e9:.2f} G records/s")
+
+    # plain: one raduls_sort call per array, same stream, same scratch
+    fill_batch(recs, starts, sizes)
+    nmax = int(sizes.max())
+    need = b.raduls_tmp_bytes(nmax, R, K)
+    scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+    lib = b.load()
+    stream = torch.cuda.current_stream().cuda_stream
+    base = recs.data_ptr()
+    sptr = scratch.data_ptr()
+
+    def plain():
+        for j in range(count):
+            st = lib.raduls_sort(base + int(starts[j]) * R, sptr, int(sizes[j]), R, K, stream)
+            if st:
+                raise RuntimeError(f"plain sort of array {j}: {b.strerror(st)}")
+
+    t_plain = ev_time(plain)
+    del scratch
+    log(f"[batch] plain per-array calls: {t_plain * 1e3:.1f} ms, {total / t_plain / 1e9:.3f} G records/s")
+
+    # served: Poisson arrivals at a fraction of the plain throughput, and a closed run
+    out = {
+        "workload": f"{count} arrays of 16 B records, sizes log-uniform in [1, 2^{args.batch_log2max}], "
+                    "uint64 key uniform, uint64 payload = index",
+        "arrays": count, "records": total,
+        "batched_ms": round(t_batched * 1e3, 3), "batched_records_per_s": total / t_batched,
+        "plain_ms": round(t_plain * 1e3, 3), "plain_records_per_s": total / t_plain,
+        "batched_vs_plain": t_plain / t_batched,
+    }
+    if args.serve_requests > 0:
+        nreq = min(args.serve_requests, count)
+        budget = min(args.serve_budget_gib << 30, total * R)
+        be = serve.GpuBackend(R, K, n_streams=3, max_batch=2048, max_records=budget // R)
+        views = [recs[int(starts[j]):int(starts[j]) + int(sizes[j])] for j in range(nreq)]
+        served_records = int(sizes[:nreq].sum())
+        for mode, rho in (("closed", None), ("poisson", args.serve_load)):
+            fill_batch(recs, starts, sizes)
+            torch.cuda.synchronize()
+            srv = serve.Server(be, R, budget, max_slots=4096).start()
+            futs = []
+            t0 = time.perf_counter()
+            if rho is None:
+                for v in views:
+                    futs.append(srv.submit(v))
+            else:
+                rate = rho * (total / t_plain) / (served_records / nreq)  # requests per second
+                gaps = np.random.default_rng(7).exponential(1.0 / rate, size=nreq)
+                t_next = t0
+                for v, g in zip(views, gaps):
+                    t_next += g
+                    wait = t_next - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)  # releases the GIL to the scheduler thread
+                    futs.append(srv.submit(v, t_arrival=t_next))
+            for f in futs:
+                f.result(timeout=600)
+            summ = srv.stop()
+            summ["wall_s"] = time.perf_counter() - t0
+            if rho is not None:
+                summ["arrival_rate_req_s"] = rate
+                summ["load_vs_plain"] = rho
+            log(f"[serve] {mode}: {summ}")
+            out["served_" + mode] = {k: (round(v, 4) if isinstance(v, float) else v)
+                                     for k, v in summ.items()}
+        rng = np.random.default_rng(1)
+        for j in rng.choice(nreq, size=min(32, nreq), replace=False):
+            a, n = int(starts[j]), int(sizes[j])
+            if not np.array_equal(recs[a:a + n].cpu().numpy(),
+                                  oracle.sort(wl.batch_array(int(j), n, a), K)):
+                raise RuntimeError(f"served array {j} differs from the oracle")
+    del recs, tmp, bt
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +288,14 @@ def main() -> int:
     ap.add_argument("--cpu-sample-log2", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=65536)
+    ap.add_argument("--batch-log2max", type=int, default=20)
+    ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--serve-requests", type=int, default=65536)
+    ap.add_argument("--serve-load", type=float, default=0.9,
+                    help="Poisson arrival rate as a fraction of the plain per-call throughput")
+    ap.add_argument("--serve-budget-gib", type=int, default=32)
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -226,6 +383,12 @@ def main() -> int:
         "lds_sort": pass_bytes / (phases["lds_sort"] * 1e-3) / 1e9,
     }
 
+    del copies, tmp
+    torch.cuda.empty_cache()
+    batched = None
+    if not args.no_batch:
+        batched = bench_batch(args)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle on 2^{args.cpu_sample_log2} records")
@@ -255,6 +418,7 @@ def main() -> int:
         "whole_sort_gbs_per_pass": round(pass_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         "stats": stats,
         "verified": verified,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
     return 0

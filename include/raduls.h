@@ -164,8 +164,9 @@ int raduls_get_tuning(raduls_tuning *tuning);
  * enqueued or captured. */
 int raduls_set_profile_events(hipEvent_t *events, uint32_t count);
 
-/* Largest mid_max (records) the LDS sorter supports for records of R bytes. */
-uint32_t raduls_mid_capacity(uint32_t rec_bytes);
+/* Largest mid_max (records) the LDS sorter supports for records of R bytes
+ * with K key bytes (0 for an unsupported shape). */
+uint32_t raduls_mid_capacity(uint32_t rec_bytes, uint32_t key_bytes);
 
 const char *raduls_strerror(int status);
 

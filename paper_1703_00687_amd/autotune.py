@@ -90,7 +90,7 @@ def tune(src, key_bytes: int, reps: int = 3, space: dict | None = None, budget_s
     import torch
     space = dict(SPACE if space is None else space)
     n, R = int(src.shape[0]), int(src.shape[1])
-    cap = b.raduls_mid_capacity(R)
+    cap = b.raduls_mid_capacity(R, key_bytes)
     copies = [torch.empty_like(src) for _ in range(2)]
     prev = b.raduls_get_tuning()
     t_start = time.perf_counter()

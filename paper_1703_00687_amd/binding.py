@@ -91,7 +91,7 @@ def load() -> ctypes.CDLL:
         "raduls_check": (i32, [vp, u64, u32, i32, ctypes.POINTER(raduls_stats), vp]),
         "raduls_set_tuning": (i32, [ctypes.POINTER(raduls_tuning)]),
         "raduls_get_tuning": (i32, [ctypes.POINTER(raduls_tuning)]),
-        "raduls_mid_capacity": (u32, [u32]),
+        "raduls_mid_capacity": (u32, [u32, u32]),
         "raduls_set_profile_events": (i32, [ctypes.POINTER(ctypes.c_void_p), u32]),
         "raduls_strerror": (ctypes.c_char_p, [i32]),
     }
@@ -234,8 +234,8 @@ def raduls_set_profile_events(events: Sequence[int]) -> None:
     _check(load().raduls_set_profile_events(arr, len(events)), "raduls_set_profile_events")
 
 
-def raduls_mid_capacity(rec_bytes: int) -> int:
-    return int(load().raduls_mid_capacity(rec_bytes))
+def raduls_mid_capacity(rec_bytes: int, key_bytes: int) -> int:
+    return int(load().raduls_mid_capacity(rec_bytes, key_bytes))
 
 
 def raduls_strerror(status: int) -> str:

@@ -29,11 +29,33 @@ __host__ __device__ constexpr uint32_t scatter_lds_bytes(int rw) {
          uint32_t(kScatterWaves * 256 * 2) + 3u * 256u * 4u + 256u * 8u;
 }
 
-// LDS sorter workgroups: 16 waves, one workgroup per CU.
-constexpr int kMidBlock = 1024;
+// LDS sorter workgroups: 8 waves, two workgroups per CU.  Only keys and a
+// 16-bit permutation live in LDS; payloads are gathered from HBM at the end.
+constexpr int kMidBlock = 512;
 constexpr int kMidWaves = kMidBlock / kWave;
-__host__ __device__ constexpr int mid_items(int rw) {
-  return rw == 1 ? 12 : rw == 2 ? 8 : rw == 3 ? 6 : rw <= 5 ? 4 : 3;
+constexpr uint32_t kMidStaticLds = 6 * 1024;  // static LDS of the LDS sorter (upper bound)
+constexpr uint32_t kMidLdsPerGroup = 80 * 1024;  // two workgroups per CU
+// Dynamic LDS for jobs of up to T records with KW key words.
+__host__ __device__ constexpr uint32_t mid_dynamic_lds(uint32_t T, int kw) {
+  return T * uint32_t(kw) * 8u + ((T + 1u) / 2u) * 4u + uint32_t(kMidWaves) * 256u * 2u +
+         4u * ((T >> 5) + 2u);
+}
+// Records per lane a whole-job pass can hold without spilling at the
+// 128-VGPR budget of two 512-thread workgroups per CU; the write-out holds
+// every record of the job in registers.
+__host__ __device__ constexpr uint32_t mid_lane_items(int rw) {
+  return rw <= 2 ? 10u : (24u / uint32_t(rw) < 10u ? 24u / uint32_t(rw) : 10u);
+}
+// Largest job (records, a multiple of 64): its keys fit the LDS share and
+// its records fit the lanes' registers.
+__host__ __device__ constexpr uint32_t mid_cap(int rw, int kw) {
+  uint32_t t = uint32_t(kMidBlock) * mid_lane_items(rw);
+  while (t > 64u && mid_dynamic_lds(t, kw) + kMidStaticLds > kMidLdsPerGroup) t -= 64u;
+  return t;
+}
+// Records per thread of a workgroup-wide LDS pass over a whole job.
+__host__ __device__ constexpr int mid_items(int rw, int kw) {
+  return int((mid_cap(rw, kw) + kMidBlock - 1) / kMidBlock);
 }
 // Records per lane of a single-wave LDS pass (a wave handles ranges of up to
 // 64 * mid_wave_items records).
@@ -41,7 +63,9 @@ __host__ __device__ constexpr int mid_wave_items(int rw) { return rw <= 2 ? 8 : 
 constexpr uint32_t kLdsBytes = 160 * 1024;
 constexpr uint32_t kMidListCap = 384;   // ranges waiting for a wave pass (per round)
 constexpr uint32_t kMidBigCap = 64;     // ranges waiting for a workgroup pass
-constexpr uint32_t kMidFixedLds = 8 * 1024;  // static LDS of the LDS sorter (upper bound)
+// Positions per lane of the enumeration phase: a range of at most 256 records
+// starting in a 64-position window ends within 5 windows.
+constexpr int kMidEsItems = 5;
 
 // Most workgroups of the histogram / carry-scan scatter grid.
 constexpr uint32_t kMaxRanges = 4096;

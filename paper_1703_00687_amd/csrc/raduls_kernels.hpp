@@ -1006,23 +1006,31 @@ __device__ __forceinline__ int bm_next(const uint32_t* bm, int p, int hi) {
   }
 }
 
-// LDS state of one LDS-sort workgroup.
+// LDS state of one LDS-sort workgroup.  The job's keys stay in LDS in input
+// order; every pass permutes `perm`, the slots in sorted order.
 struct MidLds {
-  uint64_t* rec;    // [T * RW] records of the job
-  uint16_t* perm;   // [T] final order (aliases the ranking counters)
+  uint64_t* key;    // [T * KW] keys of the job (masked), input order
+  uint16_t* perm;   // [T] position -> record slot
   uint16_t* cnt;    // [kMidWaves * kRadix] per-wave ranking counters
   uint32_t* bm;     // boundary bitmap: bit p set where a sub-range starts
   uint32_t* big;    // ranges waiting for a workgroup pass (start | size << 16)
-  uint32_t* list0;    // ranges waiting for a wave pass, double-buffered by round
+  uint32_t* list0;  // ranges waiting for a wave pass, double-buffered by round
   uint32_t* list1;
   uint32_t* nbig;
-  uint32_t* nlist;    // [2]
-  uint32_t* claim;    // next entry of the current list to claim
-  uint32_t* tot;      // [kRadix]
-  uint32_t* off;      // [kRadix]
-  uint32_t* scan;     // [8]
+  uint32_t* nlist;  // [2]
+  uint32_t* claim;  // next entry of the current list to claim
+  uint32_t* tot;    // [kRadix]
+  uint32_t* off;    // [kRadix]
+  uint32_t* scan;   // [8]
   unsigned long long* diff;  // [kMidWaves * KW]
 };
+
+template <int RW, int KW>
+__device__ __forceinline__ void slot_key(const Params& P, const MidLds& L, uint32_t slot,
+                                         uint64_t (&k)[KW]) {
+#pragma unroll
+  for (int q = 0; q < KW; ++q) k[q] = L.key[uint64_t(slot) * KW + q];
+}
 
 // Route a sub-range by size: > wave capacity -> workgroup pass, > tiny ->
 // wave pass, else enumeration sort later.  Its start is always marked.
@@ -1042,125 +1050,111 @@ __device__ __forceinline__ void mid_route(const Params& P, MidLds& L, uint32_t s
   }
 }
 
-// Stable radix pass of the whole workgroup over records [s, s + m): reads them
-// (from global memory for the first pass of a job, else from LDS), finds the
-// highest digit in which their keys differ, writes them to LDS [s, s + m) in
-// digit order and routes the non-empty sub-ranges.  All threads call it.
-template <int RW, int KW, bool FROM_GLOBAL>
-__device__ __forceinline__ void mid_wg_pass(const Params& P, MidLds& L, const uint64_t* gsrc, uint32_t s,
-                            uint32_t m, uint32_t wave_cap) {
-  constexpr int ITEMS = mid_items(RW);
+// Stable workgroup pass over positions [s, s + m): ranks the records at those
+// positions by the digit [lob, lob + w) and rewrites perm[s .. s+m) in digit
+// order.  When `identity`, perm is not read (position i holds slot i).
+// Returns through L.tot / L.off the digit counts and offsets.  All threads call.
+template <int RW, int KW, int ITEMS>
+__device__ __forceinline__ void mid_wg_digit(const Params& P, MidLds& L, uint32_t s, uint32_t m,
+                                             uint32_t lob, uint32_t w, bool identity) {
   constexpr int W = kMidWaves;
-  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t ipw = (m + kWave * W - 1) / (kWave * W);
-  uint64_t rec[ITEMS][RW];
+  uint32_t src[ITEMS], dg[ITEMS], rank[ITEMS];
   bool valid[ITEMS];
-  uint64_t key0[KW], dacc[KW];
-  if constexpr (FROM_GLOBAL) key_of<KW>(gmem(gsrc), P.kmask, key0);
-  else key_of<KW>(L.rec + uint64_t(s) * RW, P.kmask, key0);
-#pragma unroll
-  for (int q = 0; q < KW; ++q) dacc[q] = 0;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const uint32_t i = wave * ipw * kWave + j * kWave + lane;
     valid[j] = (uint32_t(j) < ipw) && (i < m);
-    if (valid[j]) {
-      if constexpr (FROM_GLOBAL) load_rec<RW>(reinterpret_cast<const uint8_t*>(gsrc), i, rec[j]);
-      else {
-#pragma unroll
-        for (int q = 0; q < RW; ++q) rec[j][q] = L.rec[uint64_t(s + i) * RW + q];
-      }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    if (valid[j]) {
-      uint64_t key[KW];
-      key_of<KW>(rec[j], P.kmask, key);
-#pragma unroll
-      for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < KW; ++q) {
-    const uint64_t v = wave_or(dacc[q]);
-    if (lane == 0) L.diff[wave * KW + q] = v;
-  }
-  __syncthreads();
-  uint64_t dall[KW];
-#pragma unroll
-  for (int q = 0; q < KW; ++q) {
-    dall[q] = 0;
-    for (int w2 = 0; w2 < W; ++w2) dall[q] |= L.diff[w2 * KW + q];
-  }
-  const int tb = top_bit<KW>(dall);
-  if (tb < 0) {  // every key equal: the range is in order; only place it
-    if constexpr (FROM_GLOBAL) {
-#pragma unroll
-      for (int j = 0; j < ITEMS; ++j) {
-        if (valid[j]) {
-          const uint32_t i = wave * ipw * kWave + j * kWave + lane;
-#pragma unroll
-          for (int q = 0; q < RW; ++q) L.rec[uint64_t(s + i) * RW + q] = rec[j][q];
-        }
-      }
-    }
-    if (tid == 0) atomicOr(&L.bm[s >> 5], 1u << (s & 31));
-    __syncthreads();
-    return;
-  }
-  const uint32_t hb = uint32_t(tb) + 1;
-  const uint32_t w = min(P.digit_bits, hb);
-  const uint32_t lob = hb - w;
-  const uint32_t nb = 1u << w;
-  uint32_t dg[ITEMS], rank[ITEMS];
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
+    src[j] = 0;
     dg[j] = 0;
     if (valid[j]) {
+      src[j] = identity ? s + i : L.perm[s + i];
       uint64_t key[KW];
-      key_of<KW>(rec[j], P.kmask, key);
+      slot_key<RW, KW>(P, L, src[j], key);
       dg[j] = digit_of<KW>(key, lob, w);
     }
   }
   uint16_t* wc = L.cnt + wave * kRadix;
   for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
   wave_rank<ITEMS>(dg, valid, w, wc, rank);
-  __syncthreads();
+  lds_barrier();  // every perm entry of the range has been read
   block_digit_scan<W>(L.cnt, L.tot, L.off, L.scan);
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    if (valid[j]) {
-      const uint32_t pos = s + L.off[dg[j]] + wc[dg[j]] + rank[j];
-#pragma unroll
-      for (int q = 0; q < RW; ++q) L.rec[uint64_t(pos) * RW + q] = rec[j][q];
-    }
-  }
-  if (tid < nb && L.tot[tid]) mid_route(P, L, s + L.off[tid], L.tot[tid], lob, wave_cap, 0);
-  __syncthreads();
+  for (int j = 0; j < ITEMS; ++j)
+    if (valid[j]) L.perm[s + L.off[dg[j]] + wc[dg[j]] + rank[j]] = uint16_t(src[j]);
 }
 
-// Stable radix pass of one wave over records [s, s + m), m <= 64 * WI, in
-// place in LDS; sub-ranges go to list `nxt` (or are left for enumeration).
+// Key spread of positions [s, s + m) over the workgroup: the highest bit in
+// which their keys differ, or -1.  All threads call.
+template <int RW, int KW>
+__device__ __forceinline__ int mid_wg_top_bit(const Params& P, MidLds& L, uint32_t s, uint32_t m,
+                                              bool identity) {
+  constexpr int W = kMidWaves;
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint64_t key0[KW], dacc[KW];
+  slot_key<RW, KW>(P, L, identity ? s : L.perm[s], key0);
+#pragma unroll
+  for (int q = 0; q < KW; ++q) dacc[q] = 0;
+  for (uint32_t i = threadIdx.x; i < m; i += kMidBlock) {
+    uint64_t key[KW];
+    slot_key<RW, KW>(P, L, identity ? s + i : L.perm[s + i], key);
+#pragma unroll
+    for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
+  }
+#pragma unroll
+  for (int q = 0; q < KW; ++q) {
+    const uint64_t v = wave_or(dacc[q]);
+    if (lane == 0) L.diff[wave * KW + q] = v;
+  }
+  lds_barrier();
+  uint64_t dall[KW];
+#pragma unroll
+  for (int q = 0; q < KW; ++q) {
+    dall[q] = 0;
+    for (int w2 = 0; w2 < W; ++w2) dall[q] |= L.diff[w2 * KW + q];
+  }
+  lds_barrier();  // L.diff is reused by the next call
+  return top_bit<KW>(dall);
+}
+
+// Workgroup pass over a range larger than one wave can hold: split it on the
+// highest digit in which its keys differ and route the sub-ranges.
+template <int RW, int KW>
+__device__ __forceinline__ void mid_wg_pass(const Params& P, MidLds& L, uint32_t s, uint32_t m,
+                                            uint32_t wave_cap) {
+  const int tb = mid_wg_top_bit<RW, KW>(P, L, s, m, false);
+  if (tb < 0) return;  // all keys equal: in order
+  const uint32_t hb = uint32_t(tb) + 1;
+  const uint32_t w = min(P.digit_bits, hb);
+  const uint32_t lob = hb - w;
+  mid_wg_digit<RW, KW, mid_items(RW, KW)>(P, L, s, m, lob, w, false);
+  const uint32_t tid = threadIdx.x;
+  if (tid < (1u << w) && L.tot[tid]) mid_route(P, L, s + L.off[tid], L.tot[tid], lob, wave_cap, 0);
+  lds_barrier();
+}
+
+// Stable pass of one wave over positions [s, s + m), m <= 64 * WI, on the
+// highest digit in which their keys differ; sub-ranges go to list `nxt`.
 template <int RW, int KW, int WI>
-__device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32_t s, uint32_t m, uint32_t nxt,
-                              uint32_t wave_cap) {
+__device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32_t s, uint32_t m,
+                                              uint32_t nxt, uint32_t wave_cap) {
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-  uint64_t rec[WI][RW];
+  uint32_t src[WI];
   bool valid[WI];
   uint64_t key0[KW], dacc[KW];
-  key_of<KW>(L.rec + uint64_t(s) * RW, P.kmask, key0);
+  slot_key<RW, KW>(P, L, L.perm[s], key0);
 #pragma unroll
   for (int q = 0; q < KW; ++q) dacc[q] = 0;
 #pragma unroll
   for (int j = 0; j < WI; ++j) {
     const uint32_t i = j * kWave + lane;
     valid[j] = i < m;
+    src[j] = 0;
     if (valid[j]) {
-#pragma unroll
-      for (int q = 0; q < RW; ++q) rec[j][q] = L.rec[uint64_t(s + i) * RW + q];
+      src[j] = L.perm[s + i];
       uint64_t key[KW];
-      key_of<KW>(rec[j], P.kmask, key);
+      slot_key<RW, KW>(P, L, src[j], key);
 #pragma unroll
       for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
     }
@@ -1178,7 +1172,7 @@ __device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32
     dg[j] = 0;
     if (valid[j]) {
       uint64_t key[KW];
-      key_of<KW>(rec[j], P.kmask, key);
+      slot_key<RW, KW>(P, L, src[j], key);
       dg[j] = digit_of<KW>(key, lob, w);
     }
   }
@@ -1205,106 +1199,23 @@ __device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32
   }
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
-  for (int j = 0; j < WI; ++j) {
-    if (valid[j]) {
-      const uint32_t pos = s + wc[dg[j]] + rank[j];
-#pragma unroll
-      for (int q = 0; q < RW; ++q) L.rec[uint64_t(pos) * RW + q] = rec[j][q];
-    }
-  }
+  for (int j = 0; j < WI; ++j)
+    if (valid[j]) L.perm[s + wc[dg[j]] + rank[j]] = uint16_t(src[j]);
 }
 
-// Stable placement of a workgroup's register-held records into LDS [0, m) by
-// the digit [lob, lob + w) (w <= 8), records ordered by (digit, input order).
-template <int RW, int KW, int ITEMS>
-__device__ __forceinline__ void mid_rank_write(const Params& P, MidLds& L,
-                                               const uint64_t (&rec)[ITEMS][RW],
-                                               const bool (&valid)[ITEMS], uint32_t lob,
-                                               uint32_t w) {
-  constexpr int W = kMidWaves;
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint32_t dg[ITEMS], rank[ITEMS];
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    dg[j] = 0;
-    if (valid[j]) {
-      uint64_t key[KW];
-      key_of<KW>(rec[j], P.kmask, key);
-      dg[j] = digit_of<KW>(key, lob, w);
-    }
-  }
-  uint16_t* wc = L.cnt + wave * kRadix;
-  for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
-  wave_rank<ITEMS>(dg, valid, w, wc, rank);
-  lds_barrier();
-  block_digit_scan<W>(L.cnt, L.tot, L.off, L.scan);
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    if (valid[j]) {
-      const uint32_t pos = L.off[dg[j]] + wc[dg[j]] + rank[j];
-#pragma unroll
-      for (int q = 0; q < RW; ++q) L.rec[uint64_t(pos) * RW + q] = rec[j][q];
-    }
-  }
-}
-
-// First split of an LDS job.  The job is read from HBM into registers once;
-// the highest key bit in which its records differ gives the top of the next
-// two digits, and two stable digit passes (lower digit first, so the pair
-// acts as one 2*digit_bits-bit digit) leave the job in LDS ordered by those
-// bits.  Runs of records equal in them are marked in the boundary bitmap;
-// runs longer than tiny_max that still have key bits below are routed to
-// further passes, the rest are finished by enumeration sort.
+// First split of a job: the highest key bit in which its records differ
+// gives the top of the next two digits; two stable digit passes (lower digit
+// first, so the pair acts as one 2*digit_bits-bit digit) order the job by
+// those bits.  Runs of equal bits are marked in the boundary bitmap; runs
+// longer than tiny_max with key bits left below are routed to further passes.
 template <int RW, int KW>
-__device__ __forceinline__ void mid_first_split(const Params& P, MidLds& L, const uint64_t* gsrc,
-                                                uint32_t m, uint32_t wave_cap) {
-  constexpr int ITEMS = mid_items(RW);
-  constexpr int W = kMidWaves;
+__device__ __forceinline__ void mid_first_split(const Params& P, MidLds& L, uint32_t m,
+                                                uint32_t wave_cap) {
+  constexpr int ITEMS = mid_items(RW, KW);
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const uint32_t ipw = (m + kWave * W - 1) / (kWave * W);
-  uint64_t rec[ITEMS][RW];
-  bool valid[ITEMS];
-  uint64_t key0[KW], dacc[KW];
-  key_of<KW>(gmem(gsrc), P.kmask, key0);
-#pragma unroll
-  for (int q = 0; q < KW; ++q) dacc[q] = 0;
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    const uint32_t i = wave * ipw * kWave + j * kWave + lane;
-    valid[j] = (uint32_t(j) < ipw) && (i < m);
-    if (valid[j]) load_rec<RW>(reinterpret_cast<const uint8_t*>(gsrc), i, rec[j]);
-  }
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    if (valid[j]) {
-      uint64_t key[KW];
-      key_of<KW>(rec[j], P.kmask, key);
-#pragma unroll
-      for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < KW; ++q) {
-    const uint64_t v = wave_or(dacc[q]);
-    if (lane == 0) L.diff[wave * KW + q] = v;
-  }
-  lds_barrier();
-  uint64_t dall[KW];
-#pragma unroll
-  for (int q = 0; q < KW; ++q) {
-    dall[q] = 0;
-    for (int w2 = 0; w2 < W; ++w2) dall[q] |= L.diff[w2 * KW + q];
-  }
-  const int tb = top_bit<KW>(dall);
+  const int tb = mid_wg_top_bit<RW, KW>(P, L, 0, m, true);
   if (tb < 0) {  // the whole job holds one key: it stays in input order
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      if (valid[j]) {
-        const uint32_t i = wave * ipw * kWave + j * kWave + lane;
-#pragma unroll
-        for (int q = 0; q < RW; ++q) L.rec[uint64_t(i) * RW + q] = rec[j][q];
-      }
-    }
+    for (uint32_t i = tid; i < m; i += kMidBlock) L.perm[i] = uint16_t(i);
     if (tid == 0) L.bm[0] = 1u;
     lds_barrier();
     return;
@@ -1313,19 +1224,10 @@ __device__ __forceinline__ void mid_first_split(const Params& P, MidLds& L, cons
   const uint32_t dw = P.digit_bits;
   const uint32_t lo2 = hb > 2 * dw ? hb - 2 * dw : 0;
   const uint32_t wa = min(dw, hb - lo2);
-  mid_rank_write<RW, KW, ITEMS>(P, L, rec, valid, lo2, wa);
+  mid_wg_digit<RW, KW, ITEMS>(P, L, 0, m, lo2, wa, true);
   if (hb > lo2 + wa) {
     lds_barrier();
-    // reread in LDS order (stable), then place by the upper digit
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const uint32_t i = wave * ipw * kWave + j * kWave + lane;
-      if (valid[j]) {
-#pragma unroll
-        for (int q = 0; q < RW; ++q) rec[j][q] = L.rec[uint64_t(i) * RW + q];
-      }
-    }
-    mid_rank_write<RW, KW, ITEMS>(P, L, rec, valid, lo2 + wa, hb - lo2 - wa);
+    mid_wg_digit<RW, KW, ITEMS>(P, L, 0, m, lo2 + wa, hb - lo2 - wa, false);
   }
   lds_barrier();
   // run starts: the key bits [lo2, hb) differ from the previous record's
@@ -1334,12 +1236,11 @@ __device__ __forceinline__ void mid_first_split(const Params& P, MidLds& L, cons
     const uint32_t p = base + lane;
     bool start = false;
     if (p < m) {
-      uint64_t kp[KW];
-      key_of<KW>(L.rec + uint64_t(p) * RW, P.kmask, kp);
       start = p == 0;
       if (p > 0) {
-        uint64_t kq[KW];
-        key_of<KW>(L.rec + uint64_t(p - 1) * RW, P.kmask, kq);
+        uint64_t kp[KW], kq[KW];
+        slot_key<RW, KW>(P, L, L.perm[p], kp);
+        slot_key<RW, KW>(P, L, L.perm[p - 1], kq);
         start = digit_of<KW>(kp, lo2, fw) != digit_of<KW>(kq, lo2, fw);
       }
     }
@@ -1363,17 +1264,20 @@ __device__ __forceinline__ void mid_first_split(const Params& P, MidLds& L, cons
 }
 
 // Sorts jobs of at most mid_max records entirely in LDS (the small-bin case of
-// Sec. 3.2, with LDS in the role of the cache).  A first workgroup-wide radix
-// pass reads the job from HBM straight into registers and writes it to LDS in
-// digit order, on the highest digit in which the job's keys differ.  Ranges
-// still larger than tiny_max get further passes: by the whole workgroup when
-// they exceed one wave's capacity, else by single waves in parallel, round by
-// round.  Ranges of at most tiny_max records are finished by enumeration sort
+// Sec. 3.2, with LDS in the role of the cache).  The job's keys are read from
+// HBM once into LDS, where they stay; every pass permutes a 16-bit index array
+// instead of moving records.  A first split orders the job by the 2*digit_bits
+// key bits below the highest bit in which its keys differ; ranges still larger
+// than tiny_max get further passes, by the whole workgroup when they exceed
+// one wave's capacity, else by single waves in parallel, round by round.
+// Ranges of at most tiny_max records are finished by enumeration sort
 // (Sec. 2.2, 3.3): each record's place is the number of smaller keys plus the
-// number of equal keys before it.  The job is written back in one coalesced
-// pass.
+// number of equal keys before it.  Finally every thread gathers its records
+// through the permutation from the job's source (just read, so it is served
+// from cache), the workgroup waits until all of them are in registers, and
+// the job is written back in one coalesced pass.
 template <int RW, int KW>
-__global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
+__global__ void __launch_bounds__(kMidBlock, 4) k_mid(Params P) {
   constexpr int W = kMidWaves;
   constexpr int WI = mid_wave_items(RW);
   extern __shared__ __align__(16) uint8_t smem[];
@@ -1385,10 +1289,10 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
 
   const uint32_t T = P.mid_max;
   MidLds L;
-  L.rec = reinterpret_cast<uint64_t*>(smem);
-  L.perm = reinterpret_cast<uint16_t*>(L.rec + uint64_t(T) * RW);
-  L.cnt = L.perm;
-  L.bm = reinterpret_cast<uint32_t*>(L.perm + align_up(T > W * kRadix ? T : W * kRadix, 2));
+  L.key = reinterpret_cast<uint64_t*>(smem);
+  L.perm = reinterpret_cast<uint16_t*>(L.key + uint64_t(T) * KW);
+  L.cnt = L.perm + align_up(T, 2);
+  L.bm = reinterpret_cast<uint32_t*>(L.cnt + W * kRadix);
   L.big = s_big;
   L.list0 = s_list[0];
   L.list1 = s_list[1];
@@ -1402,7 +1306,7 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
 
   Ctrl* c = P.L.ctrl;
   const uint32_t njobs = min(c->mid_count, P.L.cap_mid);
-  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t tiny = P.tiny_max;
   const uint32_t wave_cap = kWave * WI;
 
@@ -1418,29 +1322,36 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
                          uint64_t(job.start) * RW;
     uint64_t* dw = reinterpret_cast<uint64_t*>(arr.recs) + uint64_t(job.start) * RW;
 
+    // the job's keys, once, from HBM into LDS in input order
+    for (uint32_t i = tid; i < m; i += kMidBlock) {
+      uint64_t k[KW];
+      key_of<KW>(gmem(sw) + uint64_t(i) * RW, P.kmask, k);
+#pragma unroll
+      for (int q = 0; q < KW; ++q) L.key[uint64_t(i) * KW + q] = k[q];
+    }
     for (uint32_t q = tid; q < (m >> 5) + 2; q += kMidBlock) L.bm[q] = 0;
     if (tid == 0) {
       s_nbig = 0;
       s_nlist[0] = 0;
       s_nlist[1] = 0;
     }
-    __syncthreads();
+    lds_barrier();
     if (m > tiny) {
-      mid_first_split<RW, KW>(P, L, sw, m, wave_cap);
+      mid_first_split<RW, KW>(P, L, m, wave_cap);
     } else {
-      for (uint32_t q = tid; q < m * RW; q += kMidBlock) L.rec[q] = gmem(sw)[q];
+      for (uint32_t i = tid; i < m; i += kMidBlock) L.perm[i] = uint16_t(i);
       if (tid == 0) L.bm[0] = 1u;
-      __syncthreads();
+      lds_barrier();
     }
     // ranges too large for one wave
     for (;;) {
       const uint32_t nbig = min(s_nbig, kMidBigCap);
       if (nbig == 0) break;
       const uint32_t e = s_big[nbig - 1];
-      __syncthreads();
+      lds_barrier();
       if (tid == 0) s_nbig = nbig - 1;
-      __syncthreads();
-      mid_wg_pass<RW, KW, false>(P, L, nullptr, e & 0xFFFFu, e >> 16, wave_cap);
+      lds_barrier();
+      mid_wg_pass<RW, KW>(P, L, e & 0xFFFFu, e >> 16, wave_cap);
     }
     // medium ranges: one wave each, round by round
     for (uint32_t cur = 0;; cur ^= 1) {
@@ -1450,7 +1361,7 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
         s_claim = 0;
         s_nlist[cur ^ 1] = 0;
       }
-      __syncthreads();
+      lds_barrier();
       for (;;) {
         uint32_t k = 0;
         if (lane == 0) k = atomicAdd(&s_claim, 1u);
@@ -1459,52 +1370,77 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
         const uint32_t e = s_list[cur][k];
         mid_wave_pass<RW, KW, WI>(P, L, e & 0xFFFFu, e >> 16, cur ^ 1, wave_cap);
       }
-      __syncthreads();
+      lds_barrier();
       if (tid == 0) s_nlist[cur] = 0;
     }
-    __syncthreads();
+    lds_barrier();
 
-    // ---- tiny ranges: enumeration sort; everything else stays in place
-    for (uint32_t p = tid; p < m; p += kMidBlock) {
-      uint32_t dest = p;
-      const int lo = int(p) > int(tiny) ? int(p - tiny) : 0;
-      const int s = bm_prev(L.bm, int(p), lo);
-      if (s >= 0) {
+    // ---- tiny ranges: enumeration sort; everything else stays in place.
+    // A range of at most tiny_max records belongs to the wave that owns the
+    // 64-position window its first position falls in, so each wave reads,
+    // ranks and rewrites only positions no other wave touches.
+    const uint32_t wave = tid >> 6;
+    const uint32_t nwin = (m + kWave - 1) / kWave;
+    for (uint32_t k = wave; k < nwin; k += W) {
+      const uint32_t w0 = k * kWave;
+      uint32_t dst[kMidEsItems], slot[kMidEsItems];
+      bool act[kMidEsItems];
+#pragma unroll
+      for (int h = 0; h < kMidEsItems; ++h) {
+        const uint32_t p = w0 + h * kWave + lane;
+        act[h] = false;
+        dst[h] = p;
+        slot[h] = 0;
+        if (p >= m || uint32_t(h) * kWave > tiny + kWave) continue;
+        const int lo = int(p) > int(tiny) ? int(p - tiny) : 0;
+        const int s = bm_prev(L.bm, int(p), lo);
+        if (s < int(w0) || s >= int(w0 + kWave)) continue;  // not a range of this window
         const int hi = min(s + int(tiny), int(m) - 1);
         int e = bm_next(L.bm, int(p), hi);
         if (e < 0 && s + int(tiny) >= int(m)) e = int(m);
-        if (e > 0 && e - s >= 2) {
-          uint64_t kp[KW];
-          key_of<KW>(L.rec + uint64_t(p) * RW, P.kmask, kp);
-          uint32_t r = 0;
-          for (int q = s; q < e; ++q) {
-            uint64_t kq[KW];
-            key_of<KW>(L.rec + uint64_t(q) * RW, P.kmask, kq);
-            r += (key_lt<KW>(kq, kp) || (q < int(p) && key_eq<KW>(kq, kp))) ? 1u : 0u;
-          }
-          dest = uint32_t(s) + r;
+        if (e < 0 || e - s < 2) continue;
+        slot[h] = L.perm[p];
+        uint64_t kp[KW];
+        slot_key<RW, KW>(P, L, slot[h], kp);
+        uint32_t r = 0;
+        for (int q = s; q < e; ++q) {
+          uint64_t kq[KW];
+          slot_key<RW, KW>(P, L, L.perm[q], kq);
+          r += (key_lt<KW>(kq, kp) || (q < int(p) && key_eq<KW>(kq, kp))) ? 1u : 0u;
         }
+        dst[h] = uint32_t(s) + r;
+        act[h] = true;
       }
-      L.perm[dest] = uint16_t(p);
+      __builtin_amdgcn_wave_barrier();
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int h = 0; h < kMidEsItems; ++h)
+        if (act[h]) L.perm[dst[h]] = uint16_t(slot[h]);
+    }
+    lds_barrier();
+    // gather every record of the job (all loads complete before any store:
+    // source and destination may be the same buffer), then write in order
+    constexpr int WO = mid_items(RW, KW);
+    uint64_t out[WO][RW];
+#pragma unroll
+    for (int u = 0; u < WO; ++u) {
+      const uint32_t p = tid + u * kMidBlock;
+      if (p < m) {
+        uint32_t sl = L.perm[p];
+        if (sl >= m) {  // never taken while the passes above keep perm a permutation
+          atomicOr(&c->error, kErrBounds);
+          sl = 0;
+        }
+        load_rec<RW>(reinterpret_cast<const uint8_t*>(sw), sl, out[u]);
+      }
     }
     __syncthreads();
-    for (uint32_t p = tid; p < m; p += kMidBlock) {
-      const uint64_t* r = L.rec + uint64_t(L.perm[p]) * RW;
-      RADULS_GLOBAL uint64_t* o = gmem(dw) + uint64_t(p) * RW;
-      if constexpr (RW % 2 == 0) {
 #pragma unroll
-        for (int q = 0; q < RW; q += 2) {
-          u64x2 v;
-          v.x = r[q];
-          v.y = r[q + 1];
-          *reinterpret_cast<RADULS_GLOBAL u64x2*>(o + q) = v;
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < RW; ++q) o[q] = r[q];
-      }
+    for (int u = 0; u < WO; ++u) {
+      const uint32_t p = tid + u * kMidBlock;
+      if (p < m) store_rec<RW>(reinterpret_cast<uint8_t*>(dw), p, out[u], false);
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 

@@ -34,30 +34,17 @@ raduls_tuning current_tuning() {
   return g_tuning;
 }
 
-// LDS bytes of one LDS-sort workgroup for jobs of up to T records of RW words;
-// mirrors the carve-up at the top of k_mid.
-uint64_t mid_dynamic_lds(uint32_t T, uint32_t rw) {
-  const uint64_t perm = align_up(std::max<uint64_t>(T, uint64_t(kMidWaves) * kRadix), 2) * 2;
-  return uint64_t(T) * rw * 8 + perm + 4ull * ((T >> 5) + 2);
-}
-
-uint32_t mid_capacity_rw(uint32_t rw) {
-  const uint32_t hard = uint32_t(kMidBlock) * uint32_t(mid_items(int(rw)));
-  const uint64_t budget = kLdsBytes - kMidFixedLds;
-  uint32_t T = hard - hard % 64;
-  while (T > 64 && mid_dynamic_lds(T, rw) > budget) T -= 64;
-  return T;
-}
+uint32_t mid_capacity(uint32_t rw, uint32_t kw) { return mid_cap(int(rw), int(kw)); }
 
 struct Eff {  // tuning after defaults and clamps, for one record width
   uint32_t digit_bits, tiny_max, mid_max, tile, nontemporal, grid_blocks, lookback;
 };
 
-Eff effective(const raduls_tuning& t, uint32_t R) {
+Eff effective(const raduls_tuning& t, uint32_t R, uint32_t K) {
   const uint32_t rw = R / 8;
   Eff e;
   e.digit_bits = t.digit_bits ? std::min<uint32_t>(std::max<uint32_t>(t.digit_bits, 1), 8) : 8;
-  const uint32_t cap = mid_capacity_rw(rw);
+  const uint32_t cap = mid_capacity(rw, (K + 7) / 8);
   e.mid_max = t.mid_max ? std::min(t.mid_max, cap) : cap;
   e.tiny_max = t.tiny_max ? std::min<uint32_t>(std::max<uint32_t>(t.tiny_max, 1), 256) : 64;
   // ranges waiting for an LDS pass are disjoint and larger than tiny_max
@@ -216,8 +203,8 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
                                  : std::max<uint32_t>(1, std::min<uint32_t>(s.cap_tiles, 2 * cus));
   P.grid_classify = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_large, 4 * cus));
   P.scatter_lds_bytes = scatter_lds_bytes(int(R / 8));
-  P.mid_lds_bytes = uint32_t(mid_dynamic_lds(e.mid_max, R / 8));
-  const uint32_t per_cu = (P.mid_lds_bytes + kMidFixedLds) * 2 <= kLdsBytes ? 2 : 1;
+  P.mid_lds_bytes = mid_dynamic_lds(e.mid_max, int((K + 7) / 8));
+  const uint32_t per_cu = (P.mid_lds_bytes + kMidStaticLds) * 2 <= kLdsBytes ? 2 : 1;
   P.grid_mid = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_mid, per_cu * cus));
   P.grid_copy = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_copy, 2 * cus));
 }
@@ -253,7 +240,7 @@ int raduls_tmp_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint64_
   if (st) return st;
   if (!out_bytes) return RADULS_E_INVALID;
   if (n >= (1ull << 32)) return RADULS_E_UNSUPPORTED;
-  const Eff e = effective(current_tuning(), rec_bytes);
+  const Eff e = effective(current_tuning(), rec_bytes, key_bytes);
   const Shape s = plan_shape(n, 1, rec_bytes, key_bytes, e, false);
   *out_bytes = aux_offset(n, rec_bytes) + s.bytes;
   return RADULS_OK;
@@ -267,7 +254,7 @@ int raduls_sort(void* recs, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t 
   if (n <= 1) return RADULS_OK;
   if (!recs || !tmp) return RADULS_E_INVALID;
   if (misaligned(recs) || misaligned(tmp)) return RADULS_E_ALIGN;
-  const Eff e = effective(current_tuning(), rec_bytes);
+  const Eff e = effective(current_tuning(), rec_bytes, key_bytes);
   const Shape s = plan_shape(n, 1, rec_bytes, key_bytes, e, false);
   const uint64_t need = aux_offset(n, rec_bytes) + s.bytes;
   if (overlap(recs, n * rec_bytes, tmp, need)) return RADULS_E_INVALID;
@@ -288,7 +275,7 @@ int raduls_batch_ws_bytes(uint32_t count, uint64_t total_n, uint32_t rec_bytes,
   int st = check_shape(rec_bytes, key_bytes);
   if (st) return st;
   if (!out_bytes) return RADULS_E_INVALID;
-  const Eff e = effective(current_tuning(), rec_bytes);
+  const Eff e = effective(current_tuning(), rec_bytes, key_bytes);
   *out_bytes = plan_shape(total_n, count, rec_bytes, key_bytes, e, false).bytes;
   return RADULS_OK;
 }
@@ -301,7 +288,7 @@ int raduls_sort_batch(const raduls_array* d_arrays, uint32_t count, uint64_t tot
   if (count == 0) return RADULS_OK;
   if (!d_arrays || !ws) return RADULS_E_INVALID;
   if (misaligned(d_arrays) || misaligned(ws)) return RADULS_E_ALIGN;
-  const Eff e = effective(current_tuning(), rec_bytes);
+  const Eff e = effective(current_tuning(), rec_bytes, key_bytes);
   const Shape s = plan_shape(total_n, count, rec_bytes, key_bytes, e, false);
   if (ws_bytes < s.bytes) return RADULS_E_TMP_SMALL;
   if (overlap(d_arrays, uint64_t(count) * sizeof(raduls_array), ws, s.bytes))
@@ -318,7 +305,7 @@ int raduls_step_ws_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uin
   if (st) return st;
   if (!out_bytes) return RADULS_E_INVALID;
   if (n >= (1ull << 32)) return RADULS_E_UNSUPPORTED;
-  const Eff e = effective(current_tuning(), rec_bytes);
+  const Eff e = effective(current_tuning(), rec_bytes, key_bytes);
   *out_bytes = plan_shape(n, 1, rec_bytes, key_bytes, e, true).bytes;
   return RADULS_OK;
 }
@@ -333,7 +320,7 @@ static int step_common(const void* src, void* dst, uint64_t n, uint32_t R, uint3
   if (!src || !ws || (mode == kModePartition && !dst) || (mode == kModeHist && !d_counts))
     return RADULS_E_INVALID;
   if (misaligned(src) || misaligned(ws) || (dst && misaligned(dst))) return RADULS_E_ALIGN;
-  const Eff e = effective(current_tuning(), R);
+  const Eff e = effective(current_tuning(), R, K);
   const Shape s = plan_shape(n, 1, R, K, e, true);
   if (ws_bytes < s.bytes) return RADULS_E_TMP_SMALL;
   if (mode == kModePartition && overlap(src, n * R, dst, n * R)) return RADULS_E_INVALID;
@@ -410,9 +397,9 @@ int raduls_set_profile_events(hipEvent_t* events, uint32_t count) {
   return RADULS_OK;
 }
 
-uint32_t raduls_mid_capacity(uint32_t rec_bytes) {
-  if (rec_bytes < 8 || rec_bytes > 64 || rec_bytes % 8) return 0;
-  return mid_capacity_rw(rec_bytes / 8);
+uint32_t raduls_mid_capacity(uint32_t rec_bytes, uint32_t key_bytes) {
+  if (check_shape(rec_bytes, key_bytes) != RADULS_OK) return 0;
+  return mid_capacity(rec_bytes / 8, (key_bytes + 7) / 8);
 }
 
 const char* raduls_strerror(int status) {

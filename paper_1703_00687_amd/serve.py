@@ -85,6 +85,41 @@ class Stats:
         }
 
 
+class Arena:
+    """First-fit allocator of byte ranges inside one preallocated buffer; each
+    launched batch takes one contiguous range for the scratch of all its
+    requests, so the number of live ranges never exceeds the stream count."""
+
+    ALIGN = 256
+
+    def __init__(self, size: int):
+        self.size = size
+        self.free = [(0, size)]  # sorted, coalesced (offset, length)
+
+    def alloc(self, nbytes: int) -> int | None:
+        nbytes = max(self.ALIGN, -(-nbytes // self.ALIGN) * self.ALIGN)
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= nbytes:
+                if ln == nbytes:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (off + nbytes, ln - nbytes)
+                return off
+        return None
+
+    def release(self, off: int, nbytes: int) -> None:
+        nbytes = max(self.ALIGN, -(-nbytes // self.ALIGN) * self.ALIGN)
+        self.free.append((off, nbytes))
+        self.free.sort()
+        merged = []
+        for o, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((o, ln))
+        self.free = merged
+
+
 class GpuBackend:
     """Device side of the server: per-stream batch workspaces, launches and
     completion events."""
@@ -97,6 +132,11 @@ class GpuBackend:
         self.rec_bytes, self.key_bytes = rec_bytes, key_bytes
         self.n_streams, self.max_batch = n_streams, max_batch
         self.device = torch.device(device)
+        # scratch for every admitted request comes from one resident buffer
+        self.arena_buf = torch.empty(max_records * rec_bytes + Arena.ALIGN * (max_batch + 1),
+                                     dtype=torch.uint8, device=self.device)
+        self.arena = Arena(self.arena_buf.numel())
+        self.chunks = {}
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.batches = [b.Batch(max_batch, max_records, rec_bytes, key_bytes, device=self.device)
                         for _ in range(n_streams)]
@@ -119,10 +159,20 @@ class GpuBackend:
             self.graphs[i] = g
         torch.cuda.synchronize()
 
-    def alloc_tmp(self, n: int, stream_idx: int):
-        torch = self.torch
-        with torch.cuda.stream(self.streams[stream_idx]):
-            return torch.empty((max(n, 1), self.rec_bytes), dtype=torch.uint8, device=self.device)
+    def prepare(self, stream_idx: int, reqs: list) -> bool:
+        """Carve the batch's scratch out of the arena; False if it does not fit
+        yet (the server retries after a batch completes)."""
+        step = [-(-(r.n * self.rec_bytes) // 16) * 16 for r in reqs]
+        total = sum(step)
+        off = self.arena.alloc(total)
+        if off is None:
+            return False
+        self.chunks[stream_idx] = (off, total)
+        base = self.arena_buf.data_ptr() + off
+        for r, sz in zip(reqs, step):
+            r.tmp = base
+            base += sz
+        return True
 
     def launch(self, stream_idx: int, reqs: list) -> Any:
         torch = self.torch
@@ -133,7 +183,7 @@ class GpuBackend:
         h[:] = 0
         for i, r in enumerate(reqs):
             h[i, 0] = r.recs.data_ptr()
-            h[i, 1] = r.tmp.data_ptr()
+            h[i, 1] = r.tmp
             h[i, 2] = r.n
         ev = torch.cuda.Event()
         with torch.cuda.stream(s):
@@ -148,12 +198,18 @@ class GpuBackend:
     def done(self, token) -> bool:
         return token.query()
 
+    def release(self, stream_idx: int) -> None:
+        chunk = self.chunks.pop(stream_idx, None)
+        if chunk is not None:
+            self.arena.release(*chunk)
+
     def finish(self, stream_idx: int, token, reqs: list) -> list:
         token.synchronize()
         st, stats = self.batches[stream_idx].check(self.streams[stream_idx])
         err = None if st == self.b.OK else f"device error {stats}"
         for r in reqs:
             r.tmp = None
+        self.release(stream_idx)
         return [err] * len(reqs)
 
 
@@ -288,10 +344,14 @@ class Server:
             batch, self.admitted = self.admitted, []
         # launch on the idle stream
         try:
-            for r in batch:
-                r.tmp = self.backend.alloc_tmp(r.n, s_idx)
+            if not self.backend.prepare(s_idx, batch):
+                with self.lock:  # scratch fragmented: retry after a completion
+                    self.admitted = batch + self.admitted
+                return worked
             tok = self.backend.launch(s_idx, batch)
         except Exception as e:
+            if hasattr(self.backend, "release"):
+                self.backend.release(s_idx)
             with self.lock:
                 for r in batch:
                     self.free += self.need(r.n)

@@ -94,9 +94,13 @@ def test_size_queries():
     # auxiliary workspace stays a small fraction of the data at scale
     assert b.raduls_tmp_bytes(1 << 28, 16, 8) < (1 << 28) * 16 * 1.10
     for r in range(8, 72, 8):
-        cap = b.raduls_mid_capacity(r)
-        assert cap >= 1024 and cap * r <= 160 * 1024
-    assert b.raduls_mid_capacity(12) == 0
+        for k in sorted({1, 8, min(16, r), r}):
+            cap = b.raduls_mid_capacity(r, k)
+            kw = (k + 7) // 8
+            # keys and a 16-bit permutation of a job fit one of two LDS shares
+            assert cap >= 512 and cap % 64 == 0 and cap * (8 * kw + 2) <= 80 * 1024
+    assert b.raduls_mid_capacity(12, 8) == 0
+    assert b.raduls_mid_capacity(16, 17) == 0
 
 
 def test_tuning_roundtrip_and_rejects():

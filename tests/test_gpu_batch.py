@@ -29,7 +29,7 @@ def _run_batch(host_arrays, r, k):
 
 @pytest.mark.parametrize("r,k", [(16, 8), (32, 16), (8, 8), (24, 11)])
 def test_batch_uneven_sizes(r, k):
-    cap = b.raduls_mid_capacity(r)
+    cap = b.raduls_mid_capacity(r, k)
     sizes = [0, 1, 2, 5, 33, 1000, cap - 1, cap, cap + 1, 50000, 123457, 3, 0, 77]
     rng = np.random.default_rng(r + k)
     arrays = [wl.random_records(rng, s, r, k, distinct_keys=max(1, s // 3)) for s in sizes]

@@ -32,7 +32,7 @@ def _assert_parity(out, inp, k):
 
 @pytest.mark.parametrize("r,k", SHAPES)
 def test_sizes_and_shapes(r, k):
-    cap = b.raduls_mid_capacity(r)
+    cap = b.raduls_mid_capacity(r, k)
     sizes = [0, 1, 2, 3, 31, 32, 33, 100, 1000, cap - 1, cap, cap + 1, 3 * cap + 7, 60000]
     for i, n in enumerate(sizes):
         for distinct in (None, 7):

@@ -26,8 +26,10 @@ class FakeBackend:
         self.active = 0
         self.batch_sizes = []
 
-    def alloc_tmp(self, n, stream_idx):
-        return np.empty((max(n, 1), 16), dtype=np.uint8)
+    def prepare(self, stream_idx, reqs):
+        for r in reqs:
+            r.tmp = np.empty((max(r.n, 1), 16), dtype=np.uint8)
+        return True
 
     def launch(self, stream_idx, reqs):
         if self.fail_launch(reqs):
@@ -184,3 +186,19 @@ def test_stop_without_drain_cancels_pending():
     assert s["cancelled"] >= 3
     done = sum(1 for f in futs if f.done() and f.exception() is None)
     assert done >= 1
+
+
+def test_arena_first_fit_and_coalescing():
+    a = serve.Arena(4096)
+    x = a.alloc(1000)
+    y = a.alloc(1000)
+    z = a.alloc(1000)
+    assert (x, y, z) == (0, 1024, 2048)
+    assert a.alloc(2000) is None
+    a.release(y, 1000)
+    assert a.alloc(1100) is None      # the hole is 1024 bytes
+    a.release(x, 1000)
+    assert a.alloc(2000) == 0          # coalesced with the first hole
+    a.release(0, 2000)
+    a.release(z, 1000)
+    assert a.free == [(0, 4096)]
