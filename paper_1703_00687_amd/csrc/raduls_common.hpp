@@ -29,28 +29,36 @@ __host__ __device__ constexpr uint32_t scatter_lds_bytes(int rw) {
          uint32_t(kScatterWaves * 256 * 2) + 3u * 256u * 4u + 256u * 8u;
 }
 
-// LDS sorter workgroups: 8 waves, two workgroups per CU.  Only keys and a
-// 16-bit permutation live in LDS; payloads are gathered from HBM at the end.
-constexpr int kMidBlock = 512;
+// LDS sorter workgroups: 16 waves, one workgroup per CU, which owns the
+// CU's LDS.  Keys and a 16-bit permutation live in LDS; every thread holds
+// the records of its slots in registers.
+constexpr int kMidBlock = 1024;
 constexpr int kMidWaves = kMidBlock / kWave;
+constexpr uint32_t kLdsBytes = 160 * 1024;
 constexpr uint32_t kMidStaticLds = 6 * 1024;  // static LDS of the LDS sorter (upper bound)
-constexpr uint32_t kMidLdsPerGroup = 80 * 1024;  // two workgroups per CU
-// Dynamic LDS for jobs of up to T records with KW key words.
-__host__ __device__ constexpr uint32_t mid_dynamic_lds(uint32_t T, int kw) {
-  return T * uint32_t(kw) * 8u + ((T + 1u) / 2u) * 4u + uint32_t(kMidWaves) * 256u * 2u +
-         4u * ((T >> 5) + 2u);
+// Widest digit of a job's first pass; its counters are 16-bit, two per
+// word (the words also hold the 256 counters of each wave in single-wave
+// passes).
+constexpr int kMidFirstBits = 13;
+constexpr uint32_t kMidCounterWords = 1u << (kMidFirstBits - 1);
+static_assert(kMidCounterWords >= uint32_t(kMidWaves) * 256u, "wave counters share the pass counters");
+static_assert(kMidCounterWords % kMidBlock == 0, "counter scan splits evenly over the workgroup");
+// Dynamic LDS for jobs of up to T records of rw words: the records (in input
+// order), the permutation, the counters and two bitmaps.
+__host__ __device__ constexpr uint32_t mid_dynamic_lds(uint32_t T, int rw) {
+  return T * uint32_t(rw) * 8u + ((T + 1u) / 2u) * 4u + kMidCounterWords * 4u + 8u * ((T >> 5) + 2u);
 }
-// Records per lane a whole-job pass can hold without spilling at the
-// 128-VGPR budget of two 512-thread workgroups per CU; the write-out holds
-// every record of the job in registers.
+// Records per lane of a whole job: while a job is sorted, every thread holds
+// the next job's records of its slots in registers (at most 32 VGPRs).
 __host__ __device__ constexpr uint32_t mid_lane_items(int rw) {
-  return rw <= 2 ? 10u : (24u / uint32_t(rw) < 10u ? 24u / uint32_t(rw) : 10u);
+  return rw <= 2 ? 5u : 16u / uint32_t(rw);
 }
-// Largest job (records, a multiple of 64): its keys fit the LDS share and
-// its records fit the lanes' registers.
+// Largest job (records, a multiple of 64): its records fit the lanes'
+// registers and its LDS state the CU's LDS.
 __host__ __device__ constexpr uint32_t mid_cap(int rw, int kw) {
+  (void)kw;
   uint32_t t = uint32_t(kMidBlock) * mid_lane_items(rw);
-  while (t > 64u && mid_dynamic_lds(t, kw) + kMidStaticLds > kMidLdsPerGroup) t -= 64u;
+  while (t > 64u && mid_dynamic_lds(t, rw) + kMidStaticLds > kLdsBytes) t -= 64u;
   return t;
 }
 // Records per thread of a workgroup-wide LDS pass over a whole job.
@@ -60,7 +68,6 @@ __host__ __device__ constexpr int mid_items(int rw, int kw) {
 // Records per lane of a single-wave LDS pass (a wave handles ranges of up to
 // 64 * mid_wave_items records).
 __host__ __device__ constexpr int mid_wave_items(int rw) { return rw <= 2 ? 8 : rw <= 4 ? 4 : 2; }
-constexpr uint32_t kLdsBytes = 160 * 1024;
 constexpr uint32_t kMidListCap = 384;   // ranges waiting for a wave pass (per round)
 constexpr uint32_t kMidBigCap = 64;     // ranges waiting for a workgroup pass
 // Positions per lane of the enumeration phase: a range of at most 256 records
@@ -114,6 +121,16 @@ struct Bin {
   uint8_t flags;
 };
 
+// An LDS-sort job: a run of at most mid_max records, sorted from src into
+// dst (the same address when the run already sits in the output buffer).
+struct MidJob {
+  uint8_t* src;
+  uint8_t* dst;
+  uint32_t size;
+  uint32_t pad[3];
+};
+static_assert(sizeof(MidJob) == 32, "job descriptors are read as two 16-byte vectors");
+
 // Device control block at the start of the auxiliary workspace; cleared at
 // the start of every call.
 struct Ctrl {
@@ -126,7 +143,8 @@ struct Ctrl {
   uint32_t rounds;
   uint32_t large_bins;
   uint32_t scattered_bins;
-  uint32_t pad[2];
+  uint32_t mid_claim;  // LDS-sort jobs handed out beyond the first one per workgroup
+  uint32_t pad;
   unsigned long long moved_records;
   unsigned long long large_records;
   unsigned long long batch_total;
@@ -145,7 +163,7 @@ struct Layout {
   uint32_t* wg_tail;      // [cap_ranges][kRadix] counts of each range's last bin segment
   uint32_t* wg_carry;     // [cap_ranges][kRadix] prefix carried into each range
   uint32_t* wg_flag;      // [cap_ranges] range starts a bin (1) / lies in one bin (2)
-  Bin* mid;
+  MidJob* mid;
   Bin* copy;
   uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges;
 };

@@ -102,7 +102,7 @@ __device__ __forceinline__ void key_of(Ptr w, uint64_t kmask, uint64_t (&k)[KW])
   k[KW - 1] &= kmask;
 }
 
-// Bits [lo, lo + w) of a multi-word key, 1 <= w <= 8.
+// Bits [lo, lo + w) of a multi-word key, 1 <= w <= 16.
 template <int KW>
 __device__ __forceinline__ uint32_t digit_of(const uint64_t (&k)[KW], uint32_t lo, uint32_t w) {
   const uint32_t wi = lo >> 6, sh = lo & 63;
@@ -147,19 +147,33 @@ __device__ __forceinline__ int top_bit(const uint64_t (&d)[KW]) {
   return r;
 }
 
-__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
-  return v;
+// Wave-wide OR, returned to every lane: DPP reductions inside each row of 16
+// lanes, then the rows combined through the broadcasts of lanes 15 and 31,
+// after which lane 63 holds the total.
+__device__ __forceinline__ uint32_t wave_or32(uint32_t v) {
+  v |= uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v |= uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v |= uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x124, 0xF, 0xF, false));  // row_ror:4
+  v |= uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x128, 0xF, 0xF, false));  // row_ror:8
+  v |= uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v |= uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return uint32_t(__builtin_amdgcn_readlane(int(v), 63));
 }
 
+__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
+  return (uint64_t(wave_or32(uint32_t(v >> 32))) << 32) | wave_or32(uint32_t(v));
+}
+
+// Inclusive prefix sum over the wave's lanes: DPP shifts inside each row of
+// 16 lanes (lanes shifted in from outside the row add 0), then each row adds
+// the totals of the rows before it through the broadcasts of lanes 15 and 31.
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
-  const uint32_t lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t u = __shfl_up(v, o);
-    if (lane >= uint32_t(o)) v += u;
-  }
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x111, 0xF, 0xF, false));  // row_shr:1
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x112, 0xF, 0xF, false));  // row_shr:2
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x114, 0xF, 0xF, false));  // row_shr:4
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x118, 0xF, 0xF, false));  // row_shr:8
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x143, 0xC, 0xF, false));  // row_bcast:31
   return v;
 }
 
@@ -264,6 +278,21 @@ __device__ __forceinline__ void push_large(const Params& P, uint32_t nxt, const 
   for (int q = 0; q < 8; ++q) df[q] = 0;
 }
 
+// Append an LDS-sort job for bin b of array a.
+__device__ __forceinline__ void push_mid(const Params& P, const Bin& b, const ArrayDesc& a) {
+  const uint32_t i = atomicAdd(&P.L.ctrl->mid_count, 1u);
+  if (i >= P.L.cap_mid) {
+    atomicOr(&P.L.ctrl->error, kErrCapacity);
+    return;
+  }
+  MidJob j;
+  j.src = (b.side ? a.tmp : a.recs) + uint64_t(b.start) * P.R;
+  j.dst = a.recs + uint64_t(b.start) * P.R;
+  j.size = b.size;
+  j.pad[0] = j.pad[1] = j.pad[2] = 0;
+  P.L.mid[i] = j;
+}
+
 // Copy jobs for a finished run of records that sits in tmp.
 __device__ __forceinline__ void push_copy(const Params& P, uint32_t array, uint32_t start,
                                           uint32_t size) {
@@ -313,8 +342,7 @@ static __global__ void __launch_bounds__(64) k_seed_single(Params P) {
         P.L.large[0][0] = b;
         c->large_count[0] = 1;
       } else if (P.n >= 2) {
-        P.L.mid[0] = b;
-        c->mid_count = 1;
+        push_mid(P, b, a);
       }
     }
   }
@@ -355,7 +383,7 @@ static __global__ void __launch_bounds__(256) k_seed_batch(Params P) {
     b.side = 0;
     b.flags = 0;
     if (d.n > P.mid_max) push_large(P, 0, b);
-    else if (d.n >= 2) push_bin(P.L.mid, &c->mid_count, P.L.cap_mid, b, &c->error);
+    else if (d.n >= 2) push_mid(P, b, d);
   }
 }
 
@@ -952,7 +980,7 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
           j.bits = uint16_t(jc == 1 ? lob : bin.bits);
           j.side = cside;
           j.flags = uint8_t(jc > 1);
-          push_bin(P.L.mid, &c->mid_count, P.L.cap_mid, j, &c->error);
+          push_mid(P, j, P.L.arrays[bin.array]);
         }
         jn = 0;
         jc = 0;
@@ -1007,37 +1035,62 @@ __device__ __forceinline__ int bm_next(const uint32_t* bm, int p, int hi) {
 }
 
 // LDS state of one LDS-sort workgroup.  The job's keys stay in LDS in input
-// order; every pass permutes `perm`, the slots in sorted order.
+// order; every pass permutes `perm`, the slots (input positions) in sorted
+// order.
 struct MidLds {
-  uint64_t* key;    // [T * KW] keys of the job (masked), input order
-  uint16_t* perm;   // [T] position -> record slot
-  uint16_t* cnt;    // [kMidWaves * kRadix] per-wave ranking counters
+  uint64_t* key;    // [T * kstride] records of the job, input order (key words first)
+  uint32_t kstride; // words per record
+  uint64_t kmask;   // mask of the key bytes in the top key word
+  uint16_t* perm;   // [T] position -> slot
+  uint32_t* cnt;    // [kMidCounterWords] digit counters / offsets of a pass
   uint32_t* bm;     // boundary bitmap: bit p set where a sub-range starts
+  uint32_t* bmb;    // positions left to later passes by the first pass
   uint32_t* big;    // ranges waiting for a workgroup pass (start | size << 16)
   uint32_t* list0;  // ranges waiting for a wave pass, double-buffered by round
   uint32_t* list1;
   uint32_t* nbig;
   uint32_t* nlist;  // [2]
   uint32_t* claim;  // next entry of the current list to claim
-  uint32_t* tot;    // [kRadix]
-  uint32_t* off;    // [kRadix]
-  uint32_t* scan;   // [8]
-  unsigned long long* diff;  // [kMidWaves * KW]
+  uint32_t* scan;   // [kMidWaves]
+  unsigned long long* diff;  // [kMidWaves * (KW + 1)]
 };
 
-template <int RW, int KW>
-__device__ __forceinline__ void slot_key(const Params& P, const MidLds& L, uint32_t slot,
-                                         uint64_t (&k)[KW]) {
+// Order inside a job: by key, then by slot.  Sorting by this pair is the
+// stable sort of the job, and every pair is distinct, so the passes below
+// need not be stable: equal keys are put back in input order by slot.
+
+template <int KW>
+__device__ __forceinline__ void slot_key(const MidLds& L, uint32_t slot, uint64_t (&k)[KW]) {
 #pragma unroll
-  for (int q = 0; q < KW; ++q) k[q] = L.key[uint64_t(slot) * KW + q];
+  for (int q = 0; q < KW; ++q) k[q] = L.key[uint64_t(slot) * L.kstride + q];
+  k[KW - 1] &= L.kmask;
 }
 
-// Route a sub-range by size: > wave capacity -> workgroup pass, > tiny ->
-// wave pass, else enumeration sort later.  Its start is always marked.
+// Digit [lob, lob + w) of the pair (key, slot): of the key, or of the slot
+// once the keys of the range are all equal.
+template <int KW>
+__device__ __forceinline__ uint32_t pair_digit(const uint64_t (&k)[KW], uint32_t slot,
+                                               bool by_slot, uint32_t lob, uint32_t w) {
+  return by_slot ? (slot >> lob) & ((1u << w) - 1u) : digit_of<KW>(k, lob, w);
+}
+
+// Highest differing bit of a range from the OR of (key ^ key0) and of
+// (slot ^ slot0) over it: returns hb = that bit + 1 (0 if the range has one
+// element) and whether it is a slot bit.
+template <int KW>
+__device__ __forceinline__ uint32_t pair_top(const uint64_t (&dk)[KW], uint32_t ds, bool& by_slot) {
+  const int tb = top_bit<KW>(dk);
+  by_slot = tb < 0;
+  if (!by_slot) return uint32_t(tb) + 1;
+  return ds ? 32u - uint32_t(__clz(ds)) : 0u;
+}
+
+// Route a sub-range: it starts a run in the boundary bitmap; ranges above
+// tiny_max wait for a workgroup pass (> wave capacity) or a wave pass.
 __device__ __forceinline__ void mid_route(const Params& P, MidLds& L, uint32_t st, uint32_t cnt,
-                                          uint32_t bits_left, uint32_t wave_cap, uint32_t lst) {
+                                          uint32_t wave_cap, uint32_t lst) {
   atomicOr(&L.bm[st >> 5], 1u << (st & 31));
-  if (cnt <= P.tiny_max || bits_left == 0) return;
+  if (cnt <= P.tiny_max) return;
   const uint32_t e = st | (cnt << 16);
   if (cnt > wave_cap) {
     const uint32_t k = atomicAdd(L.nbig, 1u);
@@ -1050,102 +1103,176 @@ __device__ __forceinline__ void mid_route(const Params& P, MidLds& L, uint32_t s
   }
 }
 
-// Stable workgroup pass over positions [s, s + m): ranks the records at those
-// positions by the digit [lob, lob + w) and rewrites perm[s .. s+m) in digit
-// order.  When `identity`, perm is not read (position i holds slot i).
-// Returns through L.tot / L.off the digit counts and offsets.  All threads call.
-template <int RW, int KW, int ITEMS>
-__device__ __forceinline__ void mid_wg_digit(const Params& P, MidLds& L, uint32_t s, uint32_t m,
-                                             uint32_t lob, uint32_t w, bool identity) {
-  constexpr int W = kMidWaves;
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const uint32_t ipw = (m + kWave * W - 1) / (kWave * W);
-  uint32_t src[ITEMS], dg[ITEMS], rank[ITEMS];
-  bool valid[ITEMS];
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    const uint32_t i = wave * ipw * kWave + j * kWave + lane;
-    valid[j] = (uint32_t(j) < ipw) && (i < m);
-    src[j] = 0;
-    dg[j] = 0;
-    if (valid[j]) {
-      src[j] = identity ? s + i : L.perm[s + i];
-      uint64_t key[KW];
-      slot_key<RW, KW>(P, L, src[j], key);
-      dg[j] = digit_of<KW>(key, lob, w);
-    }
+// Sets bits [st, st + len) of an LDS bitmap.
+__device__ __forceinline__ void set_bits(uint32_t* b, uint32_t st, uint32_t len) {
+  for (uint32_t p = st, e = st + len; p < e;) {
+    const uint32_t lo = p & 31, n = min(32u - lo, e - p);
+    atomicOr(&b[p >> 5], (n == 32 ? ~0u : ((1u << n) - 1u)) << lo);
+    p += n;
   }
-  uint16_t* wc = L.cnt + wave * kRadix;
-  for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
-  wave_rank<ITEMS>(dg, valid, w, wc, rank);
-  lds_barrier();  // every perm entry of the range has been read
-  block_digit_scan<W>(L.cnt, L.tot, L.off, L.scan);
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j)
-    if (valid[j]) L.perm[s + L.off[dg[j]] + wc[dg[j]] + rank[j]] = uint16_t(src[j]);
 }
 
-// Key spread of positions [s, s + m) over the workgroup: the highest bit in
-// which their keys differ, or -1.  All threads call.
-template <int RW, int KW>
-__device__ __forceinline__ int mid_wg_top_bit(const Params& P, MidLds& L, uint32_t s, uint32_t m,
-                                              bool identity) {
-  constexpr int W = kMidWaves;
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint64_t key0[KW], dacc[KW];
-  slot_key<RW, KW>(P, L, identity ? s : L.perm[s], key0);
+// Counters of a workgroup pass: two 16-bit counts (later offsets) per word,
+// digit d in half d & 1 of word d >> 1.  Jobs hold fewer than 2^16 records,
+// so a half never carries into the other.
+__device__ __forceinline__ uint32_t pair_count(uint32_t* cnt, uint32_t d) {
+  const uint32_t sh = (d & 1u) << 4;
+  return (atomicAdd(&cnt[d >> 1], 1u << sh) >> sh) & 0xFFFFu;
+}
+__device__ __forceinline__ uint32_t pair_get(const uint32_t* cnt, uint32_t d) {
+  return (cnt[d >> 1] >> ((d & 1u) << 4)) & 0xFFFFu;
+}
+
+// Exclusive scan of the nd (even, <= 2 * kMidCounterWords) packed counters
+// in place over the workgroup, routing every non-empty digit's sub-range of
+// the range that starts at s; with `first`, sub-ranges left to later passes
+// are also marked in bmb.  All threads call; ends with a barrier.
+__device__ __forceinline__ void mid_scan_route(const Params& P, MidLds& L, uint32_t tid, uint32_t s,
+                                               uint32_t nd, uint32_t wave_cap, bool first) {
+  constexpr int kPer = kMidCounterWords / kMidBlock;
+  const uint32_t lane = tid & 63, wave = tid >> 6;
+  const uint32_t nw = nd >> 1;
+  const uint32_t per = (nw + kMidBlock - 1) / kMidBlock;
+  const uint32_t base = tid * per;
+  uint32_t v[kPer], sum = 0;
 #pragma unroll
-  for (int q = 0; q < KW; ++q) dacc[q] = 0;
-  for (uint32_t i = threadIdx.x; i < m; i += kMidBlock) {
-    uint64_t key[KW];
-    slot_key<RW, KW>(P, L, identity ? s + i : L.perm[s + i], key);
-#pragma unroll
-    for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
+  for (int k = 0; k < kPer; ++k) {
+    v[k] = (uint32_t(k) < per && base + k < nw) ? L.cnt[base + k] : 0u;
+    sum += (v[k] & 0xFFFFu) + (v[k] >> 16);
   }
+  const uint32_t incl = wave_inclusive_scan(sum);
+  if (lane == 63) L.scan[wave] = incl;
+  lds_barrier();
+  uint32_t run = incl - sum;
+  for (uint32_t w = 0; w < wave; ++w) run += L.scan[w];
 #pragma unroll
-  for (int q = 0; q < KW; ++q) {
-    const uint64_t v = wave_or(dacc[q]);
-    if (lane == 0) L.diff[wave * KW + q] = v;
+  for (int k = 0; k < kPer; ++k) {
+    if (uint32_t(k) < per && base + k < nw) {
+      const uint32_t c0 = v[k] & 0xFFFFu, c1 = v[k] >> 16;
+      L.cnt[base + k] = run | ((run + c0) << 16);
+      if (c0) {
+        mid_route(P, L, s + run, c0, wave_cap, 0);
+        if (first && c0 > P.tiny_max) set_bits(L.bmb, s + run, c0);
+      }
+      run += c0;
+      if (c1) {
+        mid_route(P, L, s + run, c1, wave_cap, 0);
+        if (first && c1 > P.tiny_max) set_bits(L.bmb, s + run, c1);
+      }
+      run += c1;
+    }
   }
   lds_barrier();
-  uint64_t dall[KW];
+}
+
+// Workgroup pass: records with slots src[] and digits dg[] (ITEMS per thread,
+// of the range [s, s + m)) are counted, the counters scanned, sub-ranges
+// routed and the slots written to their places in perm.  The counters of the
+// 2^w digits must be zero and every read of perm[s, s + m) done before the
+// call.  Afterwards they hold each digit's offset.  All threads call; ends
+// with a barrier.
+template <int ITEMS>
+__device__ __forceinline__ void mid_wg_place(const Params& P, MidLds& L, uint32_t tid, uint32_t s, uint32_t w,
+                                             const uint32_t (&src)[ITEMS], const uint32_t (&dg)[ITEMS],
+                                             const bool (&valid)[ITEMS], uint32_t wave_cap, bool first) {
+  uint32_t r[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) r[j] = valid[j] ? pair_count(L.cnt, dg[j]) : 0u;
+  lds_barrier();
+  mid_scan_route(P, L, tid, s, 1u << w, wave_cap, first);
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if (valid[j]) L.perm[s + pair_get(L.cnt, dg[j]) + r[j]] = uint16_t(src[j]);
+  lds_barrier();
+}
+
+// OR of per-thread spreads over the workgroup.  All threads call.
+template <int KW>
+__device__ __forceinline__ uint32_t mid_wg_spread(MidLds& L, uint32_t tid, uint64_t (&dk)[KW], uint32_t ds) {
+  constexpr int W = kMidWaves;
+  const uint32_t lane = tid & 63, wave = tid >> 6;
 #pragma unroll
   for (int q = 0; q < KW; ++q) {
-    dall[q] = 0;
-    for (int w2 = 0; w2 < W; ++w2) dall[q] |= L.diff[w2 * KW + q];
+    const uint64_t v = wave_or(dk[q]);
+    if (lane == 0) L.diff[wave * (KW + 1) + q] = v;
+  }
+  const uint64_t vs = wave_or(uint64_t(ds));
+  if (lane == 0) L.diff[wave * (KW + 1) + KW] = vs;
+  lds_barrier();
+  uint64_t as = 0;
+#pragma unroll
+  for (int q = 0; q < KW; ++q) dk[q] = 0;
+  for (int w2 = 0; w2 < W; ++w2) {
+#pragma unroll
+    for (int q = 0; q < KW; ++q) dk[q] |= L.diff[w2 * (KW + 1) + q];
+    as |= L.diff[w2 * (KW + 1) + KW];
   }
   lds_barrier();  // L.diff is reused by the next call
-  return top_bit<KW>(dall);
+  return uint32_t(as);
 }
 
 // Workgroup pass over a range larger than one wave can hold: split it on the
-// highest digit in which its keys differ and route the sub-ranges.
-template <int RW, int KW>
-__device__ __forceinline__ void mid_wg_pass(const Params& P, MidLds& L, uint32_t s, uint32_t m,
+// top digit_bits of the highest bits in which its (key, slot) pairs differ.
+template <int KW, int ITEMS>
+__device__ __forceinline__ void mid_wg_pass(const Params& P, MidLds& L, uint32_t tid, uint32_t s, uint32_t m,
                                             uint32_t wave_cap) {
-  const int tb = mid_wg_top_bit<RW, KW>(P, L, s, m, false);
-  if (tb < 0) return;  // all keys equal: in order
-  const uint32_t hb = uint32_t(tb) + 1;
+  uint32_t src[ITEMS];
+  bool valid[ITEMS];
+  uint64_t key0[KW], dk[KW];
+  const uint32_t slot0 = L.perm[s];
+  slot_key<KW>(L, slot0, key0);
+  uint32_t ds = 0;
+#pragma unroll
+  for (int q = 0; q < KW; ++q) dk[q] = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const uint32_t i = j * kMidBlock + tid;
+    valid[j] = i < m;
+    src[j] = 0;
+    if (valid[j]) {
+      src[j] = L.perm[s + i];
+      uint64_t k[KW];
+      slot_key<KW>(L, src[j], k);
+#pragma unroll
+      for (int q = 0; q < KW; ++q) dk[q] |= k[q] ^ key0[q];
+      ds |= src[j] ^ slot0;
+    }
+  }
+  ds = mid_wg_spread<KW>(L, tid, dk, ds);
+  bool by_slot;
+  const uint32_t hb = pair_top<KW>(dk, ds, by_slot);
   const uint32_t w = min(P.digit_bits, hb);
   const uint32_t lob = hb - w;
-  mid_wg_digit<RW, KW, mid_items(RW, KW)>(P, L, s, m, lob, w, false);
-  const uint32_t tid = threadIdx.x;
-  if (tid < (1u << w) && L.tot[tid]) mid_route(P, L, s + L.off[tid], L.tot[tid], lob, wave_cap, 0);
+  uint32_t dg[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    dg[j] = 0;
+    if (valid[j]) {
+      uint64_t k[KW];
+      slot_key<KW>(L, src[j], k);
+      dg[j] = pair_digit<KW>(k, src[j], by_slot, lob, w);
+    }
+  }
+  for (uint32_t q = tid; q < (1u << w) / 2; q += kMidBlock) L.cnt[q] = 0;
   lds_barrier();
+  mid_wg_place<ITEMS>(P, L, tid, s, w, src, dg, valid, wave_cap, false);
 }
 
-// Stable pass of one wave over positions [s, s + m), m <= 64 * WI, on the
-// highest digit in which their keys differ; sub-ranges go to list `nxt`.
-template <int RW, int KW, int WI>
-__device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32_t s, uint32_t m,
+// Pass of one wave over positions [s, s + m), m <= 64 * WI: split on the top
+// digit_bits of the highest bits in which the (key, slot) pairs differ;
+// sub-ranges go to list `nxt`.  Uses this wave's 256 counters.
+template <int KW, int WI>
+__device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32_t tid, uint32_t s, uint32_t m,
                                               uint32_t nxt, uint32_t wave_cap) {
-  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+  const uint32_t lane = tid & 63, wave = tid >> 6;
   uint32_t src[WI];
   bool valid[WI];
-  uint64_t key0[KW], dacc[KW];
-  slot_key<RW, KW>(P, L, L.perm[s], key0);
+  uint64_t key0[KW], dk[KW];
+  const uint32_t slot0 = L.perm[s];
+  slot_key<KW>(L, slot0, key0);
+  uint32_t ds = 0;
 #pragma unroll
-  for (int q = 0; q < KW; ++q) dacc[q] = 0;
+  for (int q = 0; q < KW; ++q) dk[q] = 0;
 #pragma unroll
   for (int j = 0; j < WI; ++j) {
     const uint32_t i = j * kWave + lane;
@@ -1153,35 +1280,40 @@ __device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32
     src[j] = 0;
     if (valid[j]) {
       src[j] = L.perm[s + i];
-      uint64_t key[KW];
-      slot_key<RW, KW>(P, L, src[j], key);
+      uint64_t k[KW];
+      slot_key<KW>(L, src[j], k);
 #pragma unroll
-      for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
+      for (int q = 0; q < KW; ++q) dk[q] |= k[q] ^ key0[q];
+      ds |= src[j] ^ slot0;
     }
   }
 #pragma unroll
-  for (int q = 0; q < KW; ++q) dacc[q] = wave_or(dacc[q]);
-  const int tb = top_bit<KW>(dacc);
-  if (tb < 0) return;  // all keys equal
-  const uint32_t hb = uint32_t(tb) + 1;
+  for (int q = 0; q < KW; ++q) dk[q] = wave_or(dk[q]);
+  ds = uint32_t(wave_or(uint64_t(ds)));
+  bool by_slot;
+  const uint32_t hb = pair_top<KW>(dk, ds, by_slot);
   const uint32_t w = min(P.digit_bits, hb);
   const uint32_t lob = hb - w;
-  uint32_t dg[WI], rank[WI];
-#pragma unroll
-  for (int j = 0; j < WI; ++j) {
-    dg[j] = 0;
-    if (valid[j]) {
-      uint64_t key[KW];
-      slot_key<RW, KW>(P, L, src[j], key);
-      dg[j] = digit_of<KW>(key, lob, w);
-    }
-  }
-  uint16_t* wc = L.cnt + wave * kRadix;
+  uint32_t* wc = L.cnt + wave * kRadix;
 #pragma unroll
   for (int q = 0; q < kRadix / kWave; ++q) wc[lane * 4 + q] = 0;
   __builtin_amdgcn_wave_barrier();
-  wave_rank<WI>(dg, valid, w, wc, rank);
+  asm volatile("" ::: "memory");
+  uint32_t dg[WI], r[WI];
+#pragma unroll
+  for (int j = 0; j < WI; ++j) {
+    dg[j] = 0;
+    r[j] = 0;
+    if (valid[j]) {
+      uint64_t k[KW];
+      slot_key<KW>(L, src[j], k);
+      dg[j] = pair_digit<KW>(k, src[j], by_slot, lob, w);
+      r[j] = atomicAdd(&wc[dg[j]], 1u);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0xC07F);
   __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
   // exclusive scan of the 256 counters inside the wave: 4 per lane
   uint32_t c[4], sum = 0;
 #pragma unroll
@@ -1193,154 +1325,251 @@ __device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32
   uint32_t run = incl - sum;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    wc[lane * 4 + q] = uint16_t(run);
-    if (c[q]) mid_route(P, L, s + run, c[q], lob, wave_cap, nxt);
+    wc[lane * 4 + q] = run;
+    if (c[q]) mid_route(P, L, s + run, c[q], wave_cap, nxt);
     run += c[q];
   }
+  __builtin_amdgcn_s_waitcnt(0xC07F);
   __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
 #pragma unroll
   for (int j = 0; j < WI; ++j)
-    if (valid[j]) L.perm[s + wc[dg[j]] + rank[j]] = uint16_t(src[j]);
+    if (valid[j]) L.perm[s + wc[dg[j]] + r[j]] = uint16_t(src[j]);
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
 }
 
-// First split of a job: the highest key bit in which its records differ
-// gives the top of the next two digits; two stable digit passes (lower digit
-// first, so the pair acts as one 2*digit_bits-bit digit) order the job by
-// those bits.  Runs of equal bits are marked in the boundary bitmap; runs
-// longer than tiny_max with key bits left below are routed to further passes.
-template <int RW, int KW>
-__device__ __forceinline__ void mid_first_split(const Params& P, MidLds& L, uint32_t m,
-                                                uint32_t wave_cap) {
-  constexpr int ITEMS = mid_items(RW, KW);
-  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int tb = mid_wg_top_bit<RW, KW>(P, L, 0, m, true);
-  if (tb < 0) {  // the whole job holds one key: it stays in input order
-    for (uint32_t i = tid; i < m; i += kMidBlock) L.perm[i] = uint16_t(i);
-    if (tid == 0) L.bm[0] = 1u;
-    lds_barrier();
-    return;
+// Descriptors of upcoming jobs are read with vector loads and made uniform
+// with readfirstlane when used: scalar loads share their wait counter with
+// LDS operations, so a scalar load issued in the middle of a job would be
+// waited for at the next LDS barrier.
+__device__ __forceinline__ uint32_t vzero() {
+  uint32_t z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
+}
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+struct JobV {  // a job descriptor in vector registers
+  uint32_t w[5];
+};
+__device__ __forceinline__ JobV vload_job(const MidJob* p) {
+  const RADULS_GLOBAL uint32_t* q = gmem(reinterpret_cast<const uint32_t*>(p)) + vzero();
+  JobV v;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) v.w[i] = q[i];
+  return v;
+}
+__device__ __forceinline__ MidJob uni_job(const JobV& v) {
+  MidJob j;
+  j.src = reinterpret_cast<uint8_t*>((uint64_t(uni(v.w[1])) << 32) | uni(v.w[0]));
+  j.dst = reinterpret_cast<uint8_t*>((uint64_t(uni(v.w[3])) << 32) | uni(v.w[2]));
+  j.size = uni(v.w[4]);
+  return j;
+}
+
+// Records [0, m) of a job (source `src`) into registers, all loads in flight
+// together, and the first record's key words, unmasked (every thread's
+// reference for the key spread; masking them here would wait for the load);
+// m = 0 loads nothing.
+template <int RW, int KW, int ITEMS>
+__device__ __forceinline__ void mid_fetch(const uint8_t* src, uint32_t m, uint32_t tid,
+                                          uint64_t (&kr)[ITEMS][RW], uint64_t (&key0)[KW]) {
+  const RADULS_GLOBAL uint64_t* s0 = gmem(reinterpret_cast<const uint64_t*>(src));
+#pragma unroll
+  for (int q = 0; q < KW; ++q) key0[q] = m ? s0[q] : 0ull;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const uint32_t i = j * kMidBlock + tid;
+#pragma unroll
+    for (int q = 0; q < RW; ++q) kr[j][q] = 0;
+    if (i < m) load_rec<RW>(src, i, kr[j]);
   }
-  const uint32_t hb = uint32_t(tb) + 1;
-  const uint32_t dw = P.digit_bits;
-  const uint32_t lo2 = hb > 2 * dw ? hb - 2 * dw : 0;
-  const uint32_t wa = min(dw, hb - lo2);
-  mid_wg_digit<RW, KW, ITEMS>(P, L, 0, m, lo2, wa, true);
-  if (hb > lo2 + wa) {
-    lds_barrier();
-    mid_wg_digit<RW, KW, ITEMS>(P, L, 0, m, lo2 + wa, hb - lo2 - wa, false);
-  }
-  lds_barrier();
-  // run starts: the key bits [lo2, hb) differ from the previous record's
-  const uint32_t fw = hb - lo2;
-  for (uint32_t base = wave * kWave; base < m; base += kMidBlock) {
-    const uint32_t p = base + lane;
-    bool start = false;
-    if (p < m) {
-      start = p == 0;
-      if (p > 0) {
-        uint64_t kp[KW], kq[KW];
-        slot_key<RW, KW>(P, L, L.perm[p], kp);
-        slot_key<RW, KW>(P, L, L.perm[p - 1], kq);
-        start = digit_of<KW>(kp, lo2, fw) != digit_of<KW>(kq, lo2, fw);
-      }
-    }
-    const uint64_t bal = __ballot(start);
-    if (lane == 0) {
-      L.bm[base >> 5] = uint32_t(bal);
-      L.bm[(base >> 5) + 1] = uint32_t(bal >> 32);
-    }
-  }
-  lds_barrier();
-  if (lo2 > 0) {
-    for (uint32_t p = tid; p < m; p += kMidBlock) {
-      if (L.bm[p >> 5] & (1u << (p & 31))) {
-        const int e = bm_next(L.bm, int(p), int(m) - 1);
-        const uint32_t len = (e < 0 ? m : uint32_t(e)) - p;
-        if (len > P.tiny_max) mid_route(P, L, p, len, lo2, wave_cap, 0);
-      }
-    }
-  }
-  lds_barrier();
 }
 
 // Sorts jobs of at most mid_max records entirely in LDS (the small-bin case of
-// Sec. 3.2, with LDS in the role of the cache).  The job's keys are read from
-// HBM once into LDS, where they stay; every pass permutes a 16-bit index array
-// instead of moving records.  A first split orders the job by the 2*digit_bits
-// key bits below the highest bit in which its keys differ; ranges still larger
-// than tiny_max get further passes, by the whole workgroup when they exceed
-// one wave's capacity, else by single waves in parallel, round by round.
-// Ranges of at most tiny_max records are finished by enumeration sort
-// (Sec. 2.2, 3.3): each record's place is the number of smaller keys plus the
-// number of equal keys before it.  Finally every thread gathers its records
-// through the permutation from the job's source (just read, so it is served
-// from cache), the workgroup waits until all of them are in registers, and
-// the job is written back in one coalesced pass.
+// Sec. 3.2, with LDS in the role of the cache).  A job's records are read from
+// HBM once and kept in LDS in input order; every pass permutes a 16-bit slot
+// array instead of moving records.  The first pass splits the job on up to
+// kMidFirstBits of the highest bits in which its keys differ.  Sub-ranges
+// still larger than tiny_max get further passes, by the whole workgroup when
+// they exceed one wave's capacity, else by single waves in parallel, round by
+// round.  Ranges of at most tiny_max records are finished by enumeration sort
+// (Sec. 2.2, 3.3): each record's place is the number of (key, slot) pairs
+// below its own.  The job is written out in order, each thread gathering its
+// records from LDS through the permutation, in coalesced stores.
+//
+// Jobs are pipelined so that no wave waits for HBM in the middle of a job:
+// workgroups claim jobs from a shared counter (after a first one of their
+// own), so that faster CUs take more of them.  While job i is sorted, the
+// records of job i+1 travel into registers (they are loaded before job i's
+// stores are issued, so waiting for them never waits for those stores), the
+// descriptor of job i+2 is on its way and the claim for job i+3 is made.
 template <int RW, int KW>
-__global__ void __launch_bounds__(kMidBlock, 4) k_mid(Params P) {
+__global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
   constexpr int W = kMidWaves;
   constexpr int WI = mid_wave_items(RW);
+  constexpr int ITEMS = mid_items(RW, KW);
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ uint32_t s_big[kMidBigCap];
   __shared__ uint32_t s_list[2][kMidListCap];
-  __shared__ uint32_t s_nbig, s_nlist[2], s_claim;
-  __shared__ uint32_t s_tot[kRadix], s_off[kRadix], s_scan[8];
-  __shared__ unsigned long long s_diff[W * KW];
+  __shared__ uint32_t s_nbig, s_nlist[2], s_claim, s_next, s_next2;
+  __shared__ uint32_t s_scan[W];
+  __shared__ unsigned long long s_diff[W * (KW + 1)];
 
   const uint32_t T = P.mid_max;
   MidLds L;
   L.key = reinterpret_cast<uint64_t*>(smem);
-  L.perm = reinterpret_cast<uint16_t*>(L.key + uint64_t(T) * KW);
-  L.cnt = L.perm + align_up(T, 2);
-  L.bm = reinterpret_cast<uint32_t*>(L.cnt + W * kRadix);
+  L.kstride = RW;
+  L.kmask = P.kmask;
+  L.perm = reinterpret_cast<uint16_t*>(L.key + uint64_t(T) * RW);
+  L.cnt = reinterpret_cast<uint32_t*>(L.perm + align_up(T, 2));
+  L.bm = L.cnt + kMidCounterWords;
+  L.bmb = L.bm + (T >> 5) + 2;
   L.big = s_big;
   L.list0 = s_list[0];
   L.list1 = s_list[1];
   L.nbig = &s_nbig;
   L.nlist = s_nlist;
   L.claim = &s_claim;
-  L.tot = s_tot;
-  L.off = s_off;
   L.scan = s_scan;
   L.diff = s_diff;
 
   Ctrl* c = P.L.ctrl;
   const uint32_t njobs = min(c->mid_count, P.L.cap_mid);
-  const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t tiny = P.tiny_max;
   const uint32_t wave_cap = kWave * WI;
+  const uint32_t G = gridDim.x;
+  if (blockIdx.x >= njobs) return;
 
-  for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
-    const Bin job = P.L.mid[jb];
-    const uint32_t m = job.size;
-    if (m > T) {
-      if (tid == 0) atomicOr(&c->error, kErrMidSize);
-      continue;
-    }
-    const ArrayDesc arr = P.L.arrays[job.array];
-    const uint64_t* sw = reinterpret_cast<const uint64_t*>(job.side ? arr.tmp : arr.recs) +
-                         uint64_t(job.start) * RW;
-    uint64_t* dw = reinterpret_cast<uint64_t*>(arr.recs) + uint64_t(job.start) * RW;
+  MidJob job = P.L.mid[blockIdx.x];  // job i
+  uint64_t kr[ITEMS][RW], key0[KW];
+  mid_fetch<RW, KW, ITEMS>(job.src, job.size <= T ? job.size : 0u, threadIdx.x, kr, key0);
+  if (threadIdx.x == 0) {
+    s_next = G + atomicAdd(&c->mid_claim, 1u);
+    s_next2 = G + atomicAdd(&c->mid_claim, 1u);
+  }
+  __syncthreads();
+  bool have1 = s_next < njobs;  // job i+1 exists
+  uint32_t idx2 = s_next2;      // index of job i+2
+  MidJob nxt{};                 // descriptor of job i+1
+  if (have1) nxt = P.L.mid[s_next];
+  // nothing of the set-up stays in flight into the loop, so that no wait is
+  // placed at its head
+  __builtin_amdgcn_s_waitcnt(0);
 
-    // the job's keys, once, from HBM into LDS in input order
-    for (uint32_t i = tid; i < m; i += kMidBlock) {
-      uint64_t k[KW];
-      key_of<KW>(gmem(sw) + uint64_t(i) * RW, P.kmask, k);
+  for (;;) {
+    // the thread index is made opaque per job so that the per-item
+    // addresses derived from it are recomputed instead of held in registers
+    // across the whole loop
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const uint32_t lane = tid & 63, wave = tid >> 6;
+    if (job.size > T && tid == 0) atomicOr(&c->error, kErrMidSize);
+    const uint32_t m = job.size <= T ? job.size : 0u;
+
+    // the records (already in registers) into LDS; the keys' spread against
+    // the first key
+    uint64_t dk[KW];
 #pragma unroll
-      for (int q = 0; q < KW; ++q) L.key[uint64_t(i) * KW + q] = k[q];
+    for (int q = 0; q < KW; ++q) dk[q] = 0;
+    key0[KW - 1] &= P.kmask;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t i = j * kMidBlock + tid;
+      if (i < m) {
+        uint64_t k[KW];
+        key_of<KW>(kr[j], P.kmask, k);
+#pragma unroll
+        for (int q = 0; q < KW; ++q) dk[q] |= k[q] ^ key0[q];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) L.key[uint64_t(i) * RW + q] = kr[j][q];
+      }
     }
-    for (uint32_t q = tid; q < (m >> 5) + 2; q += kMidBlock) L.bm[q] = 0;
+    // into the freed registers the records of job i+1; then the descriptor of
+    // job i+2 and the claim of job i+3, which are read in the middle of this
+    // job, before its stores are issued
+    if (have1) mid_fetch<RW, KW, ITEMS>(nxt.src, nxt.size <= T ? nxt.size : 0u, tid, kr, key0);
+    const bool have2 = have1 && idx2 < njobs;
+    JobV nextv{};
+    uint32_t claimv = 0;
+    if (have2) {
+      nextv = vload_job(P.L.mid + idx2);
+      // (the address is made opaque so that the atomic stays a single lane's
+      // and its result is not waited for here)
+      if (tid == 0) claimv = atomicAdd(&c->mid_claim + vzero(), 1u);
+    }
+    for (uint32_t q = tid; q < (m >> 5) + 2; q += kMidBlock) {
+      L.bm[q] = 0;
+      L.bmb[q] = 0;
+    }
+    for (uint32_t q = tid; q < kMidCounterWords; q += kMidBlock) L.cnt[q] = 0;
     if (tid == 0) {
       s_nbig = 0;
       s_nlist[0] = 0;
       s_nlist[1] = 0;
     }
-    lds_barrier();
-    if (m > tiny) {
-      mid_first_split<RW, KW>(P, L, m, wave_cap);
+    // slots of a job start in input order, so only the keys can differ
+    (void)mid_wg_spread<KW>(L, tid, dk, 0u);
+    bool by_slot;
+    const uint32_t hb = pair_top<KW>(dk, 0u, by_slot);
+    if (m > tiny && hb > 0) {
+      // first pass over the whole job
+      const uint32_t lg = 32u - uint32_t(__clz(m));
+      const uint32_t w = min(min(hb, uint32_t(kMidFirstBits)), lg);
+      const uint32_t lob = hb - w;
+      uint32_t src[ITEMS], dg[ITEMS];
+      bool valid[ITEMS];
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t i = j * kMidBlock + tid;
+        valid[j] = i < m;
+        src[j] = i;
+        dg[j] = 0;
+        if (valid[j]) {
+          uint64_t k[KW];
+          slot_key<KW>(L, i, k);
+          dg[j] = digit_of<KW>(k, lob, w);
+        }
+      }
+      mid_wg_place<ITEMS>(P, L, tid, 0, w, src, dg, valid, wave_cap, true);
+      // buckets of at most tiny_max records are finished here by enumeration
+      // sort (Sec. 2.2, 3.3): each record's place in its bucket is the number
+      // of (key, slot) pairs in the bucket below its own; the bucket bounds
+      // are the digit offsets just computed
+      const uint32_t nd = 1u << w;
+      uint32_t fin[ITEMS];
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        fin[j] = ~0u;
+        if (!valid[j]) continue;
+        const uint32_t b0 = pair_get(L.cnt, dg[j]);
+        const uint32_t b1 = dg[j] + 1 < nd ? pair_get(L.cnt, dg[j] + 1) : m;
+        if (b1 - b0 < 2 || b1 - b0 > tiny) continue;
+        uint64_t kp[KW];
+        slot_key<KW>(L, src[j], kp);
+        uint32_t r = 0;
+        for (uint32_t q = b0; q < b1; ++q) {
+          const uint32_t sq = L.perm[q];
+          uint64_t kq[KW];
+          slot_key<KW>(L, sq, kq);
+          r += (key_lt<KW>(kq, kp) || (sq < src[j] && key_eq<KW>(kq, kp))) ? 1u : 0u;
+        }
+        fin[j] = b0 + r;
+      }
+      lds_barrier();  // every read of perm is done
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j)
+        if (fin[j] != ~0u) L.perm[fin[j]] = uint16_t(src[j]);
+      lds_barrier();
     } else {
+      // one key (already in slot order), or a job small enough for the
+      // enumeration sort below
       for (uint32_t i = tid; i < m; i += kMidBlock) L.perm[i] = uint16_t(i);
       if (tid == 0) L.bm[0] = 1u;
+      if (hb > 0)
+        for (uint32_t q = tid; q < (m + 31) >> 5; q += kMidBlock)
+          L.bmb[q] = q < (m >> 5) ? ~0u : ((1u << (m & 31)) - 1u);
       lds_barrier();
     }
     // ranges too large for one wave
@@ -1351,7 +1580,7 @@ __global__ void __launch_bounds__(kMidBlock, 4) k_mid(Params P) {
       lds_barrier();
       if (tid == 0) s_nbig = nbig - 1;
       lds_barrier();
-      mid_wg_pass<RW, KW>(P, L, e & 0xFFFFu, e >> 16, wave_cap);
+      mid_wg_pass<KW, ITEMS>(P, L, tid, e & 0xFFFFu, e >> 16, wave_cap);
     }
     // medium ranges: one wave each, round by round
     for (uint32_t cur = 0;; cur ^= 1) {
@@ -1368,21 +1597,22 @@ __global__ void __launch_bounds__(kMidBlock, 4) k_mid(Params P) {
         k = __shfl(k, 0);
         if (k >= nl) break;
         const uint32_t e = s_list[cur][k];
-        mid_wave_pass<RW, KW, WI>(P, L, e & 0xFFFFu, e >> 16, cur ^ 1, wave_cap);
+        mid_wave_pass<KW, WI>(P, L, tid, e & 0xFFFFu, e >> 16, cur ^ 1, wave_cap);
       }
       lds_barrier();
       if (tid == 0) s_nlist[cur] = 0;
     }
     lds_barrier();
 
-    // ---- tiny ranges: enumeration sort; everything else stays in place.
-    // A range of at most tiny_max records belongs to the wave that owns the
-    // 64-position window its first position falls in, so each wave reads,
-    // ranks and rewrites only positions no other wave touches.
-    const uint32_t wave = tid >> 6;
+    // ---- tiny ranges the later passes produced (inside positions marked in
+    // bmb): enumeration sort; everything else is in place.  A range belongs
+    // to the wave that owns the 64-position window its first position falls
+    // in, so each wave reads, ranks and rewrites only positions no other wave
+    // touches.
     const uint32_t nwin = (m + kWave - 1) / kWave;
     for (uint32_t k = wave; k < nwin; k += W) {
       const uint32_t w0 = k * kWave;
+      if ((L.bmb[w0 >> 5] | L.bmb[(w0 >> 5) + 1]) == 0) continue;
       uint32_t dst[kMidEsItems], slot[kMidEsItems];
       bool act[kMidEsItems];
 #pragma unroll
@@ -1392,6 +1622,10 @@ __global__ void __launch_bounds__(kMidBlock, 4) k_mid(Params P) {
         dst[h] = p;
         slot[h] = 0;
         if (p >= m || uint32_t(h) * kWave > tiny + kWave) continue;
+        if (!((L.bmb[p >> 5] >> (p & 31)) & 1u)) continue;
+        // a run start here: a range of another window, or a single record
+        const bool st = (L.bm[p >> 5] >> (p & 31)) & 1u;
+        if (st && (h > 0 || p + 1 == m || ((L.bm[(p + 1) >> 5] >> ((p + 1) & 31)) & 1u))) continue;
         const int lo = int(p) > int(tiny) ? int(p - tiny) : 0;
         const int s = bm_prev(L.bm, int(p), lo);
         if (s < int(w0) || s >= int(w0 + kWave)) continue;  // not a range of this window
@@ -1401,16 +1635,18 @@ __global__ void __launch_bounds__(kMidBlock, 4) k_mid(Params P) {
         if (e < 0 || e - s < 2) continue;
         slot[h] = L.perm[p];
         uint64_t kp[KW];
-        slot_key<RW, KW>(P, L, slot[h], kp);
+        slot_key<KW>(L, slot[h], kp);
         uint32_t r = 0;
         for (int q = s; q < e; ++q) {
+          const uint32_t sq = L.perm[q];
           uint64_t kq[KW];
-          slot_key<RW, KW>(P, L, L.perm[q], kq);
-          r += (key_lt<KW>(kq, kp) || (q < int(p) && key_eq<KW>(kq, kp))) ? 1u : 0u;
+          slot_key<KW>(L, sq, kq);
+          r += (key_lt<KW>(kq, kp) || (sq < slot[h] && key_eq<KW>(kq, kp))) ? 1u : 0u;
         }
         dst[h] = uint32_t(s) + r;
         act[h] = true;
       }
+      __builtin_amdgcn_s_waitcnt(0xC07F);
       __builtin_amdgcn_wave_barrier();
       asm volatile("" ::: "memory");
 #pragma unroll
@@ -1418,29 +1654,39 @@ __global__ void __launch_bounds__(kMidBlock, 4) k_mid(Params P) {
         if (act[h]) L.perm[dst[h]] = uint16_t(slot[h]);
     }
     lds_barrier();
-    // gather every record of the job (all loads complete before any store:
-    // source and destination may be the same buffer), then write in order
-    constexpr int WO = mid_items(RW, KW);
-    uint64_t out[WO][RW];
+    // every load issued at the start of this job has landed (all of them,
+    // on every path, so that nothing loaded is still counted as in flight
+    // when the next job starts and this job's stores are out); then the
+    // descriptor of job i+2 and the index of job i+3
+    __builtin_amdgcn_s_waitcnt(0x3F70);  // gfx9 encoding: vmcnt(0), lgkmcnt/expcnt not waited
+    MidJob nxt2{};
+    if (have2) nxt2 = uni_job(nextv);
+    if (tid == 0) s_next = have2 ? G + claimv : njobs;
+    lds_barrier();
+    const uint32_t idx3 = s_next;
+    // the job in order: each thread gathers records from LDS through the
+    // permutation and stores them coalesced
 #pragma unroll
-    for (int u = 0; u < WO; ++u) {
-      const uint32_t p = tid + u * kMidBlock;
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t p = j * kMidBlock + tid;
       if (p < m) {
         uint32_t sl = L.perm[p];
         if (sl >= m) {  // never taken while the passes above keep perm a permutation
           atomicOr(&c->error, kErrBounds);
           sl = 0;
         }
-        load_rec<RW>(reinterpret_cast<const uint8_t*>(sw), sl, out[u]);
+        uint64_t r[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) r[q] = L.key[uint64_t(sl) * RW + q];
+        store_rec<RW>(reinterpret_cast<uint8_t*>(job.dst), p, r, false);
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < WO; ++u) {
-      const uint32_t p = tid + u * kMidBlock;
-      if (p < m) store_rec<RW>(reinterpret_cast<uint8_t*>(dw), p, out[u], false);
-    }
-    lds_barrier();
+    lds_barrier();  // the records are rewritten by the next job
+    if (!have1) break;
+    job = nxt;
+    nxt = nxt2;
+    have1 = have2;
+    idx2 = idx3;
   }
 }
 

@@ -102,7 +102,7 @@ Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const
   s.off_tail = take(uint64_t(s.cap_ranges) * kRadix * 4);
   s.off_carry = take(uint64_t(s.cap_ranges) * kRadix * 4);
   s.off_flag = take(uint64_t(s.cap_ranges) * 4);
-  s.off_mid = take(uint64_t(s.cap_mid) * sizeof(Bin));
+  s.off_mid = take(uint64_t(s.cap_mid) * sizeof(MidJob));
   s.off_copy = take(uint64_t(s.cap_copy) * sizeof(Bin));
   s.bytes = o;
   return s;
@@ -124,7 +124,7 @@ Layout make_layout(uint8_t* aux, const Shape& s) {
   L.wg_carry = reinterpret_cast<uint32_t*>(aux + s.off_carry);
   L.wg_flag = reinterpret_cast<uint32_t*>(aux + s.off_flag);
   L.cap_ranges = s.cap_ranges;
-  L.mid = reinterpret_cast<Bin*>(aux + s.off_mid);
+  L.mid = reinterpret_cast<MidJob*>(aux + s.off_mid);
   L.copy = reinterpret_cast<Bin*>(aux + s.off_copy);
   L.cap_large = s.cap_large;
   L.cap_tiles = s.cap_tiles;
@@ -203,9 +203,8 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
                                  : std::max<uint32_t>(1, std::min<uint32_t>(s.cap_tiles, 2 * cus));
   P.grid_classify = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_large, 4 * cus));
   P.scatter_lds_bytes = scatter_lds_bytes(int(R / 8));
-  P.mid_lds_bytes = mid_dynamic_lds(e.mid_max, int((K + 7) / 8));
-  const uint32_t per_cu = (P.mid_lds_bytes + kMidStaticLds) * 2 <= kLdsBytes ? 2 : 1;
-  P.grid_mid = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_mid, per_cu * cus));
+  P.mid_lds_bytes = mid_dynamic_lds(e.mid_max, int(R / 8));
+  P.grid_mid = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_mid, cus));
   P.grid_copy = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_copy, 2 * cus));
 }
 

@@ -96,9 +96,9 @@ def test_size_queries():
     for r in range(8, 72, 8):
         for k in sorted({1, 8, min(16, r), r}):
             cap = b.raduls_mid_capacity(r, k)
-            kw = (k + 7) // 8
-            # keys and a 16-bit permutation of a job fit one of two LDS shares
-            assert cap >= 512 and cap % 64 == 0 and cap * (8 * kw + 2) <= 80 * 1024
+            # the records and a 16-bit permutation of a job fit a CU's 160 KiB
+            # of LDS
+            assert cap >= 512 and cap % 64 == 0 and cap * (r + 2) <= 160 * 1024
     assert b.raduls_mid_capacity(12, 8) == 0
     assert b.raduls_mid_capacity(16, 17) == 0
 

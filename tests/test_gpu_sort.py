@@ -112,3 +112,17 @@ def test_deterministic_reruns():
     for _ in range(2):
         c, _ = gpu_sort(inp, 8)
         assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("block", [1, 63, 64, 65, 200])
+@pytest.mark.parametrize("n", [128, 1000, 5000])
+def test_runs_of_equal_keys_across_waves(block, n):
+    """Runs of one key that line up with (or straddle) the 64-lane waves of
+    the LDS sorter: every wave may see a single key while the job does not."""
+    r, k = 16, 8
+    rng = np.random.default_rng(block * 7919 + n)
+    inp = wl.random_records(rng, n, r, k)
+    run_keys = rng.integers(0, 256, size=((n + block - 1) // block, k), dtype=np.uint8)
+    inp[:, :k] = np.repeat(run_keys, block, axis=0)[:n]
+    out, _ = gpu_sort(inp, k)
+    _assert_parity(out, inp, k)
