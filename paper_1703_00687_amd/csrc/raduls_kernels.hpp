@@ -566,22 +566,70 @@ __global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) 
 
 // Carry of every histogram range: the per-digit count of records of the
 // range's first bin that lie in earlier ranges (the blocked form of the
-// exclusive scan over tiles).  One workgroup, one thread per digit.
-static __global__ void __launch_bounds__(256) k_carry(Params P, uint32_t nranges) {
+// exclusive scan over tiles).  After range h the running count R is the
+// range's own tail when h starts a bin or spans more than one bin, else the
+// previous R plus that tail; a range that starts a bin carries 0, any other
+// carries the R of the range before it.  That is a segmented scan over the
+// ranges, done in parallel: one workgroup per digit, kMaxRanges / 1024 ranges
+// per thread.
+static __global__ void __launch_bounds__(1024) k_carry(Params P, uint32_t nranges) {
+  constexpr uint32_t kPer = kMaxRanges / 1024;
+  __shared__ uint32_t s_sum[16], s_flag[16];
   const Ctrl* c = P.L.ctrl;
   const uint32_t total = c->round_tiles;
   if (total == 0) return;
-  const uint32_t d = threadIdx.x;
-  uint32_t carry = 0, tail = 0, single = 0;
-  for (uint32_t g = 0; g < nranges; ++g) {
-    const uint32_t t0 = uint32_t(uint64_t(total) * g / nranges);
-    const uint32_t t1 = uint32_t(uint64_t(total) * (g + 1) / nranges);
-    if (t0 >= t1) continue;
-    const uint32_t f = P.L.wg_flag[g];
-    carry = (f & 1u) ? 0u : tail + (single ? carry : 0u);
-    P.L.wg_carry[uint64_t(g) * kRadix + d] = carry;
-    tail = P.L.wg_tail[uint64_t(g) * kRadix + d];
-    single = f & 2u;
+  const uint32_t d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t per = (nranges + 1023) / 1024;
+  uint32_t tail[kPer];
+  bool start[kPer], head[kPer], live[kPer];
+  uint32_t run = 0;
+  bool any = false;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t g = tid * per + k;
+    live[k] = false;
+    tail[k] = 0;
+    start[k] = head[k] = false;
+    if (k < per && g < nranges) {
+      const uint32_t t0 = uint32_t(uint64_t(total) * g / nranges);
+      const uint32_t t1 = uint32_t(uint64_t(total) * (g + 1) / nranges);
+      if (t0 < t1) {  // empty ranges pass the running count through
+        const uint32_t f = P.L.wg_flag[g];
+        live[k] = true;
+        tail[k] = P.L.wg_tail[uint64_t(g) * kRadix + d];
+        start[k] = f & 1u;
+        head[k] = start[k] || !(f & 2u);
+      }
+    }
+    run = head[k] ? tail[k] : run + tail[k];
+    any = any || head[k];
+  }
+  // exclusive segmented scan of (any, run) over the threads
+  uint32_t s = run, f = any;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t s2 = __shfl_up(s, o), f2 = __shfl_up(f, o);
+    if (lane >= uint32_t(o)) {
+      s = f ? s : s2 + s;
+      f = f | f2;
+    }
+  }
+  if (lane == 63) {
+    s_sum[wave] = s;
+    s_flag[wave] = f;
+  }
+  uint32_t es = __shfl_up(s, 1), ef = __shfl_up(f, 1);
+  if (lane == 0) es = ef = 0;
+  __syncthreads();
+  uint32_t ps = 0;  // R after everything before this wave
+  for (uint32_t w = 0; w < wave; ++w) ps = s_flag[w] ? s_sum[w] : ps + s_sum[w];
+  uint32_t r = ef ? es : ps + es;  // R before this thread's first range
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    if (!live[k]) continue;
+    const uint32_t g = tid * per + k;
+    P.L.wg_carry[uint64_t(g) * kRadix + d] = start[k] ? 0u : r;
+    r = head[k] ? tail[k] : r + tail[k];
   }
 }
 
@@ -921,6 +969,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
 template <int KW>
 __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
   __shared__ uint32_t s_cnt[kRadix], s_off[kRadix], s_scan[8];
+  __shared__ uint32_t s_js[kRadix], s_jn[kRadix], s_nj, s_jbase;
   Ctrl* c = P.L.ctrl;
   const uint32_t nbins = min(c->large_count[cur], P.L.cap_large);
   const uint32_t nxt = cur ^ 1;
@@ -969,21 +1018,18 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
       ch.flags = 0;
       push_large(P, nxt, ch);
     }
+    // greedy packing of the small children into jobs (one thread; cheap
+    // arithmetic on LDS), then one reservation in the job list and a
+    // parallel write of the descriptors
     if (tid == 0) {
-      uint32_t js = 0, jn = 0, jc = 0;
+      uint32_t js = 0, jn = 0, nj = 0;
       auto flush = [&]() {
-        if (jn > 0 && !(jn == 1 && cside == 0)) {
-          Bin j;
-          j.start = bin.start + js;
-          j.size = jn;
-          j.array = bin.array;
-          j.bits = uint16_t(jc == 1 ? lob : bin.bits);
-          j.side = cside;
-          j.flags = uint8_t(jc > 1);
-          push_mid(P, j, P.L.arrays[bin.array]);
+        if (jn > 0 && !(jn == 1 && cside == 0)) {  // a lone record in recs is in place
+          s_js[nj] = js;
+          s_jn[nj] = jn;
+          ++nj;
         }
         jn = 0;
-        jc = 0;
       };
       for (uint32_t d = 0; d < nb; ++d) {
         const uint32_t cd = s_cnt[d];
@@ -995,9 +1041,26 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
         if (jn + cd > P.mid_max) flush();
         if (jn == 0) js = s_off[d];
         jn += cd;
-        ++jc;
       }
       flush();
+      s_nj = nj;
+      s_jbase = nj ? atomicAdd(&c->mid_count, nj) : 0u;
+    }
+    __syncthreads();
+    if (tid < s_nj) {
+      const uint32_t i = s_jbase + tid;
+      if (i < P.L.cap_mid) {
+        const ArrayDesc a = P.L.arrays[bin.array];
+        const uint64_t st = uint64_t(bin.start) + s_js[tid];
+        MidJob j;
+        j.src = (cside ? a.tmp : a.recs) + st * P.R;
+        j.dst = a.recs + st * P.R;
+        j.size = s_jn[tid];
+        j.pad[0] = j.pad[1] = j.pad[2] = 0;
+        P.L.mid[i] = j;
+      } else {
+        atomicOr(&c->error, kErrCapacity);
+      }
     }
   }
 }
@@ -1761,7 +1824,7 @@ inline void launch_scatter(const Params& P, uint32_t cur, hipStream_t s) {
   if (P.lookback) {
     k_scatter<RW, KW, TOP, 1><<<P.grid_scatter, kScatterBlock, P.scatter_lds_bytes, s>>>(P, cur);
   } else {
-    k_carry<<<1, 256, 0, s>>>(P, P.grid_hist);
+    k_carry<<<kRadix, 1024, 0, s>>>(P, P.grid_hist);
     k_scatter_carry<RW, KW, TOP><<<P.grid_hist, kScatterBlock, P.scatter_lds_bytes, s>>>(P, cur);
   }
 }
