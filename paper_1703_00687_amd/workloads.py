@@ -264,3 +264,49 @@ def batch_array_torch(j: int, size: int, offset: int, seed: int = 5, device="cud
         w[:, 0] = splitmix64_torch(stream_seed(seed, 1), offset, size, device)
         w[:, 1] = torch.arange(size, dtype=torch.int64, device=device)
     return w.view(torch.uint8).view(size, 16)
+
+
+def _u64_lt(a, b):
+    """a < b for int64 tensors holding uint64 bit patterns."""
+    sign = -(1 << 63)
+    return (a ^ sign) < (b ^ sign)
+
+
+def zipf16_torch(n: int, seed: int = 3, values: int = ZIPF_VALUES, s: float = ZIPF_S,
+                 override: float = ZIPF_OVERRIDE, device="cuda", chunk: int = 1 << 25):
+    """zipf16 built on the device (the dictionary and CDF on the host, the
+    draws on the device): returns an [n, 16] uint8 tensor equal to zipf16."""
+    import torch
+    d, special = zipf_dictionary(seed, values)
+    dd = torch.from_numpy(d.view(np.int64)).to(device)
+    cdf = torch.from_numpy(zipf_cdf(values, s)).to(device)
+    thresh = _s64(min(int(override * 2.0 ** 64), MASK64))
+    out = torch.empty((n, 2), dtype=torch.int64, device=device)
+    st_u, st_o = stream_seed(seed, 1), stream_seed(seed, 2)
+    for a in range(0, n, chunk):
+        c = min(chunk, n - a)
+        z = splitmix64_torch(st_u, a, c, device)
+        u = ((z >> 11) & ((1 << 53) - 1)).to(torch.float64) * (1.0 / (1 << 53))
+        rank = torch.searchsorted(cdf, u, right=True).clamp_(max=values - 1)
+        key = dd[rank]
+        hit = _u64_lt(splitmix64_torch(st_o, a, c, device), torch.tensor(thresh, device=device))
+        key[hit] = _s64(special)
+        out[a:a + c, 0] = key
+        out[a:a + c, 1] = torch.arange(a, a + c, dtype=torch.int64, device=device)
+    return out.view(torch.uint8).view(n, 16)
+
+
+def deep32_torch(n: int, seed: int = 4, hi_values: int = DEEP_HI_VALUES, device="cuda",
+                 chunk: int = 1 << 25):
+    """deep32 built on the device: returns an [n, 32] uint8 tensor equal to
+    deep32 (hi_values must be a power of two)."""
+    import torch
+    assert hi_values & (hi_values - 1) == 0
+    out = torch.empty((n, 4), dtype=torch.int64, device=device)
+    for a in range(0, n, chunk):
+        c = min(chunk, n - a)
+        out[a:a + c, 0] = splitmix64_torch(stream_seed(seed, 1), a, c, device)
+        out[a:a + c, 1] = splitmix64_torch(stream_seed(seed, 0), a, c, device) & (hi_values - 1)
+        out[a:a + c, 2] = torch.arange(a, a + c, dtype=torch.int64, device=device)
+        out[a:a + c, 3] = splitmix64_torch(stream_seed(seed, 2), a, c, device)
+    return out.view(torch.uint8).view(n, 32)

@@ -1,0 +1,220 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (default tuning, one call per array, or one batched call).
+
+The oracle cannot sort 2^28 records within a test, so every full-size output
+is checked two ways:
+
+* on the device, by properties that pin the stable sort uniquely when each
+  record carries its input index: the keys never decrease, the indices are a
+  permutation, every output record equals the input record its index names,
+  and records with equal keys keep increasing indices;
+* against the oracle on samples: windows of the output, each compared
+  element by element with the oracle's sort of exactly the input records
+  whose keys fall strictly inside the window's key range.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1703_00687_amd import binding as b
+from paper_1703_00687_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+SIGN = -(1 << 63)
+
+
+def _u(x):
+    """uint64 bit patterns in int64 tensors -> order-preserving int64."""
+    return x ^ SIGN
+
+
+def _key_cmp(kw_out):
+    """(nondecreasing, equal) masks between neighbours for a multi-word key
+    given as a list of int64 columns, least significant first."""
+    le = torch.ones_like(kw_out[0][1:], dtype=torch.bool)
+    eq = torch.ones_like(le)
+    for col in kw_out:  # least significant first: the later words decide
+        a, c = _u(col[:-1]), _u(col[1:])
+        le = (c > a) | ((c == a) & le)
+        eq = eq & (c == a)
+    return le, eq
+
+
+def check_stable_device(out, inp, words, key_words, index_word, seg_start=None, seg_of=None):
+    """Property check of a stable sort on the device.  out, inp: [n, 8*words]
+    uint8.  seg_start / seg_of: for many arrays back to back, the start of
+    each array and the array of each position (indices are array-relative)."""
+    n = out.shape[0]
+    w = out.view(torch.int64).view(n, words)
+    wi = inp.view(torch.int64).view(n, words)
+    keys = [w[:, q] for q in range(key_words)]
+    le, eq = _key_cmp(keys)
+    idx = w[:, index_word]
+    if seg_of is not None:
+        same = seg_of[1:] == seg_of[:-1]
+        le = le | ~same
+        eq = eq & same
+        gidx = seg_start[seg_of] + idx
+        size = torch.diff(torch.cat([seg_start, torch.tensor([n], device=out.device)]))
+        in_range = (idx >= 0) & (idx < size[seg_of])
+    else:
+        gidx = idx
+        in_range = (idx >= 0) & (idx < n)
+    assert bool(le.all()), "keys decrease somewhere"
+    assert bool(in_range.all()), "an index is out of range"
+    seen = torch.zeros(n, dtype=torch.bool, device=out.device)
+    seen[gidx] = True
+    assert bool(seen.all()), "indices are not a permutation"
+    assert bool((wi[gidx] == w).all()), "a record differs from the input record its index names"
+    assert bool((idx[1:][eq] > idx[:-1][eq]).all()), "equal keys out of input order"
+
+
+def sample_windows(out, inp, words, key_words, k, count=3, span=1 << 18, seed=0):
+    """Compare output windows with the oracle's sort of the input records
+    whose keys lie strictly between the window's first and last keys."""
+    n = out.shape[0]
+    w = out.view(torch.int64).view(n, words)
+    wi = inp.view(torch.int64).view(n, words)
+    rng = np.random.default_rng(seed)
+    done = 0
+    for _ in range(8 * count):
+        if done == count:
+            break
+        p0 = int(rng.integers(0, max(1, n - span)))
+        p1 = min(n - 1, p0 + span)
+        lo = [w[p0, q] for q in range(key_words)]
+        hi = [w[p1, q] for q in range(key_words)]
+
+        def gt(cols, ref):  # key > ref (multi-word, unsigned)
+            res = torch.zeros_like(cols[0], dtype=torch.bool)
+            eqs = torch.ones_like(res)
+            for q in reversed(range(key_words)):
+                a, r = _u(cols[q]), _u(ref[q])
+                res = res | (eqs & (a > r))
+                eqs = eqs & (a == r)
+            return res
+
+        def lt(cols, ref):
+            res = torch.zeros_like(cols[0], dtype=torch.bool)
+            eqs = torch.ones_like(res)
+            for q in reversed(range(key_words)):
+                a, r = _u(cols[q]), _u(ref[q])
+                res = res | (eqs & (a < r))
+                eqs = eqs & (a == r)
+            return res
+
+        icols = [wi[:, q] for q in range(key_words)]
+        sel = gt(icols, lo) & lt(icols, hi)
+        m = int(sel.sum())
+        if m == 0 or m > (1 << 22):
+            continue  # an empty interior, or one dominated by a heavy key
+        ocols = [w[:, q] for q in range(key_words)]
+        osel = gt(ocols, lo) & lt(ocols, hi)
+        pos = torch.nonzero(osel).flatten()
+        assert int(pos.numel()) == m
+        assert int(pos[-1] - pos[0]) + 1 == m, "window records are not contiguous"
+        expect = oracle.sort(inp[sel].cpu().numpy(), k)
+        got = out[int(pos[0]):int(pos[0]) + m].cpu().numpy()
+        assert np.array_equal(got, expect), f"window at {p0} differs from the oracle"
+        done += 1
+    assert done > 0, "no window could be sampled"
+
+
+def _sort_full(inp, key_bytes):
+    n, r = inp.shape
+    out = inp.clone()
+    tmp = torch.empty(b.raduls_tmp_bytes(n, r, key_bytes), dtype=torch.uint8, device=inp.device)
+    b.raduls_sort(out, tmp, n, r, key_bytes)
+    st, stats = b.raduls_check(tmp, n, r, False)
+    assert st == b.OK, stats
+    del tmp
+    return out, stats
+
+
+def test_uniform16_full():
+    n = 1 << 28
+    inp = wl.uniform16_torch(n)
+    out, stats = _sort_full(inp, 8)
+    assert stats["rounds"] >= 2
+    check_stable_device(out, inp, 2, 1, 1)
+    sample_windows(out, inp, 2, 1, 8)
+
+
+def test_zipf16_full():
+    n = 1 << 28
+    inp = wl.zipf16_torch(n)
+    out, _ = _sort_full(inp, 8)
+    check_stable_device(out, inp, 2, 1, 1)
+    sample_windows(out, inp, 2, 1, 8, seed=1)
+
+
+def test_deep32_full():
+    n = 1 << 27
+    inp = wl.deep32_torch(n)
+    out, stats = _sort_full(inp, 16)
+    assert stats["rounds"] >= 3  # the high key word forces deep recursion
+    check_stable_device(out, inp, 4, 2, 2)
+    sample_windows(out, inp, 4, 2, 16, seed=2)
+
+
+def test_batch_full():
+    """The batched workload at full size: 65536 arrays, sizes log-uniform in
+    [1, 2^20] (about 5e9 records), one batched call.  Every array is checked
+    on the device, group by group against its regenerated input; a sample of
+    arrays is compared with the oracle."""
+    count, r, k = 65536, 16, 8
+    sizes = wl.batch_sizes(count, max_log2=20).astype(np.int64)
+    starts = np.zeros(count, dtype=np.int64)
+    starts[1:] = np.cumsum(sizes)[:-1]
+    total = int(sizes.sum())
+    dev = torch.device("cuda:0")
+    stream = wl.stream_seed(5, 1)
+
+    def generate(a0, a1, arr0, arr1, into):
+        """Input records [a0, a1) (arrays arr0..arr1-1) into `into`."""
+        w = into.view(torch.int64).view(a1 - a0, 2)
+        loc = torch.from_numpy(starts[arr0:arr1] - a0).to(dev)
+        chunk = 1 << 26
+        for c0 in range(0, a1 - a0, chunk):
+            c = min(chunk, a1 - a0 - c0)
+            w[c0:c0 + c, 0] = wl.splitmix64_torch(stream, a0 + c0, c, dev)
+            g = torch.arange(c0, c0 + c, dtype=torch.int64, device=dev)
+            w[c0:c0 + c, 1] = g - loc[torch.searchsorted(loc, g, right=True) - 1]
+        return loc
+
+    out = torch.empty((total, r), dtype=torch.uint8, device=dev)
+    generate(0, total, 0, count, out)
+    tmp = torch.empty((total + 64, r), dtype=torch.uint8, device=dev)
+    bt = b.Batch(count, total, r, k, device=dev)
+    h = bt.host_desc.numpy()
+    h[:, 0] = out.data_ptr() + starts * r
+    h[:, 1] = tmp.data_ptr() + starts * r
+    h[:, 2] = sizes
+    bt.desc.copy_(bt.host_desc)
+    bt.launch()
+    stt, stats = bt.check()
+    assert stt == b.OK, stats
+    del tmp, bt
+    torch.cuda.empty_cache()
+    # groups of whole arrays, about 2^26 records each
+    ends = starts + sizes
+    arr0 = 0
+    while arr0 < count:
+        arr1 = int(np.searchsorted(ends, starts[arr0] + (1 << 26), side="right"))
+        arr1 = max(arr1, arr0 + 1)
+        a0, a1 = int(starts[arr0]), int(ends[arr1 - 1])
+        if a1 > a0:
+            inp = torch.empty((a1 - a0, r), dtype=torch.uint8, device=dev)
+            loc = generate(a0, a1, arr0, arr1, inp)
+            seg_of = torch.searchsorted(loc, torch.arange(a1 - a0, device=dev), right=True) - 1
+            check_stable_device(out[a0:a1], inp, 2, 1, 1, seg_start=loc, seg_of=seg_of)
+            del inp, seg_of
+        arr0 = arr1
+    rng = np.random.default_rng(3)
+    for j in rng.choice(count, size=64, replace=False):
+        a, s = int(starts[j]), int(sizes[j])
+        expect = oracle.sort(wl.batch_array(int(j), s, a), k)
+        assert np.array_equal(out[a:a + s].cpu().numpy(), expect), f"array {j}"
