@@ -14,13 +14,13 @@ constexpr int kRadixBitsMax = 8;
 constexpr int kRadix = 1 << kRadixBitsMax;  // buckets per digit (upper bound)
 constexpr int kWave = 64;                   // CDNA wavefront width
 
-// Scatter / histogram workgroups: 8 waves.  Records per thread per tile are
-// chosen per record width so that one tile stages about 64 KiB in LDS and two
-// tiles fit in a CU's 160 KiB.
-constexpr int kScatterBlock = 512;
+// Scatter / histogram workgroups: 16 waves, one per CU.  Records per thread
+// per tile are chosen per record width so that a tile stages up to about
+// 150 KiB in LDS: big tiles give every digit long runs per tile.
+constexpr int kScatterBlock = 1024;
 constexpr int kScatterWaves = kScatterBlock / kWave;
 __host__ __device__ constexpr int scatter_items(int rw) {
-  return rw == 1 ? 15 : rw == 2 ? 8 : rw == 3 ? 5 : rw == 4 ? 4 : rw == 5 ? 3 : 2;
+  return rw == 1 ? 10 : rw == 2 ? 8 : rw == 3 ? 5 : rw == 4 ? 4 : rw == 5 ? 3 : 2;
 }
 // Dynamic LDS of one scatter workgroup: staged records, their digits,
 // per-wave counters, three 256-entry tables and the per-digit global bases.
