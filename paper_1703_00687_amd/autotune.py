@@ -82,6 +82,42 @@ def _time_sort(src, copies, tmp, n, R, K, reps):
     return times[len(times) // 2]
 
 
+def _looks_sorted(out, src, key_bytes: int) -> bool:
+    """Keys non-decreasing (keys up to 16 bytes) and the same records in
+    total (two wrapping sums of every 64-bit word, one of them weighted by a
+    function of the whole record)."""
+    import torch
+    n, R = int(out.shape[0]), int(out.shape[1])
+    if n < 2:
+        return True
+    w = out.view(torch.int64).view(n, R // 8)
+    ws = src.view(torch.int64).view(n, R // 8)
+
+    def digest(x):
+        h = x.sum(1) * -7046029254386353131 + x[:, 0]  # per record, wrapping
+        return x.sum(0), (h * (h | 1)).sum()
+
+    (a0, a1), (b0, b1) = digest(w), digest(ws)
+    if not (bool((a0 == b0).all()) and bool(a1 == b1)):
+        return False
+    if key_bytes > 16:
+        return True
+    sign = -(1 << 63)
+    kw = (key_bytes + 7) // 8
+    cols = []
+    for q in range(kw):
+        col = w[:, q]
+        bytes_here = min(8, key_bytes - 8 * q)
+        if bytes_here < 8:
+            col = col & ((1 << (8 * bytes_here)) - 1)
+        cols.append(col ^ sign)
+    le = torch.ones(n - 1, dtype=torch.bool, device=out.device)
+    for col in cols:  # least significant word first
+        a, c = col[:-1], col[1:]
+        le = (c > a) | ((c == a) & le)
+    return bool(le.all())
+
+
 def tune(src, key_bytes: int, reps: int = 3, space: dict | None = None, budget_s: float = 300.0,
          path: str | None = DEFAULT_CACHE, log=print) -> dict:
     """Search the space for the [n, R] uint8 device tensor `src` (left
@@ -127,13 +163,17 @@ def tune(src, key_bytes: int, reps: int = 3, space: dict | None = None, budget_s
                     best_ms, cur, improved = ms, c, True
     best = {"tuning": cand_to_tuning(cur), "ms": best_ms, "n": n,
             "records_per_s": n / (best_ms * 1e-3)}
-    # verify the winner sorts correctly (stable sort properties on keys only)
+    # the winner must sort: no device error, keys non-decreasing and the
+    # record words' sum and xor unchanged
     b.raduls_set_tuning(**best["tuning"])
     out = copies[0]
     out.copy_(src)
     tmp = torch.empty(b.raduls_tmp_bytes(n, R, key_bytes), dtype=torch.uint8, device=src.device)
     b.raduls_sort(out, tmp, n, R, key_bytes)
-    torch.cuda.synchronize()
+    st, stats = b.raduls_check(tmp, n, R, False)
+    if st != b.OK or not _looks_sorted(out, src, key_bytes):
+        b.raduls_set_tuning(**prev)
+        raise RuntimeError(f"autotune: the winning setting {best['tuning']} did not sort ({stats})")
     if path:
         cache = load_cache(path)
         cache[shape_key(_arch(), R, key_bytes, n)] = best

@@ -940,13 +940,23 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
     const bool same = next < r1 && P.L.tile_bin[next] == b;
     if (active && same) issue_loads(next);  // registers are free once staged
     if (active) {
+      // unrolled in groups of four so that the LDS reads of a group are in
+      // flight at once
       bool oob = false;
-      for (uint32_t p = tid; p < tn; p += kScatterBlock) {
-        const uint32_t d = s_dig[p];
-        const uint64_t at = s_gbase[d] + p;
-        // never write outside the bin, whatever the counts say
-        if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_rec + uint64_t(p) * RW, nt);
-        else oob = true;
+#pragma unroll 1
+      for (int j0 = 0; j0 < ITEMS; j0 += 4)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = j0 + jj;
+        const uint32_t p = j * kScatterBlock + tid;
+        if (j >= ITEMS) continue;
+        if (p < tn) {
+          const uint32_t d = s_dig[p];
+          const uint64_t at = s_gbase[d] + p;
+          // never write outside the bin, whatever the counts say
+          if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_rec + uint64_t(p) * RW, nt);
+          else oob = true;
+        }
       }
       if (oob) atomicOr(&c->error, kErrBounds);
     }
