@@ -839,6 +839,16 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
   uint32_t* s_off = s_tot + kRadix;
   uint32_t* s_binoff = s_off + kRadix;
   uint64_t* s_gbase = reinterpret_cast<uint64_t*>(s_binoff + kRadix);
+  // line buffers: per digit up to one line of records not yet stored, the
+  // limit below which a tile's records are stored now, where the buffer's
+  // records start (new and old) and how many old ones are stored now
+  constexpr bool LINES = scatter_lines(RW);
+  constexpr uint32_t LREC = 16u / RW;  // records per 128-byte line
+  uint64_t* s_line = s_gbase + kRadix;
+  uint64_t* s_lim = s_line + (LINES ? kRadix * 16 : 0);
+  uint64_t* s_ncst = s_lim + kRadix;
+  uint64_t* s_ocst = s_ncst + kRadix;
+  uint32_t* s_fl = reinterpret_cast<uint32_t*>(s_ocst + kRadix);
   __shared__ uint32_t s_scan[8];
 
   Ctrl* c = P.L.ctrl;
@@ -849,6 +859,9 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const bool nt = P.nontemporal != 2;
   uint32_t running = tid < kRadix ? P.L.wg_carry[uint64_t(blockIdx.x) * kRadix + tid] : 0;
+  uint64_t lcst = 0;   // thread d: global index of the first buffered record of digit d
+  uint32_t lcnt = 0;   // thread d: buffered records of digit d
+  bool lines_on = false;  // the destination's lines align with records
 
   // state of the bin the current tile belongs to (uniform)
   uint32_t b = 0, w = 0, lob = 0, nb = 0;
@@ -862,6 +875,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
     const ArrayDesc arr = P.L.arrays[bin.array];
     src = bin.side ? arr.tmp : arr.recs;
     dst = bin.side ? arr.recs : arr.tmp;
+    lines_on = LINES && (reinterpret_cast<uintptr_t>(dst) & 127u) == 0;
     w = min(P.digit_bits, uint32_t(bin.bits));
     lob = bin.bits - w;
     nb = 1u << w;
@@ -922,8 +936,28 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
       lds_barrier();
       block_digit_scan<W>(s_cnt, s_tot, s_off, s_scan);
       if (tid < nb) {
-        s_gbase[tid] = uint64_t(bin.start) + s_binoff[tid] + running - s_off[tid];
+        const uint64_t g0 = uint64_t(bin.start) + s_binoff[tid] + running;  // first record of d
+        s_gbase[tid] = g0 - s_off[tid];
         running += s_tot[tid];
+        if (LINES && lines_on) {
+          // whole lines of [buffered records, this tile's records) are
+          // stored now; the tail (less than a line) stays buffered
+          const uint64_t A = lcnt ? lcst : g0, E = g0 + s_tot[tid];
+          const uint64_t Eal = E & ~uint64_t(LREC - 1);
+          if (Eal > A) {
+            s_lim[tid] = Eal;
+            s_fl[tid] = lcnt;
+            s_ocst[tid] = lcst;
+            lcst = Eal;
+            lcnt = uint32_t(E - Eal);
+          } else {
+            s_lim[tid] = A;
+            s_fl[tid] = 0;
+            lcst = A;
+            lcnt = uint32_t(E - A);
+          }
+          s_ncst[tid] = lcst;
+        }
       }
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
@@ -940,28 +974,74 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
     const bool same = next < r1 && P.L.tile_bin[next] == b;
     if (active && same) issue_loads(next);  // registers are free once staged
     if (active) {
-      // unrolled in groups of four so that the LDS reads of a group are in
-      // flight at once
       bool oob = false;
-#pragma unroll 1
-      for (int j0 = 0; j0 < ITEMS; j0 += 4)
+      if (LINES && lines_on) {
+        // buffered records completing a line go out first, then the tile:
+        // records below their digit's limit are stored, the rest buffered
+        for (uint32_t i = tid; i < kRadix * LREC; i += kScatterBlock) {
+          const uint32_t d = i / LREC, k = i % LREC;
+          if (d < nb && k < s_fl[d]) {
+            const uint64_t at = s_ocst[d] + k;
+            if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_line + uint64_t(i) * RW, nt);
+            else oob = true;
+          }
+        }
+        lds_barrier();  // those buffer slots are refilled below
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int j = j0 + jj;
-        const uint32_t p = j * kScatterBlock + tid;
-        if (j >= ITEMS) continue;
-        if (p < tn) {
-          const uint32_t d = s_dig[p];
-          const uint64_t at = s_gbase[d] + p;
-          // never write outside the bin, whatever the counts say
-          if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_rec + uint64_t(p) * RW, nt);
-          else oob = true;
+        for (int j = 0; j < ITEMS; ++j) {
+          const uint32_t p = j * kScatterBlock + tid;
+          if (p < tn) {
+            const uint32_t d = s_dig[p];
+            const uint64_t at = s_gbase[d] + p;
+            if (at < s_lim[d]) {
+              // never write outside the bin, whatever the counts say
+              if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_rec + uint64_t(p) * RW, nt);
+              else oob = true;
+            } else {
+              const uint64_t slot = at - s_ncst[d];
+              if (slot < LREC) {
+#pragma unroll
+                for (int q = 0; q < RW; ++q)
+                  s_line[(uint64_t(d) * LREC + slot) * RW + q] = s_rec[uint64_t(p) * RW + q];
+              } else {
+                oob = true;
+              }
+            }
+          }
+        }
+      } else {
+        // unrolled so that every LDS read of the write-out is in flight at once
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+          const uint32_t p = j * kScatterBlock + tid;
+          if (p < tn) {
+            const uint32_t d = s_dig[p];
+            const uint64_t at = s_gbase[d] + p;
+            // never write outside the bin, whatever the counts say
+            if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_rec + uint64_t(p) * RW, nt);
+            else oob = true;
+          }
         }
       }
       if (oob) atomicOr(&c->error, kErrBounds);
     }
     lds_barrier();
     t = next;
+    if (LINES && lines_on && active && (t >= r1 || !same)) {
+      // the bin's part of this range ends: its buffered records go out as
+      // they are (at most a partial line per digit)
+      if (tid < nb) {
+        bool bad = false;
+        for (uint32_t k = 0; k < lcnt && k < LREC; ++k) {
+          const uint64_t at = lcst + k;
+          if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_line + (uint64_t(tid) * LREC + k) * RW, nt);
+          else bad = true;
+        }
+        if (bad) atomicOr(&c->error, kErrBounds);
+      }
+      lcnt = 0;
+      lds_barrier();  // the buffers are reused by the next bin
+    }
     if (t < r1 && !same) {
       enter_bin(t);
       if (active) issue_loads(t);
