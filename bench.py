@@ -383,6 +383,16 @@ def main() -> int:
         "lds_sort": pass_bytes / (phases["lds_sort"] * 1e-3) / 1e9,
     }
 
+    # for scale: the runtime's own device copy of the same n*R bytes
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    copies[0].copy_(src)
+    ce0.record()
+    for _ in range(3):
+        copies[0].copy_(src)
+    ce1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * n * R / (ce0.elapsed_time(ce1) / 3 * 1e-3) / 1e9
+
     del copies, tmp
     torch.cuda.empty_cache()
     batched = None
@@ -416,6 +426,7 @@ def main() -> int:
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "phases_gbs": {k: round(v, 1) for k, v in phase_gbs.items()},
         "whole_sort_gbs_per_pass": round(pass_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "device_copy_gbs": round(copy_gbs, 1),
         "stats": stats,
         "verified": verified,
         "batched": batched,
