@@ -58,11 +58,12 @@ typedef enum raduls_status {
 typedef struct raduls_tuning {
   uint32_t digit_bits;   /* radix digit width in bits, 1..8 (default 8: one byte, Sec. 3.1) */
   uint32_t tiny_max;     /* bins of <= tiny_max records are finished by enumeration
-                            sort (Sec. 3.3); 1..256 (default 32) */
+                            sort (Sec. 3.3); 1..256 (default 64) */
   uint32_t mid_max;      /* bins of <= mid_max records are sorted inside one workgroup's
                             LDS (the "small bin fits in cache" case, Sec. 3.2); clamped
                             to the LDS capacity for R; default = that capacity */
-  uint32_t grid_blocks;  /* workgroups of the persistent kernels (default 2 per CU) */
+  uint32_t grid_blocks;  /* workgroups of the look-back scatter (lookback = 1; default
+                            2 per CU); the other kernels size their grids themselves */
   uint32_t nontemporal;  /* 1: scatter stores use the nontemporal (streaming) cache
                             policy, 2: ordinary stores (default 1) */
   uint32_t lookback;     /* 0 (default): each scatter workgroup walks the contiguous tile
@@ -77,7 +78,8 @@ typedef struct raduls_stats {
   uint32_t error;          /* bit 0: list capacity exceeded; bit 1: bounded look-back
                               wait expired; bit 2: a bin larger than mid_max reached the
                               LDS sorter; bit 3: batch total exceeded its capacity;
-                              bit 4: a scatter destination fell outside its bin
+                              bit 4: a destination fell outside its bin, or the LDS
+                              sorter's permutation named a record outside its job
                               (write suppressed) */
   uint32_t rounds;         /* radix rounds that found at least one large bin */
   uint32_t large_bins;     /* large bins processed over all rounds */
