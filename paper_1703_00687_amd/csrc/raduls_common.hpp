@@ -20,19 +20,21 @@ constexpr int kWave = 64;                   // CDNA wavefront width
 constexpr int kScatterBlock = 1024;
 constexpr int kScatterWaves = kScatterBlock / kWave;
 __host__ __device__ constexpr int scatter_items(int rw) {
-  return rw == 1 ? 8 : rw == 2 ? 6 : rw == 3 ? 5 : rw == 4 ? 4 : rw == 5 ? 3 : 2;
+  return rw == 1 ? 7 : rw == 2 ? 6 : rw == 3 ? 5 : rw == 4 ? 4 : rw == 5 ? 3 : 2;
 }
 // Records of 8 and 16 bytes leave the carry-mode scatter through per-digit
 // line buffers in LDS, so that every store but the first and last line of a
 // digit's output in a workgroup's range covers whole 128-byte lines.
 __host__ __device__ constexpr bool scatter_lines(int rw) { return rw <= 2; }
-// Dynamic LDS of one scatter workgroup: staged records, their digits,
-// per-wave counters, three 256-entry tables, the per-digit global bases and,
-// with line buffers, 128 bytes per digit plus four more per-digit tables.
+// Dynamic LDS of one scatter workgroup: the tile's records (input order) and
+// a 16-bit permutation (or, for the look-back variant, the records in digit
+// order and their digits), per-wave counters, three 256-entry tables, the
+// per-digit global bases and, with line buffers, 128 bytes per digit plus
+// three more per-digit tables.
 __host__ __device__ constexpr uint32_t scatter_lds_bytes(int rw) {
-  return uint32_t(kScatterBlock * scatter_items(rw)) * (8u * rw + 1u) +
+  return uint32_t(kScatterBlock * scatter_items(rw)) * (8u * rw + 2u) +
          uint32_t(kScatterWaves * 256 * 2) + 3u * 256u * 4u + 256u * 8u +
-         (scatter_lines(rw) ? 256u * 128u + 3u * 256u * 8u + 256u * 4u : 0u);
+         (scatter_lines(rw) ? 256u * 128u + 2u * 256u * 8u + 256u * 4u : 0u);
 }
 
 // LDS sorter workgroups: 16 waves, one workgroup per CU, which owns the

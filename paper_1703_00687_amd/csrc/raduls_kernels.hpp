@@ -832,9 +832,9 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
   constexpr int W = kScatterWaves;
   constexpr uint32_t TILE = kScatterBlock * ITEMS;
   extern __shared__ __align__(16) uint8_t smem[];
-  uint64_t* s_rec = reinterpret_cast<uint64_t*>(smem);
-  uint8_t* s_dig = reinterpret_cast<uint8_t*>(s_rec + TILE * RW);
-  uint16_t* s_cnt = reinterpret_cast<uint16_t*>(s_dig + TILE);
+  uint64_t* s_rec = reinterpret_cast<uint64_t*>(smem);          // tile, input order
+  uint16_t* s_perm = reinterpret_cast<uint16_t*>(s_rec + TILE * RW);  // position -> slot
+  uint16_t* s_cnt = s_perm + TILE;
   uint32_t* s_tot = reinterpret_cast<uint32_t*>(s_cnt + W * kRadix);
   uint32_t* s_off = s_tot + kRadix;
   uint32_t* s_binoff = s_off + kRadix;
@@ -847,8 +847,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
   uint64_t* s_line = s_gbase + kRadix;
   uint64_t* s_lim = s_line + (LINES ? kRadix * 16 : 0);
   uint64_t* s_ncst = s_lim + kRadix;
-  uint64_t* s_ocst = s_ncst + kRadix;
-  uint32_t* s_fl = reinterpret_cast<uint32_t*>(s_ocst + kRadix);
+  uint32_t* s_fl = reinterpret_cast<uint32_t*>(s_ncst + kRadix);
   __shared__ uint32_t s_scan[8];
 
   Ctrl* c = P.L.ctrl;
@@ -917,8 +916,12 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
     tile_span(t, tbeg, tn, ipw);
     uint32_t dg[ITEMS];
     bool valid[ITEMS];
+    const uint32_t next = t + 1;
+    const bool same = next < r1 && P.L.tile_bin[next] == b;
     if (active) {
-      uint32_t rank[ITEMS];
+      // the tile into LDS in input order and its digits into registers; the
+      // registers are then free for the next tile's loads, which stay in
+      // flight through the ranking and the stores of this tile
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
         const uint32_t i = wave * ipw * kWave + j * kWave + lane;
@@ -928,8 +931,12 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
           uint64_t key[KW];
           key_of<KW>(rec[j], P.kmask, key);
           dg[j] = digit_of<KW>(key, lob, w);
+#pragma unroll
+          for (int q = 0; q < RW; ++q) s_rec[uint64_t(i) * RW + q] = rec[j][q];
         }
       }
+      if (same) issue_loads(next);
+      uint32_t rank[ITEMS];
       uint16_t* wc = s_cnt + wave * kRadix;
       for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
       wave_rank<ITEMS>(dg, valid, w, wc, rank);
@@ -947,7 +954,6 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
           if (Eal > A) {
             s_lim[tid] = Eal;
             s_fl[tid] = lcnt;
-            s_ocst[tid] = lcst;
             lcst = Eal;
             lcnt = uint32_t(E - Eal);
           } else {
@@ -963,25 +969,21 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
       for (int j = 0; j < ITEMS; ++j) {
         if (valid[j]) {
           const uint32_t pos = s_off[dg[j]] + wc[dg[j]] + rank[j];
-#pragma unroll
-          for (int q = 0; q < RW; ++q) s_rec[pos * RW + q] = rec[j][q];
-          s_dig[pos] = uint8_t(dg[j]);
+          s_perm[pos] = uint16_t(wave * ipw * kWave + j * kWave + lane);
         }
       }
       lds_barrier();
     }
-    const uint32_t next = t + 1;
-    const bool same = next < r1 && P.L.tile_bin[next] == b;
-    if (active && same) issue_loads(next);  // registers are free once staged
     if (active) {
       bool oob = false;
       if (LINES && lines_on) {
-        // buffered records completing a line go out first, then the tile:
+        // buffered records completing a line go out first (they end right
+        // before the digit's first record of this tile), then the tile:
         // records below their digit's limit are stored, the rest buffered
         for (uint32_t i = tid; i < kRadix * LREC; i += kScatterBlock) {
           const uint32_t d = i / LREC, k = i % LREC;
           if (d < nb && k < s_fl[d]) {
-            const uint64_t at = s_ocst[d] + k;
+            const uint64_t at = s_gbase[d] + s_off[d] - s_fl[d] + k;
             if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_line + uint64_t(i) * RW, nt);
             else oob = true;
           }
@@ -991,18 +993,21 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
         for (int j = 0; j < ITEMS; ++j) {
           const uint32_t p = j * kScatterBlock + tid;
           if (p < tn) {
-            const uint32_t d = s_dig[p];
+            const uint32_t sl = s_perm[p];
+            const uint64_t* r = s_rec + uint64_t(sl) * RW;
+            uint64_t key[KW];
+            key_of<KW>(r, P.kmask, key);
+            const uint32_t d = digit_of<KW>(key, lob, w);
             const uint64_t at = s_gbase[d] + p;
             if (at < s_lim[d]) {
               // never write outside the bin, whatever the counts say
-              if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_rec + uint64_t(p) * RW, nt);
+              if (at - bin.start < bin.size) store_rec<RW>(dst, at, r, nt);
               else oob = true;
             } else {
               const uint64_t slot = at - s_ncst[d];
               if (slot < LREC) {
 #pragma unroll
-                for (int q = 0; q < RW; ++q)
-                  s_line[(uint64_t(d) * LREC + slot) * RW + q] = s_rec[uint64_t(p) * RW + q];
+                for (int q = 0; q < RW; ++q) s_line[(uint64_t(d) * LREC + slot) * RW + q] = r[q];
               } else {
                 oob = true;
               }
@@ -1015,10 +1020,14 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
         for (int j = 0; j < ITEMS; ++j) {
           const uint32_t p = j * kScatterBlock + tid;
           if (p < tn) {
-            const uint32_t d = s_dig[p];
+            const uint32_t sl = s_perm[p];
+            const uint64_t* r = s_rec + uint64_t(sl) * RW;
+            uint64_t key[KW];
+            key_of<KW>(r, P.kmask, key);
+            const uint32_t d = digit_of<KW>(key, lob, w);
             const uint64_t at = s_gbase[d] + p;
             // never write outside the bin, whatever the counts say
-            if (at - bin.start < bin.size) store_rec<RW>(dst, at, s_rec + uint64_t(p) * RW, nt);
+            if (at - bin.start < bin.size) store_rec<RW>(dst, at, r, nt);
             else oob = true;
           }
         }
