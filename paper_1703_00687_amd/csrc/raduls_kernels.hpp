@@ -447,7 +447,7 @@ static __global__ void __launch_bounds__(1024) k_prep(Params P, uint32_t cur) {
 // flushing to the bin's global row when the range crosses into the next bin.
 // Also clears the look-back status rows of its tiles and records their bin.
 template <int RW, int KW, int TOP>
-__global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) {
+__global__ void __launch_bounds__(kScatterBlock, 8) k_hist(Params P, uint32_t cur) {
   constexpr int ITEMS = scatter_items(RW);
   constexpr int W = kScatterWaves;
   constexpr uint32_t TILE = kScatterBlock * ITEMS;
@@ -512,12 +512,39 @@ __global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) 
     __syncthreads();
   };
 
+  // Tiles are software-pipelined: the keys of tile t+1 are loaded while tile
+  // t is counted.  Counting needs no order, so every lane adds its items to
+  // its wave's counters with LDS atomics.
   Bin bin = P.L.large[cur][b];
   ArrayDesc arr = P.L.arrays[bin.array];
   const uint8_t* src = bin.side ? arr.tmp : arr.recs;
   uint64_t key0[KW];
   key_of<KW>(gmem(reinterpret_cast<const uint64_t*>(src)) + uint64_t(bin.start) * RW, P.kmask, key0);
 
+  // the tile to load: its bin (bl), its records and where they come from
+  uint32_t bl = b;
+  auto load_tile = [&](uint32_t t, uint64_t (&kt)[ITEMS][KW], uint32_t& tn_out) {
+    while (bl + 1 < nbins && t >= tp[bl + 1]) ++bl;
+    const Bin bb = P.L.large[cur][bl];
+    const ArrayDesc aa = P.L.arrays[bb.array];
+    const RADULS_GLOBAL uint64_t* sw =
+        gmem(reinterpret_cast<const uint64_t*>(bb.side ? aa.tmp : aa.recs));
+    const uint32_t k = t - tp[bl];
+    const uint32_t tbeg = bb.start + k * TILE;
+    const uint32_t tn = min(TILE, bb.size - k * TILE);
+    const uint32_t ipw = (tn + kWave * W - 1) / (kWave * W);
+    tn_out = tn;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+#pragma unroll
+      for (int q = 0; q < KW; ++q) kt[j][q] = 0;
+      if (uint32_t(j) < ipw && i < tn) key_of<KW>(sw + uint64_t(tbeg + i) * RW, P.kmask, kt[j]);
+    }
+  };
+  uint64_t kc[ITEMS][KW];
+  uint32_t tnc = 0;
+  load_tile(t0, kc, tnc);
   for (uint32_t t = t0; t < t1; ++t) {
     while (b + 1 < nbins && t >= tp[b + 1]) {
       flush(b, false);
@@ -528,13 +555,10 @@ __global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) 
       key_of<KW>(gmem(reinterpret_cast<const uint64_t*>(src)) + uint64_t(bin.start) * RW, P.kmask, key0);
     }
     if (tid == 0) P.L.tile_bin[t] = b;
-    const uint32_t k = t - tp[b];
-    const uint32_t tbeg = bin.start + k * TILE;
-    const uint32_t tn = min(TILE, bin.size - k * TILE);
+    const uint32_t tn = tnc;
     const uint32_t ipw = (tn + kWave * W - 1) / (kWave * W);
     const uint32_t w = min(P.digit_bits, uint32_t(bin.bits));
     const uint32_t lob = bin.bits - w;
-    const RADULS_GLOBAL uint64_t* sw = gmem(reinterpret_cast<const uint64_t*>(src));
     uint32_t dg[ITEMS];
     bool valid[ITEMS];
 #pragma unroll
@@ -543,19 +567,16 @@ __global__ void __launch_bounds__(kScatterBlock) k_hist(Params P, uint32_t cur) 
       valid[j] = (uint32_t(j) < ipw) && (i < tn);
       dg[j] = 0;
       if (valid[j]) {
-        uint64_t key[KW];
-        key_of<KW>(sw + uint64_t(tbeg + i) * RW, P.kmask, key);
-        dg[j] = digit_of<KW>(key, lob, w);
+        dg[j] = digit_of<KW>(kc[j], lob, w);
 #pragma unroll
-        for (int q = 0; q < KW; ++q) dacc[q] |= key[q] ^ key0[q];
+        for (int q = 0; q < KW; ++q) dacc[q] |= kc[j][q] ^ key0[q];
       }
     }
+    if (t + 1 < t1) load_tile(t + 1, kc, tnc);
     uint32_t* wc = s_cnt + wave * kRadix;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const uint64_t peers = match_digit(dg[j], valid[j], w);
-      if (valid[j] && __popcll(peers & lanemask_lt()) == 0) wc[dg[j]] += __popcll(peers);
-    }
+    for (int j = 0; j < ITEMS; ++j)
+      if (valid[j]) atomicAdd(&wc[dg[j]], 1u);
   }
   flush(b, true);
   if (tid == 0) {
