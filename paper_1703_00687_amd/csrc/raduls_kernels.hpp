@@ -1889,7 +1889,17 @@ __global__ void __launch_bounds__(256) k_copy(Params P) {
     if ((reinterpret_cast<uintptr_t>(s) & 15) == 0 && (reinterpret_cast<uintptr_t>(d) & 15) == 0) {
       const RADULS_GLOBAL u64x2* s2 = reinterpret_cast<const RADULS_GLOBAL u64x2*>(s);
       RADULS_GLOBAL u64x2* d2 = reinterpret_cast<RADULS_GLOBAL u64x2*>(d);
-      for (uint64_t q = threadIdx.x; q < words / 2; q += 256) d2[q] = s2[q];
+      // four 16-byte loads in flight per thread before their stores
+      const uint64_t n2 = words / 2;
+      for (uint64_t q0 = threadIdx.x; q0 < n2; q0 += 4 * 256) {
+        u64x2 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (q0 + k * 256 < n2) v[k] = s2[q0 + k * 256];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (q0 + k * 256 < n2) d2[q0 + k * 256] = v[k];
+      }
       if ((words & 1) && threadIdx.x == 0) d[words - 1] = s[words - 1];
     } else {
       for (uint64_t q = threadIdx.x; q < words; q += 256) d[q] = s[q];

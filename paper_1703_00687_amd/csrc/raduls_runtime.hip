@@ -205,7 +205,7 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
   P.scatter_lds_bytes = scatter_lds_bytes(int(R / 8));
   P.mid_lds_bytes = mid_dynamic_lds(e.mid_max, int(R / 8));
   P.grid_mid = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_mid, cus));
-  P.grid_copy = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_copy, 2 * cus));
+  P.grid_copy = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_copy, 8 * cus));
 }
 
 int launch(const Params& P, uint32_t R, uint32_t K, hipStream_t stream) {
