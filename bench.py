@@ -3,9 +3,12 @@
 
 Workload (default): 2^28 records of 16 B -- a uint64 key uniform over 64 bits
 and a uint64 payload holding the record's input index -- sorted by the 8 key
-bytes with 1-byte digits.  Synthetic, seeded, generated on the host and
-uploaded once; every step sorts its own resident copy of the input, so the
-timed region holds nothing but sorts.
+bytes with 1-byte digits.  `--workload` selects the others (uniform8, zipf16,
+deep32, keys16) and `--rec-sweep` adds records of 8-64 B.  Synthetic and
+seeded, generated on the device; every step sorts its own resident copy of
+the input, so the timed region holds nothing but sorts.  The default run also
+compares one batched call over 65,536 uneven arrays with one call per array
+and serves the same arrays as a request stream.
 
 Prints one JSON line.  `value` is records sorted per second over the timed
 steps.  `roofline` covers the dominant kernel, the top-level scatter, from HIP
@@ -91,43 +94,165 @@ def load_traffic(n: int) -> float | None:
     return t.get("hbm_bytes_per_launch")
 
 
-def check_sorted_device(out, src, n):
-    """Stable-sort properties on the device: keys non-decreasing, payloads a
-    permutation, every record equal to the input record its payload names,
-    equal keys in input order.  Together they pin the unique stable result."""
+def _u64(x):
+    """Order-preserving map of uint64 bit patterns (in int64) onto int64."""
+    return x ^ (-(1 << 63))
+
+
+def lexsort_order(wi, kw):
+    """Permutation that stably sorts the rows of wi (int64 [n, words]) by
+    their first kw words as one unsigned integer (word kw-1 most
+    significant), from torch's own stable sort one word at a time, least
+    significant first."""
     import torch
-    w = out.view(torch.int64).view(n, 2)
-    sign = torch.tensor(-(1 << 63), dtype=torch.int64, device=w.device)
-    k = w[:, 0] ^ sign  # order-preserving map of uint64 onto int64
-    p = w[:, 1]
-    if not bool((k[1:] >= k[:-1]).all()):
+    order = torch.arange(wi.shape[0], device=wi.device)
+    for q in range(kw):
+        col = wi[:, q].contiguous()
+        o = torch.sort(_u64(col[order]), stable=True).indices
+        order = order[o]
+    return order
+
+
+def check_sorted_device(out, src, n, R, K):
+    """Sort properties on the device.  Keys (K a multiple of 8) must not
+    decrease.  With a payload word after the key holding the input index:
+    the indices form a permutation, every record equals the input record its
+    index names, and equal keys keep input order -- together they pin the
+    unique stable result.  Without one (the record is all key): the output
+    must equal torch's own stable lexicographic sort of the input."""
+    import torch
+    words, kw = R // 8, K // 8
+    w = out.view(torch.int64).view(n, words)
+    ws = src.view(torch.int64).view(n, words)
+    le = torch.ones(n - 1, dtype=torch.bool, device=w.device)
+    eq = torch.ones_like(le)
+    for q in range(kw):  # least significant word first: later words decide
+        a, c = _u64(w[:-1, q]), _u64(w[1:, q])
+        le = (c > a) | ((c == a) & le)
+        eq = eq & (c == a)
+    if not bool(le.all()):
         return False
+    if R == K:
+        order = lexsort_order(ws, kw)
+        return all(bool(torch.equal(ws[:, q].contiguous()[order], w[:, q].contiguous()))
+                   for q in range(words))
+    p = w[:, kw]
     if not bool(((p >= 0) & (p < n)).all()):
         return False
     seen = torch.zeros(n, dtype=torch.bool, device=w.device)
     seen[p] = True
     if not bool(seen.all()):
         return False
-    ws = src.view(torch.int64).view(n, 2)
     if not bool((ws[p] == w).all()):
         return False
-    eq = k[1:] == k[:-1]
     return bool((p[1:][eq] > p[:-1][eq]).all())
 
 
-def cpu_baseline(log2n: int) -> dict:
+def cpu_baseline(name: str, log2n: int) -> dict:
     import oracle
     from paper_1703_00687_amd import workloads as wl
     n = 1 << log2n
-    host = wl.uniform16(n)
-    oracle.sort(host[:1024], 8)  # load/build outside the timing
+    host, k = wl.make(name, n)
+    oracle.sort(host[:1024], k)  # load/build outside the timing
     t0 = time.perf_counter()
-    out = oracle.sort(host, 8)
+    out = oracle.sort(host, k)
     dt = time.perf_counter() - t0
-    assert oracle.check_sorted(out[: 1 << 16], 8)
+    assert oracle.check_sorted(out[: 1 << 16], k)
     return {"value": n / dt, "unit": "records/s", "cores": 1, "kind": "oracle",
-            "sample": f"first 2^{log2n} records of the same uniform16 workload "
+            "sample": f"first 2^{log2n} records of the same {name} workload "
                       f"(std::stable_sort, one thread, {dt:.1f} s)"}
+
+
+def time_sorts(src, n, R, K, steps, warm, verify):
+    """Sort `steps` resident copies of src (after `warm` untimed sorts), with
+    the library's profile events around each kernel class.  Returns
+    (ms per step on the GPU clock, mean phase times, device stats, verified)."""
+    import torch
+    from paper_1703_00687_amd import binding as b
+    copies = []
+    for _ in range(warm + steps):
+        c = torch.empty_like(src)
+        c.copy_(src)
+        copies.append(c)
+    tmp = torch.empty(b.raduls_tmp_bytes(n, R, K), dtype=torch.uint8, device=src.device)
+    torch.cuda.synchronize()
+    log(f"[bench] {warm + steps} resident copies of {n * R / 2**30:.2f} GiB, tmp "
+        f"{tmp.numel() / 2**30:.2f} GiB")
+    hip = HipEvents()
+    nslot = len(PROFILE_SLOTS)
+    step_events = [hip.create(2 * nslot) for _ in range(steps)]
+    for i in range(warm):
+        b.raduls_sort(copies[i], tmp, n, R, K)
+    torch.cuda.synchronize()
+    st, stats = b.raduls_check(tmp, n, R, False)
+    if st != b.OK:
+        raise RuntimeError(f"device error in warm-up: {stats}")
+    log(f"[bench] warm-up done; stats {stats}")
+
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for i in range(steps):
+        b.raduls_set_profile_events(step_events[i])
+        b.raduls_sort(copies[warm + i], tmp, n, R, K)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.raduls_set_profile_events([])
+    gpu_ms = start.elapsed_time(stop)
+    log(f"[bench] timed {steps} steps: {gpu_ms:.2f} ms on the GPU clock, {wall * 1e3:.2f} ms wall")
+    st, stats = b.raduls_check(tmp, n, R, False)
+    if st != b.OK:
+        raise RuntimeError(f"device error in timed steps: {stats}")
+    phases = {}
+    for j, name in enumerate(PROFILE_SLOTS):
+        vals = [hip.elapsed_ms(ev[2 * j], ev[2 * j + 1]) for ev in step_events]
+        phases[name] = sum(vals) / len(vals)
+    for ev in step_events:
+        hip.destroy(ev)
+    del tmp
+    verified = None
+    if verify:
+        last = copies[-1]
+        del copies
+        torch.cuda.empty_cache()
+        verified = check_sorted_device(last, src, n, R, K)
+        if not verified:
+            raise RuntimeError("sorted output failed the sort property check")
+        log("[bench] last step's output verified on the device")
+        del last
+    else:
+        del copies
+    torch.cuda.empty_cache()
+    return gpu_ms / steps, phases, stats, verified
+
+
+SWEEP_SHAPES = [(8, 8), (16, 8), (16, 16), (24, 8), (24, 16), (32, 8), (32, 16), (48, 8),
+                (48, 16), (64, 8), (64, 16)]
+
+
+def rec_sweep(log2n: int, verify: bool) -> list:
+    """Records of 8-64 bytes with 8- or 16-byte keys (the paper's sweep over
+    record sizes), 2^log2n records each, 1 warm-up and 3 timed sorts."""
+    import torch
+    from paper_1703_00687_amd import workloads as wl
+    n = 1 << log2n
+    out = []
+    for R, K in SWEEP_SHAPES:
+        log(f"[sweep] R={R} K={K} n=2^{log2n}")
+        src = wl.sweep_records_torch(n, R, K)
+        ms, ph, stats, ok = time_sorts(src, n, R, K, 3, 1, verify)
+        del src
+        torch.cuda.empty_cache()
+        out.append({"rec_bytes": R, "key_bytes": K, "n": n, "ms": round(ms, 3),
+                    "records_per_s": n / (ms * 1e-3),
+                    "gbs_per_pass": round(2 * n * R / (ms * 1e-3) / 1e9, 1),
+                    "top_scatter_gbs": round(2 * n * R / (ph["top_scatter"] * 1e-3) / 1e9, 1),
+                    "rounds": stats["rounds"], "verified": ok})
+        log(f"[sweep] {out[-1]}")
+    return out
 
 
 def fill_batch(recs, starts, sizes, seed=5):
@@ -279,13 +404,31 @@ def bench_batch(args) -> dict:
     return out
 
 
+WORKLOAD_DESC = {
+    "uniform16": "2^{l} records of 16 B (uint64 key uniform, uint64 payload = index), key 8 B, "
+                 "1-byte digits",
+    "uniform8": "2^{l} records of 8 B (uint64 key uniform, no payload), key 8 B, 1-byte digits; "
+                "8 MiB fits the on-package cache, so the roofline is no HBM claim",
+    "zipf16": "2^{l} records of 16 B, keys Zipf(s=1.1) over 2^24 distinct uint64 values with 5% "
+              "of records sharing one extra key, payload = index; key 8 B, 1-byte digits",
+    "deep32": "2^{l} records of 32 B, 16 B key (low word uniform, high word uniform over "
+              "0..2^20-1), payload = index + random word; key 16 B, 1-byte digits",
+    "keys16": "2^{l} records of 16 B that are all key (uniform over 128 bits); key 16 B, "
+              "1-byte digits",
+}
+DEFAULT_LOG2 = {"uniform16": 28, "uniform8": 20, "zipf16": 28, "deep32": 27, "keys16": 28}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--log2n", type=int, default=28, help="records = 2^log2n (default 28)")
-    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--workload", default="uniform16", choices=sorted(WORKLOAD_DESC))
+    ap.add_argument("--log2n", type=int, default=None,
+                    help="records = 2^log2n (default: the workload's size)")
+    ap.add_argument("--cpu-sample-log2", type=int, default=None,
+                    help="oracle sample, 2^k records (default 25, or the whole input if smaller)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--batch-count", type=int, default=65536)
@@ -295,119 +438,81 @@ def main() -> int:
     ap.add_argument("--serve-load", type=float, default=0.9,
                     help="Poisson arrival rate as a fraction of the plain per-call throughput")
     ap.add_argument("--serve-budget-gib", type=int, default=32)
-    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched / served comparison (run only with uniform16)")
+    ap.add_argument("--rec-sweep", action="store_true",
+                    help="also sort records of 8-64 B with 8/16 B keys (2^--sweep-log2 each)")
+    ap.add_argument("--sweep-log2", type=int, default=28)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU path is a design in DESIGN.md, not built)", file=sys.stderr)
+              "(the multi-GPU path is a design only, not built)", file=sys.stderr)
         return 2
 
     import torch
-    from paper_1703_00687_amd import binding as b
     from paper_1703_00687_amd import workloads as wl
 
-    n, R, K = 1 << args.log2n, 16, 8
+    name = args.workload
+    log2n = DEFAULT_LOG2[name] if args.log2n is None else args.log2n
+    spec = wl.WORKLOADS[name]
+    n, R, K = 1 << log2n, spec["rec_bytes"], spec["key_bytes"]
     steps, warm = args.steps, args.warmup
-    log(f"[bench] generating uniform16 n=2^{args.log2n}")
-    host = wl.uniform16(n)
+    log(f"[bench] generating {name} n=2^{log2n} on the device")
     dev = torch.device("cuda:0")
-    src = torch.from_numpy(host.reshape(-1)).to(dev)
-    del host
-    copies = []
-    for _ in range(warm + steps):
-        c = torch.empty_like(src)
-        c.copy_(src)
-        copies.append(c)
-    tmp = torch.empty(b.raduls_tmp_bytes(n, R, K), dtype=torch.uint8, device=dev)
+    src = wl.make_torch(name, n, device=dev)
     torch.cuda.synchronize()
-    log(f"[bench] {warm + steps} resident copies of {n * R / 2**30:.1f} GiB, tmp "
-        f"{tmp.numel() / 2**30:.2f} GiB")
-
-    hip = HipEvents()
-    nslot = len(PROFILE_SLOTS)
-    step_events = [hip.create(2 * nslot) for _ in range(steps)]
-
-    for i in range(warm):
-        b.raduls_sort(copies[i], tmp, n, R, K)
-    torch.cuda.synchronize()
-    st, stats = b.raduls_check(tmp, n, R, False)
-    if st != b.OK:
-        raise RuntimeError(f"device error in warm-up: {stats}")
-    log(f"[bench] warm-up done; stats {stats}")
-
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record()
-    for i in range(steps):
-        b.raduls_set_profile_events(step_events[i])
-        b.raduls_sort(copies[warm + i], tmp, n, R, K)
-    stop.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    b.raduls_set_profile_events([])
-    gpu_ms = start.elapsed_time(stop)
-    ms_per_step = gpu_ms / steps
-    log(f"[bench] timed {steps} steps: {gpu_ms:.2f} ms on the GPU clock, {wall * 1e3:.2f} ms wall")
-
-    st, stats = b.raduls_check(tmp, n, R, False)
-    if st != b.OK:
-        raise RuntimeError(f"device error in timed steps: {stats}")
-    verified = None
-    if not args.no_verify:
-        verified = check_sorted_device(copies[-1], src, n)
-        if not verified:
-            raise RuntimeError("sorted output failed the stable-sort property check")
-        log("[bench] last step's output verified on the device")
-
-    phases = {}
-    for j, name in enumerate(PROFILE_SLOTS):
-        vals = [hip.elapsed_ms(ev[2 * j], ev[2 * j + 1]) for ev in step_events]
-        phases[name] = sum(vals) / len(vals)
-    for ev in step_events:
-        hip.destroy(ev)
+    ms_per_step, phases, stats, verified = time_sorts(src, n, R, K, steps, warm,
+                                                      not args.no_verify)
     pass_bytes = 2 * n * R
-    scat_ms = phases["top_scatter"]
+    # the dominant kernel: the first scatter that moves every record (the
+    # deep32 keys' constant top digits are skipped, so there it is round 2)
+    roof_phase = "round2_scatter" if name == "deep32" else "top_scatter"
+    scat_ms = phases[roof_phase]
     achieved = pass_bytes / (scat_ms * 1e-3) / 1e9
-    traffic = load_traffic(n)
+    traffic = load_traffic(n) if name == "uniform16" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "k_scatter_carry<2,1,1> (top-level scatter)",
+                "traffic": traffic,
+                "kernel": f"k_scatter_carry<{R // 8},{(K + 7) // 8},"
+                          f"{1 if roof_phase == 'top_scatter' else 0}> ({roof_phase})",
                 "bytes_per_launch": pass_bytes, "mean_launch_ms": round(scat_ms, 4)}
     phase_gbs = {
         "top_hist": n * R / (phases["top_hist"] * 1e-3) / 1e9,
-        "top_scatter": achieved,
+        "top_scatter": pass_bytes / (phases["top_scatter"] * 1e-3) / 1e9,
         "round2_hist": n * R / (phases["round2_hist"] * 1e-3) / 1e9,
         "round2_scatter": pass_bytes / (phases["round2_scatter"] * 1e-3) / 1e9,
         "lds_sort": pass_bytes / (phases["lds_sort"] * 1e-3) / 1e9,
     }
 
     # for scale: the runtime's own device copy of the same n*R bytes
+    dst = torch.empty_like(src)
     ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    copies[0].copy_(src)
+    dst.copy_(src)
     ce0.record()
     for _ in range(3):
-        copies[0].copy_(src)
+        dst.copy_(src)
     ce1.record()
     torch.cuda.synchronize()
     copy_gbs = 2 * n * R / (ce0.elapsed_time(ce1) / 3 * 1e-3) / 1e9
-
-    del copies, tmp
+    del dst, src
     torch.cuda.empty_cache()
+
     batched = None
-    if not args.no_batch:
+    if not args.no_batch and name == "uniform16":
         batched = bench_batch(args)
+    sweep = None
+    if args.rec_sweep:
+        sweep = rec_sweep(args.sweep_log2, not args.no_verify)
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"[bench] CPU oracle on 2^{args.cpu_sample_log2} records")
-        cpu = cpu_baseline(args.cpu_sample_log2)
+        clog2 = min(log2n, 25) if args.cpu_sample_log2 is None else args.cpu_sample_log2
+        log(f"[bench] CPU oracle on 2^{clog2} records of {name}")
+        cpu = cpu_baseline(name, clog2)
 
-    value = n / (ms_per_step * 1e-3)
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": n / (ms_per_step * 1e-3),
         "unit": "records/s",
         "n_gpus": 1,
         "steps": steps,
@@ -418,8 +523,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"uniform16: 2^{args.log2n} records of 16 B (uint64 key uniform, "
-                               "uint64 payload = index), key 8 B, 1-byte digits",
+        "config": {"workload": f"{name}: " + WORKLOAD_DESC[name].format(l=log2n),
                    "n": n, "rec_bytes": R, "key_bytes": K},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -431,6 +535,8 @@ def main() -> int:
         "verified": verified,
         "batched": batched,
     }
+    if sweep is not None:
+        line["rec_sweep"] = sweep
     print(json.dumps(line), flush=True)
     return 0
 

@@ -23,6 +23,12 @@ Workloads (record = key bytes first, little-endian, then payload):
                  a random word).
 * ``batch16``    many arrays of 16 B records, sizes log-uniform in
                  [1, 2^max_log2]; key uniform, payload = index in its array.
+* ``keys16``     2^28 records of 16 B that are all key (uniform over 128 bits,
+                 no payload): the shape of the 16 B k-mer records the paper's
+                 application sorts (Sec. 4.2), synthetic.
+* ``sweep_records(n, R, K)``  the record-size sweep (Sec. 4.2, records of
+                 various sizes): K key bytes uniform, then a payload word
+                 holding the index when R > K, then random words.
 """
 
 from __future__ import annotations
@@ -194,11 +200,38 @@ def batch_array(j: int, size: int, offset: int, seed: int = 5) -> np.ndarray:
     return out.view(np.uint8).reshape(size, 16)
 
 
+SWEEP_SEED = 6
+
+
+def sweep_records(n: int, rec_bytes: int, key_bytes: int, seed: int = SWEEP_SEED) -> np.ndarray:
+    """n records of rec_bytes (a multiple of 8) with key_bytes in {8, 16}:
+    key words uniform over 64 bits each, then (if rec_bytes > key_bytes) a
+    word holding the record's index, then uniform words."""
+    assert rec_bytes % 8 == 0 and key_bytes in (8, 16) and key_bytes <= rec_bytes
+    words = rec_bytes // 8
+    kw = key_bytes // 8
+    out = np.empty((n, words), dtype="<u8")
+    chunk = 1 << 23
+    for a in range(0, n, chunk):
+        c = min(chunk, n - a)
+        for q in range(words):
+            if q == kw:
+                out[a:a + c, q] = np.arange(a, a + c, dtype=np.uint64)
+            else:
+                out[a:a + c, q] = splitmix64(stream_seed(seed, 100 * rec_bytes + q), a, c)
+    return out.view(np.uint8).reshape(n, rec_bytes)
+
+
+def keys16(n: int = 1 << 28, seed: int = 7) -> np.ndarray:
+    return sweep_records(n, 16, 16, seed=seed)
+
+
 WORKLOADS = {
     "uniform8": dict(fn=uniform8, n=1 << 20, rec_bytes=8, key_bytes=8, seed=1),
     "uniform16": dict(fn=uniform16, n=1 << 28, rec_bytes=16, key_bytes=8, seed=2),
     "zipf16": dict(fn=zipf16, n=1 << 28, rec_bytes=16, key_bytes=8, seed=3),
     "deep32": dict(fn=deep32, n=1 << 27, rec_bytes=32, key_bytes=16, seed=4),
+    "keys16": dict(fn=keys16, n=1 << 28, rec_bytes=16, key_bytes=16, seed=7),
 }
 
 
@@ -310,3 +343,38 @@ def deep32_torch(n: int, seed: int = 4, hi_values: int = DEEP_HI_VALUES, device=
         out[a:a + c, 2] = torch.arange(a, a + c, dtype=torch.int64, device=device)
         out[a:a + c, 3] = splitmix64_torch(stream_seed(seed, 2), a, c, device)
     return out.view(torch.uint8).view(n, 32)
+
+
+def sweep_records_torch(n: int, rec_bytes: int, key_bytes: int, seed: int = SWEEP_SEED,
+                        device="cuda", chunk: int = 1 << 25):
+    """sweep_records built on the device: returns an [n, rec_bytes] uint8 tensor."""
+    import torch
+    assert rec_bytes % 8 == 0 and key_bytes in (8, 16) and key_bytes <= rec_bytes
+    words = rec_bytes // 8
+    kw = key_bytes // 8
+    out = torch.empty((n, words), dtype=torch.int64, device=device)
+    for a in range(0, n, chunk):
+        c = min(chunk, n - a)
+        for q in range(words):
+            if q == kw:
+                out[a:a + c, q] = torch.arange(a, a + c, dtype=torch.int64, device=device)
+            else:
+                out[a:a + c, q] = splitmix64_torch(stream_seed(seed, 100 * rec_bytes + q), a, c,
+                                                   device)
+    return out.view(torch.uint8).view(n, rec_bytes)
+
+
+def uniform8_torch(n: int, seed: int = 1, device="cuda"):
+    import torch
+    return splitmix64_torch(stream_seed(seed, 0), 0, n, device).view(torch.uint8).view(n, 8)
+
+
+def keys16_torch(n: int, seed: int = 7, device="cuda"):
+    return sweep_records_torch(n, 16, 16, seed=seed, device=device)
+
+
+def make_torch(name: str, n: int, device="cuda"):
+    """Workload `name` with n records built on the device."""
+    fns = {"uniform8": uniform8_torch, "uniform16": uniform16_torch, "zipf16": zipf16_torch, "deep32": deep32_torch,
+           "keys16": keys16_torch}
+    return fns[name](n, device=device)

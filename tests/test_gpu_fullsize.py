@@ -160,6 +160,25 @@ def test_deep32_full():
     sample_windows(out, inp, 4, 2, 16, seed=2)
 
 
+def test_keys16_full():
+    """Records that are all key (no index payload): the output must equal
+    torch's own stable lexicographic sort of the input, word by word."""
+    n = 1 << 28
+    inp = wl.keys16_torch(n)
+    out, _ = _sort_full(inp, 16)
+    w = out.view(torch.int64).view(n, 2)
+    wi = inp.view(torch.int64).view(n, 2)
+    le, _ = _key_cmp([w[:, 0], w[:, 1]])
+    assert bool(le.all()), "keys decrease somewhere"
+    order = torch.arange(n, device=inp.device)
+    for q in range(2):  # least significant word first
+        col = wi[:, q].contiguous()
+        order = order[torch.sort(_u(col[order]), stable=True).indices]
+    for q in range(2):
+        assert torch.equal(wi[:, q].contiguous()[order], w[:, q].contiguous())
+    sample_windows(out, inp, 2, 2, 16, seed=4)
+
+
 def test_batch_full():
     """The batched workload at full size: 65536 arrays, sizes log-uniform in
     [1, 2^20] (about 5e9 records), one batched call.  Every array is checked

@@ -64,11 +64,23 @@ def test_store_policies_and_scans(nontemporal, lookback):
 
 
 @pytest.mark.parametrize("name,n", [("uniform8", 1 << 20), ("uniform16", 1 << 22),
-                                    ("zipf16", 1 << 21), ("deep32", 1 << 20)])
+                                    ("zipf16", 1 << 21), ("deep32", 1 << 20),
+                                    ("keys16", 1 << 21)])
 def test_workloads_reduced(name, n):
     inp, k = wl.make(name, n)
     out, _ = gpu_sort(inp, k)
     _assert_parity(out, inp, k)
+
+
+@pytest.mark.parametrize("r,k", [(8, 8), (16, 8), (16, 16), (24, 8), (24, 16), (32, 8),
+                                 (32, 16), (48, 8), (48, 16), (64, 8), (64, 16)])
+def test_record_size_sweep_reduced(r, k):
+    """The record shapes of the record-size sweep, element by element against
+    the oracle, at a size that still takes two radix rounds."""
+    inp = wl.sweep_records(1 << 19, r, k)
+    out, stats = gpu_sort(inp, k)
+    _assert_parity(out, inp, k)
+    assert stats["rounds"] >= 1
 
 
 def _adversarial(r, k, n, seed):

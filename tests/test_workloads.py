@@ -30,3 +30,27 @@ def test_zipf_shape():
     # frequent Zipf rank several percent more
     assert 0.03 < counts.max() / keys.size < 0.2
     assert np.array_equal(recs[:, 8:].copy().view("<u8").ravel(), np.arange(1 << 16))
+
+
+@pytest.mark.parametrize("r,k", [(8, 8), (16, 8), (16, 16), (24, 8), (24, 16), (32, 16),
+                                 (48, 8), (64, 16)])
+def test_sweep_records_twins_and_layout(r, k):
+    pytest.importorskip("torch")
+    n = 5003
+    host = wl.sweep_records(n, r, k)
+    assert host.shape == (n, r)
+    assert np.array_equal(host, wl.sweep_records_torch(n, r, k, device="cpu", chunk=1024).numpy())
+    w = host.view("<u8").reshape(n, r // 8)
+    if r > k:  # the word after the key holds the index
+        assert np.array_equal(w[:, k // 8], np.arange(n, dtype=np.uint64))
+    # key words look uniform: each of the 8 top bits is set about half the time
+    top = (w[:, k // 8 - 1] >> np.uint64(56)).astype(np.int64)
+    for bit in range(8):
+        assert abs(((top >> bit) & 1).mean() - 0.5) < 0.05
+
+
+def test_named_device_builders_match_host():
+    pytest.importorskip("torch")
+    for name in ("uniform8", "uniform16", "deep32", "keys16"):
+        host, _ = wl.make(name, 4099)
+        assert np.array_equal(host, wl.make_torch(name, 4099, device="cpu").numpy()), name
