@@ -70,7 +70,14 @@ typedef struct raduls_tuning {
                             range of the histogram pass and starts from a carry computed
                             from the per-range counts; 1: tiles taken in ticket order get
                             their prefix by decoupled look-back over earlier tiles */
-  uint32_t reserved[10];
+  uint32_t pair_hist;    /* raduls_sort with 8-bit digits on large inputs: 0 (default) or 1:
+                            the top-level histogram pass also counts the second digit per
+                            top digit, and when the second round's bins are many, of even
+                            size and nowhere constant in that digit, the second round takes
+                            its histograms from those counts instead of reading its bins
+                            again (its scatter then gives each bin one workgroup); 2: never.
+                            Costs 128 KiB of tmp per histogram workgroup (at most 128 MiB) */
+  uint32_t reserved[9];
 } raduls_tuning;
 
 /* Device-side counters left in the workspace by the last sort that used it. */
@@ -88,6 +95,9 @@ typedef struct raduls_stats {
   uint32_t copy_jobs;      /* tmp -> recs copies of finished bins */
   uint64_t moved_records;  /* records moved by global scatter passes */
   uint64_t large_records;  /* records in large bins, summed over rounds */
+  uint32_t pair_rounds;    /* 1 if the second round took its histograms from the
+                              top-level digit pair counts (tuning pair_hist) */
+  uint32_t reserved;
 } raduls_stats;
 
 /* Bytes of `tmp` that raduls_sort needs for n records: n*R for the scatter

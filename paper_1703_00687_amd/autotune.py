@@ -27,6 +27,7 @@ SPACE = {
     "mid_frac": [1.0, 0.75, 0.5],       # mid_max as a fraction of the LDS capacity
     "nontemporal": [1, 2],
     "lookback": [0, 1],
+    "pair_hist": [1, 2],
 }
 
 
@@ -134,7 +135,8 @@ def tune(src, key_bytes: int, reps: int = 3, space: dict | None = None, budget_s
     def cand_to_tuning(c):
         return {"digit_bits": c["digit_bits"], "tiny_max": c["tiny_max"],
                 "mid_max": max(64, int(cap * c["mid_frac"]) // 64 * 64),
-                "nontemporal": c["nontemporal"], "lookback": c["lookback"], "grid_blocks": 0}
+                "nontemporal": c["nontemporal"], "lookback": c["lookback"],
+                "pair_hist": c.get("pair_hist", 1), "grid_blocks": 0}
 
     def measure(c):
         t = cand_to_tuning(c)

@@ -40,7 +40,8 @@ class raduls_tuning(ctypes.Structure):
         ("grid_blocks", ctypes.c_uint32),
         ("nontemporal", ctypes.c_uint32),
         ("lookback", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 10),
+        ("pair_hist", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 9),
     ]
 
 
@@ -54,17 +55,20 @@ class raduls_stats(ctypes.Structure):
         ("copy_jobs", ctypes.c_uint32),
         ("moved_records", ctypes.c_uint64),
         ("large_records", ctypes.c_uint64),
+        ("pair_rounds", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
-        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+        return {name: int(getattr(self, name)) for name, _ in self._fields_ if name != "reserved"}
 
 
 class raduls_array(ctypes.Structure):
     _fields_ = [("recs", ctypes.c_void_p), ("tmp", ctypes.c_void_p), ("n", ctypes.c_uint64)]
 
 
-TUNING_FIELDS = ("digit_bits", "tiny_max", "mid_max", "grid_blocks", "nontemporal", "lookback")
+TUNING_FIELDS = ("digit_bits", "tiny_max", "mid_max", "grid_blocks", "nontemporal", "lookback",
+                 "pair_hist")
 
 _lib = None
 

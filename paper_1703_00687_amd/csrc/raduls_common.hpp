@@ -85,6 +85,12 @@ constexpr int kMidEsItems = 5;
 // Most workgroups of the histogram / carry-scan scatter grid.
 constexpr uint32_t kMaxRanges = 4096;
 
+// Second-digit counts of the top-level histogram pass: 2^16 (top digit,
+// second digit) pairs as 16-bit halves of 2^15 words per workgroup, and at
+// most this many workgroups when they are taken.
+constexpr uint32_t kPairWords = 1u << 15;
+constexpr uint32_t kPairRanges = 1024;
+
 // Finished bins that sit in tmp are copied back in chunks of this many records.
 constexpr uint32_t kCopyChunk = 1u << 16;
 
@@ -152,6 +158,8 @@ struct Ctrl {
   uint32_t large_bins;
   uint32_t scattered_bins;
   uint32_t mid_claim;  // LDS-sort jobs handed out beyond the first one per workgroup
+  uint32_t fused;      // 1: this round's histograms came from the top-level pair counts
+  uint32_t pair_rounds;  // rounds that did so
   uint32_t pad;
   unsigned long long moved_records;
   unsigned long long large_records;
@@ -173,6 +181,8 @@ struct Layout {
   uint32_t* wg_flag;      // [cap_ranges] range starts a bin (1) / lies in one bin (2)
   MidJob* mid;
   Bin* copy;
+  uint32_t* pair_part;    // [kPairRanges][kPairWords] per-range packed pair counts
+  uint32_t* pair_hist;    // [2^16] pair counts of the whole array
   uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges;
 };
 
@@ -189,6 +199,8 @@ struct Params {
   uint32_t tile;          // records per scatter tile
   uint32_t nontemporal;
   uint32_t lookback;      // 1: decoupled look-back scatter, 0: carry scan
+  uint32_t pair;          // 1: the top-level histogram also counts digit pairs
+  uint32_t pair_min_bins; // fewest second-round bins that take the pair counts
   uint32_t rounds;
   uint32_t mode;
   uint32_t count;          // arrays

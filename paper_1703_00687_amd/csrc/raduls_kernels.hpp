@@ -4,8 +4,13 @@
 //
 // The sort is an MSD radix sort of fixed-size records (RADULS2, Sec. 3):
 //   round r (large bins):  k_prep     tile counts of the round's bins
-//                          k_hist     per-bin digit histogram (+ key spread)
-//                          k_scatter  stable scatter with decoupled look-back
+//                          k_hist     per-bin digit histogram (+ key spread);
+//                                     at the top level optionally also the
+//                                     (top, second) digit pair counts, which
+//                                     can stand in for round 1's histograms
+//                          k_carry    per-range carries (blocked scan)
+//                          k_scatter_carry / k_scatter (look-back variant)
+//                                     stable scatter into the child bins
 //                          k_classify child bins -> next round / LDS jobs
 //   then                   k_mid      bins that fit in LDS, sorted there; tiny
 //                                     sub-bins by enumeration sort
@@ -389,15 +394,95 @@ static __global__ void __launch_bounds__(256) k_seed_batch(Params P) {
 
 // ------------------------------------------------------------ round: prep
 
-// Tile prefix over the round's large bins (one workgroup).
-static __global__ void __launch_bounds__(1024) k_prep(Params P, uint32_t cur) {
+// Second round of a sort whose top level counted digit pairs (one workgroup
+// of 1024 threads; all threads call).  The round's bins are the large
+// children of the root, in recs order of their top digit d1, each to be split
+// on the second digit, whose counts per d1 are row d1 of pair_hist.  Those
+// rows replace this round's histogram pass when
+//   - no 16-bit pair counter wrapped: for every d1 the row sums to the root's
+//     exact count of d1;
+//   - every bin is a child of the root split on the byte below the top one;
+//   - the bins are many (>= pair_min_bins, at most one per scatter
+//     workgroup) and of even size (largest <= 5/4 of the mean, in tiles),
+//     since the scatter then gives each bin one workgroup;
+//   - no bin is constant in the second digit (such a bin would jump digits).
+// Then the rows, the key spreads (every bit below the bin's digit may
+// differ) and the tile -> bin map are written for the scatter and classify.
+// Returns 1 if so.
+__device__ uint32_t pair_decide(const Params& P, uint32_t cur, uint32_t nb, uint32_t tiles,
+                                uint32_t max_tiles_thread) {
+  __shared__ uint32_t s_pre[kRadix], s_scan[8], s_d1[kRadix], s_ok, s_max;
+  const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const uint32_t* root = P.L.hist[0];  // the root was bin 0 of round 0
+  if (t == 0) {
+    s_ok = 1;
+    s_max = 0;
+  }
+  __syncthreads();
+  atomicMax(&s_max, max_tiles_thread);
+  const uint32_t h0 = t < kRadix ? root[t] : 0u;
+  block_exclusive_scan256(h0, s_pre, s_scan);  // all threads; ends with a barrier
+  const uint32_t bits = 8u * P.K - 8u;
+  bool ok = nb >= P.pair_min_bins && nb <= kRadix && nb <= P.grid_hist &&
+            4ull * s_max * nb <= 5ull * tiles;
+  // pair rows sum to the exact top-digit counts (no counter wrapped)
+  for (uint32_t d1 = wave; ok && d1 < kRadix; d1 += kMidWaves) {
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sum += P.L.pair_hist[d1 * kRadix + lane * 4 + k];
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    if (sum != root[d1]) ok = false;
+  }
+  // each bin: its top digit, a second digit that is not constant
+  for (uint32_t k = wave; ok && k < nb; k += kMidWaves) {
+    const Bin bn = P.L.large[cur][k];
+    uint32_t lo = 0, hi = kRadix;  // last d with s_pre[d] <= start
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_pre[mid] <= bn.start) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t d1 = lo;
+    if (bn.bits != bits || bn.side != 1 || bn.array != 0 || s_pre[d1] != bn.start ||
+        root[d1] != bn.size)
+      ok = false;
+    uint32_t nz = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nz += P.L.pair_hist[d1 * kRadix + lane * 4 + q] != 0u;
+    for (int o = 32; o > 0; o >>= 1) nz += __shfl_xor(nz, o);
+    if (nz < 2) ok = false;
+    if (lane == 0) s_d1[k] = d1;
+  }
+  if (!ok) atomicAnd(&s_ok, 0u);
+  __syncthreads();
+  if (!s_ok) return 0;
+  for (uint32_t k = wave; k < nb; k += kMidWaves) {
+    const uint32_t d1 = s_d1[k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      P.L.hist[cur][uint64_t(k) * kRadix + lane * 4 + q] = P.L.pair_hist[d1 * kRadix + lane * 4 + q];
+    if (lane < 8) {
+      const uint32_t b0 = 64u * lane;
+      P.L.diff[cur][uint64_t(k) * 8 + lane] =
+          bits >= b0 + 64 ? ~0ull : (bits > b0 ? (1ull << (bits - b0)) - 1ull : 0ull);
+    }
+    for (uint32_t tt = P.L.tile_prefix[k] + lane, te = P.L.tile_prefix[k + 1]; tt < te; tt += 64)
+      P.L.tile_bin[tt] = k;
+  }
+  return 1;
+}
+
+// Tile prefix over the round's large bins (one workgroup).  In the second
+// round of a sort whose top level counted digit pairs, also decides whether
+// this round takes its histograms from those counts (see pair_decide).
+static __global__ void __launch_bounds__(1024) k_prep(Params P, uint32_t cur, uint32_t round) {
   __shared__ uint32_t s_part[16];
   __shared__ unsigned long long s_sz[16];
   Ctrl* c = P.L.ctrl;
   const uint32_t nb = min(c->large_count[cur], P.L.cap_large);
   const Bin* bins = P.L.large[cur];
   const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  uint32_t running = 0;
+  uint32_t running = 0, max_tiles = 0;
   unsigned long long records = 0;
   for (uint32_t base = 0; base < nb; base += 1024) {
     const uint32_t i = base + t;
@@ -407,6 +492,7 @@ static __global__ void __launch_bounds__(1024) k_prep(Params P, uint32_t cur) {
       sz = bins[i].size;
       v = (sz + P.tile - 1) / P.tile;
     }
+    max_tiles = max(max_tiles, v);
     const uint32_t inc = wave_inclusive_scan(v);
     unsigned long long s64 = sz;
 #pragma unroll
@@ -426,11 +512,15 @@ static __global__ void __launch_bounds__(1024) k_prep(Params P, uint32_t cur) {
     records += chunk_rec;
     __syncthreads();
   }
+  uint32_t fused = 0;
+  if (t == 0) P.L.tile_prefix[nb] = running;
+  if (P.pair && round == 1) fused = pair_decide(P, cur, nb, running, max_tiles);
   if (t == 0) {
-    P.L.tile_prefix[nb] = running;
     c->round_tiles = running;
     c->ticket = 0;
     c->large_count[cur ^ 1] = 0;
+    c->fused = fused;
+    c->pair_rounds += fused;
     if (nb) {
       c->rounds += 1;
       c->large_bins += nb;
@@ -446,6 +536,11 @@ static __global__ void __launch_bounds__(1024) k_prep(Params P, uint32_t cur) {
 // constant.  Workgroups take contiguous tile ranges and accumulate in LDS,
 // flushing to the bin's global row when the range crosses into the next bin.
 // Also clears the look-back status rows of its tiles and records their bin.
+// With P.pair (top level of a single-array sort, one bin, 8-bit digits) every
+// workgroup also counts the pairs (top digit, second digit) of its range in
+// 16-bit LDS counters and stores them to its row of pair_part; a counter that
+// wraps is caught later because the pair counts of a top digit then fall
+// short of its exact count.
 template <int RW, int KW, int TOP>
 __global__ void __launch_bounds__(kScatterBlock, 8) k_hist(Params P, uint32_t cur) {
   constexpr int ITEMS = scatter_items(RW);
@@ -453,15 +548,26 @@ __global__ void __launch_bounds__(kScatterBlock, 8) k_hist(Params P, uint32_t cu
   constexpr uint32_t TILE = kScatterBlock * ITEMS;
   __shared__ uint32_t s_cnt[W * kRadix];
   __shared__ unsigned long long s_diff[W][KW];
+  extern __shared__ __align__(16) uint32_t s_pair[];  // [kPairWords] with P.pair
 
   const Ctrl* c = P.L.ctrl;
+  const bool pair = TOP && P.pair;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (pair) {  // the pair totals are summed into here after this kernel
+    for (uint32_t q = blockIdx.x * kScatterBlock + tid; q < 2 * kPairWords;
+         q += gridDim.x * kScatterBlock)
+      P.L.pair_hist[q] = 0;
+  }
+  if (!TOP && c->fused) return;  // histograms already taken from the pair counts
   const uint32_t total = c->round_tiles;
   const uint32_t nbins = min(c->large_count[cur], P.L.cap_large);
   if (total == 0) return;
   const uint32_t t0 = uint32_t(uint64_t(total) * blockIdx.x / gridDim.x);
   const uint32_t t1 = uint32_t(uint64_t(total) * (blockIdx.x + 1) / gridDim.x);
   if (t0 >= t1) return;
-  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (pair) {
+    for (uint32_t q = tid; q < kPairWords; q += kScatterBlock) s_pair[q] = 0;
+  }
 
   // clear look-back rows of this range (only that scatter uses them)
   if (P.lookback) {
@@ -572,17 +678,57 @@ __global__ void __launch_bounds__(kScatterBlock, 8) k_hist(Params P, uint32_t cu
         for (int q = 0; q < KW; ++q) dacc[q] |= kc[j][q] ^ key0[q];
       }
     }
+    uint32_t d2[ITEMS];
+    if (pair) {
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) d2[j] = valid[j] ? digit_of<KW>(kc[j], lob - 8, 8) : 0u;
+    }
     if (t + 1 < t1) load_tile(t + 1, kc, tnc);
     uint32_t* wc = s_cnt + wave * kRadix;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j)
       if (valid[j]) atomicAdd(&wc[dg[j]], 1u);
+    if (pair) {
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j)
+        if (valid[j]) atomicAdd(&s_pair[(dg[j] << 7) | (d2[j] >> 1)], 1u << ((d2[j] & 1u) << 4));
+    }
   }
   flush(b, true);
+  if (pair) {  // flush ends with a barrier
+    uint4* dstp = reinterpret_cast<uint4*>(P.L.pair_part + uint64_t(blockIdx.x) * kPairWords);
+    const uint4* srcp = reinterpret_cast<const uint4*>(s_pair);
+    for (uint32_t q = tid; q < kPairWords / 4; q += kScatterBlock) dstp[q] = srcp[q];
+  }
   if (tid == 0) {
     // bit 0: the range starts a bin; bit 1: the whole range lies in one bin
     P.L.wg_flag[blockIdx.x] = (t0 == tp[b_first] ? 1u : 0u) | (b_first == b ? 2u : 0u);
   }
+}
+
+// Sum of the per-range pair counts of the top-level histogram pass: thread
+// (word q, group g) adds word q over the ranges of group g and adds both
+// 16-bit halves, the pairs (d1, 2 * (q & 127)) and (d1, 2 * (q & 127) + 1) of
+// top digit d1 = q >> 7, into pair_hist.  Ranges without tiles wrote nothing.
+constexpr uint32_t kPairGroups = 8;
+static __global__ void __launch_bounds__(256) k_pair_reduce(Params P, uint32_t nranges) {
+  const Ctrl* c = P.L.ctrl;
+  const uint32_t total = c->round_tiles;
+  const uint32_t q = (blockIdx.x % (kPairWords / 256)) * 256 + threadIdx.x;
+  const uint32_t g = blockIdx.x / (kPairWords / 256);
+  const uint32_t h0 = uint32_t(uint64_t(nranges) * g / kPairGroups);
+  const uint32_t h1 = uint32_t(uint64_t(nranges) * (g + 1) / kPairGroups);
+  uint32_t lo = 0, hi = 0;
+#pragma unroll 8
+  for (uint32_t h = h0; h < h1; ++h) {
+    const uint32_t t0 = uint32_t(uint64_t(total) * h / nranges);
+    const uint32_t t1 = uint32_t(uint64_t(total) * (h + 1) / nranges);
+    const uint32_t v = t0 < t1 ? P.L.pair_part[uint64_t(h) * kPairWords + q] : 0u;
+    lo += v & 0xFFFFu;
+    hi += v >> 16;
+  }
+  if (lo) atomicAdd(&P.L.pair_hist[2 * q], lo);
+  if (hi) atomicAdd(&P.L.pair_hist[2 * q + 1], hi);
 }
 
 // Carry of every histogram range: the per-digit count of records of the
@@ -598,7 +744,7 @@ static __global__ void __launch_bounds__(1024) k_carry(Params P, uint32_t nrange
   __shared__ uint32_t s_sum[16], s_flag[16];
   const Ctrl* c = P.L.ctrl;
   const uint32_t total = c->round_tiles;
-  if (total == 0) return;
+  if (total == 0 || c->fused) return;
   const uint32_t d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t per = (nranges + 1023) / 1024;
   uint32_t tail[kPer];
@@ -873,12 +1019,20 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
 
   Ctrl* c = P.L.ctrl;
   const uint32_t total = c->round_tiles;
-  const uint32_t r0 = uint32_t(uint64_t(total) * blockIdx.x / gridDim.x);
-  const uint32_t r1 = uint32_t(uint64_t(total) * (blockIdx.x + 1) / gridDim.x);
+  uint32_t r0 = uint32_t(uint64_t(total) * blockIdx.x / gridDim.x);
+  uint32_t r1 = uint32_t(uint64_t(total) * (blockIdx.x + 1) / gridDim.x);
+  // histograms from the pair counts: workgroup i sorts the whole bin i
+  const bool whole_bin = !TOP && c->fused;
+  if (whole_bin) {
+    const uint32_t nbins = min(c->large_count[cur], P.L.cap_large);
+    r0 = blockIdx.x < nbins ? P.L.tile_prefix[blockIdx.x] : 0u;
+    r1 = blockIdx.x < nbins ? P.L.tile_prefix[blockIdx.x + 1] : 0u;
+  }
   if (r0 >= r1) return;
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const bool nt = P.nontemporal != 2;
-  uint32_t running = tid < kRadix ? P.L.wg_carry[uint64_t(blockIdx.x) * kRadix + tid] : 0;
+  uint32_t running =
+      tid < kRadix && !whole_bin ? P.L.wg_carry[uint64_t(blockIdx.x) * kRadix + tid] : 0u;
   uint64_t lcst = 0;   // thread d: global index of the first buffered record of digit d
   uint32_t lcnt = 0;   // thread d: buffered records of digit d
   bool lines_on = false;  // the destination's lines align with records
@@ -1966,6 +2120,7 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
   set_lds_limit<k_scatter<RW, KW, 1, 1>>(P.scatter_lds_bytes);
   set_lds_limit<k_scatter<RW, KW, 0, 1>>(P.scatter_lds_bytes);
   set_lds_limit<k_mid<RW, KW>>(P.mid_lds_bytes);
+  if (P.pair) set_lds_limit<k_hist<RW, KW, 1>>(kPairWords * 4);
   if (P.mode == kModeBatch) {
     k_zero_ctrl<<<1, 64, 0, s>>>(P);
     const uint32_t g = P.count ? (P.count + 255) / 256 : 1;
@@ -1974,7 +2129,7 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
     k_seed_single<<<1, 64, 0, s>>>(P);
   }
   if (P.mode == kModeHist || P.mode == kModePartition) {
-    k_prep<<<1, 1024, 0, s>>>(P, 0);
+    k_prep<<<1, 1024, 0, s>>>(P, 0, 0);
     k_hist<RW, KW, 1><<<P.grid_hist, kScatterBlock, 0, s>>>(P, 0);
     if (P.mode == kModePartition) launch_scatter<RW, KW, 1>(P, 0, s);
     k_step_out<<<1, 256, 0, s>>>(P);
@@ -1983,10 +2138,14 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
   for (uint32_t r = 0; r < P.rounds; ++r) {
     const uint32_t cur = r & 1;
     const uint32_t slot = r == 0 ? kProfTopHist : kProfRoundHist;
-    k_prep<<<1, 1024, 0, s>>>(P, cur);
+    k_prep<<<1, 1024, 0, s>>>(P, cur, r);
     if (r <= 1) prof_mark(slot, 0, s);
-    if (r == 0) k_hist<RW, KW, 1><<<P.grid_hist, kScatterBlock, 0, s>>>(P, cur);
-    else k_hist<RW, KW, 0><<<P.grid_hist, kScatterBlock, 0, s>>>(P, cur);
+    if (r == 0) {
+      k_hist<RW, KW, 1><<<P.grid_hist, kScatterBlock, P.pair ? kPairWords * 4 : 0, s>>>(P, cur);
+      if (P.pair) k_pair_reduce<<<(kPairWords / 256) * kPairGroups, 256, 0, s>>>(P, P.grid_hist);
+    } else {
+      k_hist<RW, KW, 0><<<P.grid_hist, kScatterBlock, 0, s>>>(P, cur);
+    }
     if (r <= 1) prof_mark(slot, 1, s);
     if (r <= 1) prof_mark(slot + 1, 0, s);
     if (r == 0) launch_scatter<RW, KW, 1>(P, cur, s);

@@ -37,7 +37,7 @@ raduls_tuning current_tuning() {
 uint32_t mid_capacity(uint32_t rw, uint32_t kw) { return mid_cap(int(rw), int(kw)); }
 
 struct Eff {  // tuning after defaults and clamps, for one record width
-  uint32_t digit_bits, tiny_max, mid_max, tile, nontemporal, grid_blocks, lookback;
+  uint32_t digit_bits, tiny_max, mid_max, tile, nontemporal, grid_blocks, lookback, pair_hist;
 };
 
 Eff effective(const raduls_tuning& t, uint32_t R, uint32_t K) {
@@ -55,13 +55,22 @@ Eff effective(const raduls_tuning& t, uint32_t R, uint32_t K) {
   e.nontemporal = t.nontemporal ? t.nontemporal : 1;
   e.grid_blocks = t.grid_blocks;
   e.lookback = t.lookback ? 1 : 0;
+  e.pair_hist = t.pair_hist == 2 ? 0 : 1;
   return e;
 }
 
+// Whether a single-array sort of n records counts digit pairs at the top
+// level: 8-bit digits, at least two key bytes, the carry-scan scatter, and
+// enough records that the second round's bins are likely large.
+bool use_pair(const Eff& e, uint64_t n, uint32_t K) {
+  return e.pair_hist && e.digit_bits == 8 && K >= 2 && !e.lookback &&
+         n > 256ull * uint64_t(e.mid_max);
+}
+
 struct Shape {
-  uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges, rounds;
+  uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges, rounds, pair;
   uint64_t off_ctrl, off_arrays, off_large[2], off_hist[2], off_diff[2], off_tp, off_tb, off_status,
-      off_tail, off_carry, off_flag, off_mid, off_copy, bytes;
+      off_tail, off_carry, off_flag, off_mid, off_copy, off_pair_part, off_pair_hist, bytes;
 };
 
 // Capacities of the device lists.  Large bins of one round are disjoint and
@@ -70,8 +79,9 @@ struct Shape {
 // a parent's greedy packing yields at most 2*small/mid_max + (large children)
 // + 2 jobs.  Copy jobs: every record is copied at most once, in chunks.
 Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const Eff& e,
-                 bool step) {
+                 bool step, bool pair = false) {
   Shape s{};
+  s.pair = pair ? 1 : 0;
   const uint64_t T = e.mid_max;
   s.rounds = step ? 1 : (8 * K + e.digit_bits - 1) / e.digit_bits;
   const uint64_t large = step ? 1 : n_total / (T + 1) + 1;
@@ -104,6 +114,11 @@ Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const
   s.off_flag = take(uint64_t(s.cap_ranges) * 4);
   s.off_mid = take(uint64_t(s.cap_mid) * sizeof(MidJob));
   s.off_copy = take(uint64_t(s.cap_copy) * sizeof(Bin));
+  // per-range pair counts, one row per histogram workgroup (at most
+  // kPairRanges of them when pairs are counted), and their sum
+  const uint64_t pair_rows = pair ? std::min<uint64_t>(s.cap_ranges, kPairRanges) : 0;
+  s.off_pair_part = take(pair_rows * kPairWords * 4);
+  s.off_pair_hist = take(pair ? 2ull * kPairWords * 4 : 0);
   s.bytes = o;
   return s;
 }
@@ -126,6 +141,8 @@ Layout make_layout(uint8_t* aux, const Shape& s) {
   L.cap_ranges = s.cap_ranges;
   L.mid = reinterpret_cast<MidJob*>(aux + s.off_mid);
   L.copy = reinterpret_cast<Bin*>(aux + s.off_copy);
+  L.pair_part = reinterpret_cast<uint32_t*>(aux + s.off_pair_part);
+  L.pair_hist = reinterpret_cast<uint32_t*>(aux + s.off_pair_hist);
   L.cap_large = s.cap_large;
   L.cap_tiles = s.cap_tiles;
   L.cap_mid = s.cap_mid;
@@ -199,6 +216,11 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
   const DevInfo d = device_info();
   const uint32_t cus = uint32_t(d.cus);
   P.grid_hist = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_ranges, 4 * cus));
+  if (s.pair) {
+    P.pair = 1;
+    P.grid_hist = std::min<uint32_t>(P.grid_hist, kPairRanges);
+    P.pair_min_bins = std::max<uint32_t>(1, cus * 3 / 4);
+  }
   P.grid_scatter = e.grid_blocks ? e.grid_blocks
                                  : std::max<uint32_t>(1, std::min<uint32_t>(s.cap_tiles, 2 * cus));
   P.grid_classify = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_large, 4 * cus));
@@ -240,7 +262,7 @@ int raduls_tmp_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint64_
   if (!out_bytes) return RADULS_E_INVALID;
   if (n >= (1ull << 32)) return RADULS_E_UNSUPPORTED;
   const Eff e = effective(current_tuning(), rec_bytes, key_bytes);
-  const Shape s = plan_shape(n, 1, rec_bytes, key_bytes, e, false);
+  const Shape s = plan_shape(n, 1, rec_bytes, key_bytes, e, false, use_pair(e, n, key_bytes));
   *out_bytes = aux_offset(n, rec_bytes) + s.bytes;
   return RADULS_OK;
 }
@@ -254,7 +276,7 @@ int raduls_sort(void* recs, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t 
   if (!recs || !tmp) return RADULS_E_INVALID;
   if (misaligned(recs) || misaligned(tmp)) return RADULS_E_ALIGN;
   const Eff e = effective(current_tuning(), rec_bytes, key_bytes);
-  const Shape s = plan_shape(n, 1, rec_bytes, key_bytes, e, false);
+  const Shape s = plan_shape(n, 1, rec_bytes, key_bytes, e, false, use_pair(e, n, key_bytes));
   const uint64_t need = aux_offset(n, rec_bytes) + s.bytes;
   if (overlap(recs, n * rec_bytes, tmp, need)) return RADULS_E_INVALID;
   st = check_room(tmp, need);
@@ -369,6 +391,7 @@ int raduls_check(const void* tmp_or_ws, uint64_t n, uint32_t rec_bytes, int ws_o
   stats->copy_jobs = c.copy_count;
   stats->moved_records = c.moved_records;
   stats->large_records = c.large_records;
+  stats->pair_rounds = c.pair_rounds;
   return c.error ? RADULS_E_DEVICE : RADULS_OK;
 }
 

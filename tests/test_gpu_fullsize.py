@@ -139,6 +139,7 @@ def test_uniform16_full():
     inp = wl.uniform16_torch(n)
     out, stats = _sort_full(inp, 8)
     assert stats["rounds"] >= 2
+    assert stats["pair_rounds"] == 1  # round 2 took the top level's pair counts
     check_stable_device(out, inp, 2, 1, 1)
     sample_windows(out, inp, 2, 1, 8)
 
@@ -158,6 +159,30 @@ def test_deep32_full():
     assert stats["rounds"] >= 3  # the high key word forces deep recursion
     check_stable_device(out, inp, 4, 2, 2)
     sample_windows(out, inp, 4, 2, 16, seed=2)
+
+
+def test_pair_counter_wrap_detected():
+    """2^27 records whose every histogram range is dominated by one (top,
+    second) digit pair -- more than 2^16 records of it per range, so its
+    16-bit counter wraps -- while over the whole array the 256 top digits
+    stay equally frequent and no bin is constant in the second digit.  The
+    wrap must be caught (the pair counts are declined) and the sort stay
+    exact."""
+    n = 1 << 27
+    dev = torch.device("cuda:0")
+    idx = torch.arange(n, dtype=torch.int64, device=dev)
+    h = idx // (1 << 17)
+    top16 = ((h % 256) << 8) | (h // 256)
+    low = wl.splitmix64_torch(wl.stream_seed(9, 0), 0, n, dev) & ((1 << 48) - 1)
+    w = torch.empty((n, 2), dtype=torch.int64, device=dev)
+    w[:, 0] = (top16 << 48) | low
+    w[:, 1] = idx
+    del idx, h, top16, low
+    inp = w.view(torch.uint8).view(n, 16)
+    out, stats = _sort_full(inp, 8)
+    assert stats["pair_rounds"] == 0, stats
+    check_stable_device(out, inp, 2, 1, 1)
+    sample_windows(out, inp, 2, 1, 8, seed=5)
 
 
 def test_keys16_full():

@@ -83,6 +83,44 @@ def test_record_size_sweep_reduced(r, k):
     assert stats["rounds"] >= 1
 
 
+@pytest.mark.parametrize("r,k", [(16, 8), (8, 2), (16, 16), (24, 13), (32, 16)])
+def test_pair_counts_on_and_off(r, k):
+    """Inputs large enough that the top level counts (top, second) digit
+    pairs and the second round takes its histograms from them; the result
+    must be the same with that path switched off."""
+    n = 1 << 22
+    inp = _recs(77 + r + k, n, r, k)
+    for pair, used in ((0, 1), (2, 0)):
+        with tuned(pair_hist=pair):
+            out, stats = gpu_sort(inp, k)
+        _assert_parity(out, inp, k)
+        assert stats["pair_rounds"] == used, stats
+
+
+def test_pair_counts_declined_for_uneven_bins():
+    """Skewed keys make the second round's bins uneven (one holds a fifth of
+    the records): the pair counts are not used, and the sort is unchanged."""
+    n = 1 << 22
+    inp = _recs(5, n, 16, 8)
+    heavy = np.random.default_rng(6).random(n) < 0.2
+    inp[heavy, 7] = 0x5A
+    out, stats = gpu_sort(inp, 8)
+    _assert_parity(out, inp, 8)
+    assert stats["pair_rounds"] == 0, stats
+
+
+def test_pair_counts_declined_for_constant_second_digit():
+    """One top digit whose records all share the second key byte: that bin
+    would have to jump digits, so the pair counts are not used."""
+    n = 1 << 22
+    inp = _recs(8, n, 16, 8)
+    sel = inp[:, 7] == 0x33
+    inp[sel, 6] = 0x44
+    out, stats = gpu_sort(inp, 8)
+    _assert_parity(out, inp, 8)
+    assert stats["pair_rounds"] == 0, stats
+
+
 def _adversarial(r, k, n, seed):
     rng = np.random.default_rng(seed)
     base = wl.random_records(rng, n, r, k)
