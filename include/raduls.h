@@ -76,7 +76,7 @@ typedef struct raduls_tuning {
                             size and nowhere constant in that digit, the second round takes
                             its histograms from those counts instead of reading its bins
                             again (its scatter then gives each bin one workgroup); 2: never.
-                            Costs 128 KiB of tmp per histogram workgroup (at most 128 MiB) */
+                            Costs 128 KiB of tmp per histogram workgroup (at most 64 MiB) */
   uint32_t reserved[9];
 } raduls_tuning;
 

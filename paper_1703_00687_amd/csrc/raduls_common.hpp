@@ -89,7 +89,7 @@ constexpr uint32_t kMaxRanges = 4096;
 // second digit) pairs as 16-bit halves of 2^15 words per workgroup, and at
 // most this many workgroups when they are taken.
 constexpr uint32_t kPairWords = 1u << 15;
-constexpr uint32_t kPairRanges = 1024;
+constexpr uint32_t kPairRanges = 512;
 
 // Finished bins that sit in tmp are copied back in chunks of this many records.
 constexpr uint32_t kCopyChunk = 1u << 16;

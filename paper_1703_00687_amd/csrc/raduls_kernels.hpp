@@ -536,22 +536,23 @@ static __global__ void __launch_bounds__(1024) k_prep(Params P, uint32_t cur, ui
 // constant.  Workgroups take contiguous tile ranges and accumulate in LDS,
 // flushing to the bin's global row when the range crosses into the next bin.
 // Also clears the look-back status rows of its tiles and records their bin.
-// With P.pair (top level of a single-array sort, one bin, 8-bit digits) every
-// workgroup also counts the pairs (top digit, second digit) of its range in
-// 16-bit LDS counters and stores them to its row of pair_part; a counter that
-// wraps is caught later because the pair counts of a top digit then fall
-// short of its exact count.
+// TOP: 0 for later rounds, 1 for the top level, 2 for the top level of a
+// single-array sort with 8-bit digits that also counts the pairs (top digit,
+// second digit) of each range in 16-bit LDS counters and stores them to the
+// range's row of pair_part (a counter that wraps is caught later because the
+// pair counts of a top digit then fall short of its exact count).  Those
+// counters fill the LDS, so that variant runs one workgroup per CU.
 template <int RW, int KW, int TOP>
-__global__ void __launch_bounds__(kScatterBlock, 8) k_hist(Params P, uint32_t cur) {
+__global__ void __launch_bounds__(kScatterBlock, TOP == 2 ? 1 : 8) k_hist(Params P, uint32_t cur) {
   constexpr int ITEMS = scatter_items(RW);
   constexpr int W = kScatterWaves;
   constexpr uint32_t TILE = kScatterBlock * ITEMS;
+  constexpr bool pair = TOP == 2;
   __shared__ uint32_t s_cnt[W * kRadix];
   __shared__ unsigned long long s_diff[W][KW];
-  extern __shared__ __align__(16) uint32_t s_pair[];  // [kPairWords] with P.pair
+  extern __shared__ __align__(16) uint32_t s_pair[];  // [kPairWords] when pair
 
   const Ctrl* c = P.L.ctrl;
-  const bool pair = TOP && P.pair;
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (pair) {  // the pair totals are summed into here after this kernel
     for (uint32_t q = blockIdx.x * kScatterBlock + tid; q < 2 * kPairWords;
@@ -627,41 +628,62 @@ __global__ void __launch_bounds__(kScatterBlock, 8) k_hist(Params P, uint32_t cu
   uint64_t key0[KW];
   key_of<KW>(gmem(reinterpret_cast<const uint64_t*>(src)) + uint64_t(bin.start) * RW, P.kmask, key0);
 
-  // the tile to load: its bin (bl), its records and where they come from
+  // the tile to load: its bin (bl) and that bin's tiles, records and source,
+  // kept in registers so that the loads of a tile wait for nothing (a load of
+  // a descriptor would wait for every key load still in flight); they are
+  // reread only when the tiles cross into the next bin
   uint32_t bl = b;
+  uint32_t bl_first = tp[b], bl_end = b + 1 < nbins ? tp[b + 1] : 0xFFFFFFFFu;
+  uint32_t bl_start = bin.start, bl_size = bin.size;
+  const uint8_t* bl_src = src;
   auto load_tile = [&](uint32_t t, uint64_t (&kt)[ITEMS][KW], uint32_t& tn_out) {
-    while (bl + 1 < nbins && t >= tp[bl + 1]) ++bl;
-    const Bin bb = P.L.large[cur][bl];
-    const ArrayDesc aa = P.L.arrays[bb.array];
-    const RADULS_GLOBAL uint64_t* sw =
-        gmem(reinterpret_cast<const uint64_t*>(bb.side ? aa.tmp : aa.recs));
-    const uint32_t k = t - tp[bl];
-    const uint32_t tbeg = bb.start + k * TILE;
-    const uint32_t tn = min(TILE, bb.size - k * TILE);
+    if (t >= bl_end) {
+      while (bl + 1 < nbins && t >= tp[bl + 1]) ++bl;
+      bl_first = tp[bl];
+      bl_end = bl + 1 < nbins ? tp[bl + 1] : 0xFFFFFFFFu;
+      const Bin bb = P.L.large[cur][bl];
+      const ArrayDesc aa = P.L.arrays[bb.array];
+      bl_src = bb.side ? aa.tmp : aa.recs;
+      bl_start = bb.start;
+      bl_size = bb.size;
+    }
+    const RADULS_GLOBAL uint64_t* sw = gmem(reinterpret_cast<const uint64_t*>(bl_src));
+    const uint32_t k = t - bl_first;
+    const uint32_t tbeg = bl_start + k * TILE;
+    const uint32_t tn = min(TILE, bl_size - k * TILE);
     const uint32_t ipw = (tn + kWave * W - 1) / (kWave * W);
     tn_out = tn;
+    // Raw, unconditional loads (lanes past the tile reread its last record,
+    // which is not counted): a load under a branch, or masking the top word
+    // here, would make the loads wait at once instead of when the tile is
+    // counted.
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       const uint32_t i = wave * ipw * kWave + j * kWave + lane;
+      const uint32_t ii = (uint32_t(j) < ipw && i < tn) ? i : tn - 1u;
+      const RADULS_GLOBAL uint64_t* kp = sw + uint64_t(tbeg + ii) * RW;
 #pragma unroll
-      for (int q = 0; q < KW; ++q) kt[j][q] = 0;
-      if (uint32_t(j) < ipw && i < tn) key_of<KW>(sw + uint64_t(tbeg + i) * RW, P.kmask, kt[j]);
+      for (int q = 0; q < KW; ++q) kt[j][q] = kp[q];
     }
   };
-  uint64_t kc[ITEMS][KW];
-  uint32_t tnc = 0;
-  load_tile(t0, kc, tnc);
+  uint64_t kt[ITEMS][KW];
+  uint32_t tnr = 0;
+  load_tile(t0, kt, tnr);
+  uint32_t b_end = b + 1 < nbins ? tp[b + 1] : 0xFFFFFFFFu;
   for (uint32_t t = t0; t < t1; ++t) {
-    while (b + 1 < nbins && t >= tp[b + 1]) {
-      flush(b, false);
-      ++b;
-      bin = P.L.large[cur][b];
-      arr = P.L.arrays[bin.array];
-      src = bin.side ? arr.tmp : arr.recs;
-      key_of<KW>(gmem(reinterpret_cast<const uint64_t*>(src)) + uint64_t(bin.start) * RW, P.kmask, key0);
+    if (t >= b_end) {
+      while (b + 1 < nbins && t >= tp[b + 1]) {
+        flush(b, false);
+        ++b;
+        bin = P.L.large[cur][b];
+        arr = P.L.arrays[bin.array];
+        src = bin.side ? arr.tmp : arr.recs;
+        key_of<KW>(gmem(reinterpret_cast<const uint64_t*>(src)) + uint64_t(bin.start) * RW, P.kmask, key0);
+      }
+      b_end = b + 1 < nbins ? tp[b + 1] : 0xFFFFFFFFu;
     }
     if (tid == 0) P.L.tile_bin[t] = b;
-    const uint32_t tn = tnc;
+    const uint32_t tn = tnr;
     const uint32_t ipw = (tn + kWave * W - 1) / (kWave * W);
     const uint32_t w = min(P.digit_bits, uint32_t(bin.bits));
     const uint32_t lob = bin.bits - w;
@@ -672,18 +694,19 @@ __global__ void __launch_bounds__(kScatterBlock, 8) k_hist(Params P, uint32_t cu
       const uint32_t i = wave * ipw * kWave + j * kWave + lane;
       valid[j] = (uint32_t(j) < ipw) && (i < tn);
       dg[j] = 0;
+      kt[j][KW - 1] &= P.kmask;
       if (valid[j]) {
-        dg[j] = digit_of<KW>(kc[j], lob, w);
+        dg[j] = digit_of<KW>(kt[j], lob, w);
 #pragma unroll
-        for (int q = 0; q < KW; ++q) dacc[q] |= kc[j][q] ^ key0[q];
+        for (int q = 0; q < KW; ++q) dacc[q] |= kt[j][q] ^ key0[q];
       }
     }
     uint32_t d2[ITEMS];
     if (pair) {
 #pragma unroll
-      for (int j = 0; j < ITEMS; ++j) d2[j] = valid[j] ? digit_of<KW>(kc[j], lob - 8, 8) : 0u;
+      for (int j = 0; j < ITEMS; ++j) d2[j] = valid[j] ? digit_of<KW>(kt[j], lob - 8, 8) : 0u;
     }
-    if (t + 1 < t1) load_tile(t + 1, kc, tnc);
+    if (t + 1 < t1) load_tile(t + 1, kt, tnr);
     uint32_t* wc = s_cnt + wave * kRadix;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j)
@@ -2120,7 +2143,7 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
   set_lds_limit<k_scatter<RW, KW, 1, 1>>(P.scatter_lds_bytes);
   set_lds_limit<k_scatter<RW, KW, 0, 1>>(P.scatter_lds_bytes);
   set_lds_limit<k_mid<RW, KW>>(P.mid_lds_bytes);
-  if (P.pair) set_lds_limit<k_hist<RW, KW, 1>>(kPairWords * 4);
+  if (P.pair) set_lds_limit<k_hist<RW, KW, 2>>(kPairWords * 4);
   if (P.mode == kModeBatch) {
     k_zero_ctrl<<<1, 64, 0, s>>>(P);
     const uint32_t g = P.count ? (P.count + 255) / 256 : 1;
@@ -2140,9 +2163,11 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
     const uint32_t slot = r == 0 ? kProfTopHist : kProfRoundHist;
     k_prep<<<1, 1024, 0, s>>>(P, cur, r);
     if (r <= 1) prof_mark(slot, 0, s);
-    if (r == 0) {
-      k_hist<RW, KW, 1><<<P.grid_hist, kScatterBlock, P.pair ? kPairWords * 4 : 0, s>>>(P, cur);
-      if (P.pair) k_pair_reduce<<<(kPairWords / 256) * kPairGroups, 256, 0, s>>>(P, P.grid_hist);
+    if (r == 0 && P.pair) {
+      k_hist<RW, KW, 2><<<P.grid_hist, kScatterBlock, kPairWords * 4, s>>>(P, cur);
+      k_pair_reduce<<<(kPairWords / 256) * kPairGroups, 256, 0, s>>>(P, P.grid_hist);
+    } else if (r == 0) {
+      k_hist<RW, KW, 1><<<P.grid_hist, kScatterBlock, 0, s>>>(P, cur);
     } else {
       k_hist<RW, KW, 0><<<P.grid_hist, kScatterBlock, 0, s>>>(P, cur);
     }
