@@ -183,6 +183,7 @@ struct Layout {
   Bin* copy;
   uint32_t* pair_part;    // [kPairRanges][kPairWords] per-range packed pair counts
   uint32_t* pair_hist;    // [2^16] pair counts of the whole array
+  uint32_t* pair_d1;      // [kRadix] top digit of each second-round bin (when used)
   uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges;
 };
 

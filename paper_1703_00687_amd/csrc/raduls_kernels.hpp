@@ -406,13 +406,13 @@ static __global__ void __launch_bounds__(256) k_seed_batch(Params P) {
 //     workgroup) and of even size (largest <= 5/4 of the mean, in tiles),
 //     since the scatter then gives each bin one workgroup;
 //   - no bin is constant in the second digit (such a bin would jump digits).
-// Then the rows, the key spreads (every bit below the bin's digit may
-// differ) and the tile -> bin map are written for the scatter and classify.
-// Returns 1 if so.
+// Then every bin's top digit goes to pair_d1, where the scatter and classify
+// of this round find the bin's row of pair_hist (and take every key bit
+// below the bin's digit as possibly differing).  Returns 1 if so.
 __device__ uint32_t pair_decide(const Params& P, uint32_t cur, uint32_t nb, uint32_t tiles,
                                 uint32_t max_tiles_thread) {
-  __shared__ uint32_t s_pre[kRadix], s_scan[8], s_d1[kRadix], s_ok, s_max;
-  const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  __shared__ uint32_t s_pre[kRadix], s_scan[8], s_d1[kRadix], s_nz[kRadix], s_ok, s_max;
+  const uint32_t t = threadIdx.x;
   const uint32_t* root = P.L.hist[0];  // the root was bin 0 of round 0
   if (t == 0) {
     s_ok = 1;
@@ -423,52 +423,49 @@ __device__ uint32_t pair_decide(const Params& P, uint32_t cur, uint32_t nb, uint
   const uint32_t h0 = t < kRadix ? root[t] : 0u;
   block_exclusive_scan256(h0, s_pre, s_scan);  // all threads; ends with a barrier
   const uint32_t bits = 8u * P.K - 8u;
-  bool ok = nb >= P.pair_min_bins && nb <= kRadix && nb <= P.grid_hist &&
-            4ull * s_max * nb <= 5ull * tiles;
-  // pair rows sum to the exact top-digit counts (no counter wrapped)
-  for (uint32_t d1 = wave; ok && d1 < kRadix; d1 += kMidWaves) {
-    uint32_t sum = 0;
+  if (t == 0 && !(nb >= P.pair_min_bins && nb <= kRadix && nb <= P.grid_hist &&
+                  4ull * s_max * nb <= 5ull * tiles))
+    s_ok = 0;
+  // row d1 = t / 4 of the pair counts, a quarter per thread: its sum must be
+  // the root's exact count of d1 (no counter wrapped), and its non-zero
+  // entries say whether the second digit is constant in that bin
+  {
+    const uint32_t d1 = t >> 2, qq = t & 3;
+    const uint4* rowp = reinterpret_cast<const uint4*>(P.L.pair_hist + d1 * kRadix + qq * 64);
+    uint32_t sum = 0, nz = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sum += P.L.pair_hist[d1 * kRadix + lane * 4 + k];
-    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
-    if (sum != root[d1]) ok = false;
+    for (int k = 0; k < 16; ++k) {
+      const uint4 v = rowp[k];
+      sum += v.x + v.y + v.z + v.w;
+      nz += (v.x != 0u) + (v.y != 0u) + (v.z != 0u) + (v.w != 0u);
+    }
+    sum += __shfl_xor(sum, 1);
+    sum += __shfl_xor(sum, 2);
+    nz += __shfl_xor(nz, 1);
+    nz += __shfl_xor(nz, 2);
+    if (qq == 0) {
+      s_nz[d1] = nz;
+      if (sum != root[d1]) atomicAnd(&s_ok, 0u);
+    }
   }
-  // each bin: its top digit, a second digit that is not constant
-  for (uint32_t k = wave; ok && k < nb; k += kMidWaves) {
-    const Bin bn = P.L.large[cur][k];
-    uint32_t lo = 0, hi = kRadix;  // last d with s_pre[d] <= start
+  __syncthreads();
+  // bin t: its top digit (the last d with s_pre[d] <= start), and checks
+  if (t < nb && t < kRadix) {
+    const Bin bn = P.L.large[cur][t];
+    uint32_t lo = 0, hi = kRadix;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
       if (s_pre[mid] <= bn.start) lo = mid;
       else hi = mid;
     }
-    const uint32_t d1 = lo;
-    if (bn.bits != bits || bn.side != 1 || bn.array != 0 || s_pre[d1] != bn.start ||
-        root[d1] != bn.size)
-      ok = false;
-    uint32_t nz = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) nz += P.L.pair_hist[d1 * kRadix + lane * 4 + q] != 0u;
-    for (int o = 32; o > 0; o >>= 1) nz += __shfl_xor(nz, o);
-    if (nz < 2) ok = false;
-    if (lane == 0) s_d1[k] = d1;
+    s_d1[t] = lo;
+    if (bn.bits != bits || bn.side != 1 || bn.array != 0 || s_pre[lo] != bn.start ||
+        root[lo] != bn.size || s_nz[lo] < 2)
+      atomicAnd(&s_ok, 0u);
   }
-  if (!ok) atomicAnd(&s_ok, 0u);
   __syncthreads();
   if (!s_ok) return 0;
-  for (uint32_t k = wave; k < nb; k += kMidWaves) {
-    const uint32_t d1 = s_d1[k];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      P.L.hist[cur][uint64_t(k) * kRadix + lane * 4 + q] = P.L.pair_hist[d1 * kRadix + lane * 4 + q];
-    if (lane < 8) {
-      const uint32_t b0 = 64u * lane;
-      P.L.diff[cur][uint64_t(k) * 8 + lane] =
-          bits >= b0 + 64 ? ~0ull : (bits > b0 ? (1ull << (bits - b0)) - 1ull : 0ull);
-    }
-    for (uint32_t tt = P.L.tile_prefix[k] + lane, te = P.L.tile_prefix[k + 1]; tt < te; tt += 64)
-      P.L.tile_bin[tt] = k;
-  }
+  if (t < nb) P.L.pair_d1[t] = s_d1[t];
   return 1;
 }
 
@@ -1067,7 +1064,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
   uint8_t* dst = nullptr;
   bool active = false;
   auto enter_bin = [&](uint32_t t) {
-    b = P.L.tile_bin[t];
+    b = whole_bin ? blockIdx.x : P.L.tile_bin[t];
     bin = P.L.large[cur][b];
     const ArrayDesc arr = P.L.arrays[bin.array];
     src = bin.side ? arr.tmp : arr.recs;
@@ -1076,12 +1073,14 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
     w = min(P.digit_bits, uint32_t(bin.bits));
     lob = bin.bits - w;
     nb = 1u << w;
-    const uint32_t h = tid < nb ? P.L.hist[cur][uint64_t(b) * kRadix + tid] : 0;
+    const uint32_t* hrow = whole_bin ? P.L.pair_hist + P.L.pair_d1[b] * kRadix
+                                     : P.L.hist[cur] + uint64_t(b) * kRadix;
+    const uint32_t h = tid < nb ? hrow[tid] : 0;
     active = true;
     if (P.mode != kModePartition) {
-      uint64_t any = 0;
+      uint64_t any = whole_bin ? 1u : 0u;  // (a bin of pair counts is never constant)
 #pragma unroll
-      for (int i = 0; i < KW; ++i) any |= P.L.diff[cur][uint64_t(b) * 8 + i];
+      for (int i = 0; i < KW; ++i) any |= whole_bin ? 0ull : P.L.diff[cur][uint64_t(b) * 8 + i];
       // all keys equal, or a digit shared by the whole bin: nothing moves
       active = any != 0 && !__syncthreads_or(tid < nb && h == bin.size);
     }
@@ -1115,7 +1114,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
     uint32_t dg[ITEMS];
     bool valid[ITEMS];
     const uint32_t next = t + 1;
-    const bool same = next < r1 && P.L.tile_bin[next] == b;
+    const bool same = next < r1 && (whole_bin || P.L.tile_bin[next] == b);
     if (active) {
       // the tile into LDS in input order and its digits into registers; the
       // registers are then free for the next tile's loads, which stay in
@@ -1277,15 +1276,24 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
     const uint32_t w = min(P.digit_bits, uint32_t(bin.bits));
     const uint32_t lob = bin.bits - w;
     const uint32_t nb = 1u << w;
+    // with pair counts (second round only) the bin's row is its top digit's
+    // row of pair_hist, and any key bit below the bin's digit may differ
+    const bool fused = c->fused != 0;
     uint64_t dif[KW];
 #pragma unroll
-    for (int i = 0; i < KW; ++i) dif[i] = P.L.diff[cur][uint64_t(b) * 8 + i];
+    for (int i = 0; i < KW; ++i) {
+      const uint32_t b0 = 64u * uint32_t(i), bits = bin.bits;
+      dif[i] = fused ? (bits >= b0 + 64 ? ~0ull : (bits > b0 ? (1ull << (bits - b0)) - 1ull : 0ull))
+                     : P.L.diff[cur][uint64_t(b) * 8 + i];
+    }
     const int tb = top_bit<KW>(dif);
     if (tb < 0) {  // every key equal: finished where it is
       if (tid == 0 && bin.side == 1) push_copy(P, bin.array, bin.start, bin.size);
       continue;
     }
-    const uint32_t h = tid < nb ? P.L.hist[cur][uint64_t(b) * kRadix + tid] : 0;
+    const uint32_t* hrow = fused ? P.L.pair_hist + P.L.pair_d1[b] * kRadix
+                                 : P.L.hist[cur] + uint64_t(b) * kRadix;
+    const uint32_t h = tid < nb ? hrow[tid] : 0;
     if (__syncthreads_or(tid < nb && h == bin.size)) {
       if (tid == 0) {
         Bin nbn = bin;

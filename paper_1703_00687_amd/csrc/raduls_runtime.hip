@@ -70,7 +70,8 @@ bool use_pair(const Eff& e, uint64_t n, uint32_t K) {
 struct Shape {
   uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges, rounds, pair;
   uint64_t off_ctrl, off_arrays, off_large[2], off_hist[2], off_diff[2], off_tp, off_tb, off_status,
-      off_tail, off_carry, off_flag, off_mid, off_copy, off_pair_part, off_pair_hist, bytes;
+      off_tail, off_carry, off_flag, off_mid, off_copy, off_pair_part, off_pair_hist, off_pair_d1,
+      bytes;
 };
 
 // Capacities of the device lists.  Large bins of one round are disjoint and
@@ -119,6 +120,7 @@ Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const
   const uint64_t pair_rows = pair ? std::min<uint64_t>(s.cap_ranges, kPairRanges) : 0;
   s.off_pair_part = take(pair_rows * kPairWords * 4);
   s.off_pair_hist = take(pair ? 2ull * kPairWords * 4 : 0);
+  s.off_pair_d1 = take(pair ? kRadix * 4 : 0);
   s.bytes = o;
   return s;
 }
@@ -143,6 +145,7 @@ Layout make_layout(uint8_t* aux, const Shape& s) {
   L.copy = reinterpret_cast<Bin*>(aux + s.off_copy);
   L.pair_part = reinterpret_cast<uint32_t*>(aux + s.off_pair_part);
   L.pair_hist = reinterpret_cast<uint32_t*>(aux + s.off_pair_hist);
+  L.pair_d1 = reinterpret_cast<uint32_t*>(aux + s.off_pair_d1);
   L.cap_large = s.cap_large;
   L.cap_tiles = s.cap_tiles;
   L.cap_mid = s.cap_mid;
