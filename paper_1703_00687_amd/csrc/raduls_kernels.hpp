@@ -1917,11 +1917,23 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
         uint64_t kp[KW];
         slot_key<KW>(L, src[j], kp);
         uint32_t r = 0;
-        for (uint32_t q = b0; q < b1; ++q) {
-          const uint32_t sq = L.perm[q];
-          uint64_t kq[KW];
-          slot_key<KW>(L, sq, kq);
-          r += (key_lt<KW>(kq, kp) || (sq < src[j] && key_eq<KW>(kq, kp))) ? 1u : 0u;
+        // with multi-word keys four members per step, their slots and then
+        // their keys read together (positions past the bucket reread its
+        // last member and are not counted), so that a bucket of up to four
+        // costs one round trip for the slots and one for the keys; with
+        // one-word keys the extra instructions cost more than they save, and
+        // with more than four words the registers run out
+        constexpr uint32_t kStep = KW >= 2 && KW <= 4 ? 4u : 1u;
+        for (uint32_t q = b0; q < b1; q += kStep) {
+          uint32_t sq[kStep];
+#pragma unroll
+          for (uint32_t u = 0; u < kStep; ++u) sq[u] = L.perm[kStep > 1 ? min(q + u, b1 - 1) : q];
+#pragma unroll
+          for (uint32_t u = 0; u < kStep; ++u) {
+            uint64_t kq[KW];
+            slot_key<KW>(L, sq[u], kq);
+            r += (q + u < b1 && (key_lt<KW>(kq, kp) || (sq[u] < src[j] && key_eq<KW>(kq, kp)))) ? 1u : 0u;
+          }
         }
         fin[j] = b0 + r;
       }
@@ -2005,11 +2017,17 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
         uint64_t kp[KW];
         slot_key<KW>(L, slot[h], kp);
         uint32_t r = 0;
-        for (int q = s; q < e; ++q) {
-          const uint32_t sq = L.perm[q];
-          uint64_t kq[KW];
-          slot_key<KW>(L, sq, kq);
-          r += (key_lt<KW>(kq, kp) || (sq < slot[h] && key_eq<KW>(kq, kp))) ? 1u : 0u;
+        constexpr int kStep = KW >= 2 && KW <= 4 ? 4 : 1;  // as in the first pass
+        for (int q = s; q < e; q += kStep) {
+          uint32_t sq[kStep];
+#pragma unroll
+          for (int u = 0; u < kStep; ++u) sq[u] = L.perm[kStep > 1 ? min(q + u, e - 1) : q];
+#pragma unroll
+          for (int u = 0; u < kStep; ++u) {
+            uint64_t kq[KW];
+            slot_key<KW>(L, sq[u], kq);
+            r += (q + u < e && (key_lt<KW>(kq, kp) || (sq[u] < slot[h] && key_eq<KW>(kq, kp)))) ? 1u : 0u;
+          }
         }
         dst[h] = uint32_t(s) + r;
         act[h] = true;
