@@ -1575,7 +1575,9 @@ __device__ __forceinline__ uint32_t mid_wg_spread(MidLds& L, uint32_t tid, uint6
     for (int q = 0; q < KW; ++q) dk[q] |= L.diff[w2 * (KW + 1) + q];
     as |= L.diff[w2 * (KW + 1) + KW];
   }
-  lds_barrier();  // L.diff is reused by the next call
+  // no barrier here: every path from one call to the next passes barriers
+  // (the pass that follows each call has them), so no wave rewrites L.diff
+  // while another still reads it
   return uint32_t(as);
 }
 
@@ -1953,9 +1955,11 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
       lds_barrier();
     }
     // ranges too large for one wave
+    bool passes = false;  // (uniform: taken from LDS counters after barriers)
     for (;;) {
       const uint32_t nbig = min(s_nbig, kMidBigCap);
       if (nbig == 0) break;
+      passes = true;
       const uint32_t e = s_big[nbig - 1];
       lds_barrier();
       if (tid == 0) s_nbig = nbig - 1;
@@ -1966,6 +1970,7 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
     for (uint32_t cur = 0;; cur ^= 1) {
       const uint32_t nl = min(s_nlist[cur], kMidListCap);
       if (nl == 0) break;
+      passes = true;
       if (tid == 0) {
         s_claim = 0;
         s_nlist[cur ^ 1] = 0;
@@ -1982,7 +1987,7 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
       lds_barrier();
       if (tid == 0) s_nlist[cur] = 0;
     }
-    lds_barrier();
+    if (passes) lds_barrier();  // without later passes perm is complete already
 
     // ---- tiny ranges the later passes produced (inside positions marked in
     // bmb): enumeration sort; everything else is in place.  A range belongs
@@ -2039,11 +2044,11 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
       for (int h = 0; h < kMidEsItems; ++h)
         if (act[h]) L.perm[dst[h]] = uint16_t(slot[h]);
     }
-    lds_barrier();
     // every load issued at the start of this job has landed (all of them,
     // on every path, so that nothing loaded is still counted as in flight
     // when the next job starts and this job's stores are out); then the
-    // descriptor of job i+2 and the index of job i+3
+    // descriptor of job i+2 and the index of job i+3, published by the same
+    // barrier that completes perm
     __builtin_amdgcn_s_waitcnt(0x3F70);  // gfx9 encoding: vmcnt(0), lgkmcnt/expcnt not waited
     MidJob nxt2{};
     if (have2) nxt2 = uni_job(nextv);
