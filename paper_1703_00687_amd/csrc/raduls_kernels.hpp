@@ -1491,10 +1491,27 @@ __device__ __forceinline__ uint32_t pair_get(const uint32_t* cnt, uint32_t d) {
   return (cnt[d >> 1] >> ((d & 1u) << 4)) & 0xFFFFu;
 }
 
+// One non-empty digit's sub-range [st, st + cnt) of a workgroup pass.  In a
+// job's first pass only sub-ranges above tiny_max are routed (the others are
+// finished by the enumeration sort that follows, which needs no boundary
+// bits), and they are marked in bmb and get a boundary bit at their end too,
+// so that the runs later passes cut out of them are bounded on both sides.
+__device__ __forceinline__ void mid_scan_route_one(const Params& P, MidLds& L, uint32_t st,
+                                                   uint32_t cnt, uint32_t wave_cap, bool first) {
+  if (!first) {
+    mid_route(P, L, st, cnt, wave_cap, 0);
+  } else if (cnt > P.tiny_max) {
+    mid_route(P, L, st, cnt, wave_cap, 0);
+    set_bits(L.bmb, st, cnt);
+    const uint32_t e = st + cnt;
+    atomicOr(&L.bm[e >> 5], 1u << (e & 31));
+  }
+}
+
 // Exclusive scan of the nd (even, <= 2 * kMidCounterWords) packed counters
 // in place over the workgroup, routing every non-empty digit's sub-range of
-// the range that starts at s; with `first`, sub-ranges left to later passes
-// are also marked in bmb.  All threads call; ends with a barrier.
+// the range that starts at s (with `first`, only those left to later passes;
+// see mid_scan_route_one).  All threads call; ends with a barrier.
 __device__ __forceinline__ void mid_scan_route(const Params& P, MidLds& L, uint32_t tid, uint32_t s,
                                                uint32_t nd, uint32_t wave_cap, bool first) {
   constexpr int kPer = kMidCounterWords / kMidBlock;
@@ -1518,15 +1535,9 @@ __device__ __forceinline__ void mid_scan_route(const Params& P, MidLds& L, uint3
     if (uint32_t(k) < per && base + k < nw) {
       const uint32_t c0 = v[k] & 0xFFFFu, c1 = v[k] >> 16;
       L.cnt[base + k] = run | ((run + c0) << 16);
-      if (c0) {
-        mid_route(P, L, s + run, c0, wave_cap, 0);
-        if (first && c0 > P.tiny_max) set_bits(L.bmb, s + run, c0);
-      }
+      if (c0) mid_scan_route_one(P, L, s + run, c0, wave_cap, first);
       run += c0;
-      if (c1) {
-        mid_route(P, L, s + run, c1, wave_cap, 0);
-        if (first && c1 > P.tiny_max) set_bits(L.bmb, s + run, c1);
-      }
+      if (c1) mid_scan_route_one(P, L, s + run, c1, wave_cap, first);
       run += c1;
     }
   }
