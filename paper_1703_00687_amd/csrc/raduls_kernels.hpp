@@ -1057,14 +1057,18 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
   uint32_t lcnt = 0;   // thread d: buffered records of digit d
   bool lines_on = false;  // the destination's lines align with records
 
-  // state of the bin the current tile belongs to (uniform)
-  uint32_t b = 0, w = 0, lob = 0, nb = 0;
+  // state of the bin the current tile belongs to (uniform), including its
+  // tile range [bt0, bt1), kept in registers: a global load inside the tile
+  // loop would make it wait for every store still in flight
+  uint32_t b = 0, w = 0, lob = 0, nb = 0, bt0 = 0, bt1 = 0;
   Bin bin{};
   const uint8_t* src = nullptr;
   uint8_t* dst = nullptr;
   bool active = false;
   auto enter_bin = [&](uint32_t t) {
     b = whole_bin ? blockIdx.x : P.L.tile_bin[t];
+    bt0 = P.L.tile_prefix[b];
+    bt1 = P.L.tile_prefix[b + 1];
     bin = P.L.large[cur][b];
     const ArrayDesc arr = P.L.arrays[bin.array];
     src = bin.side ? arr.tmp : arr.recs;
@@ -1089,7 +1093,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
 
   uint64_t rec[ITEMS][RW];
   auto tile_span = [&](uint32_t t, uint32_t& tbeg, uint32_t& tn, uint32_t& ipw) {
-    const uint32_t k = t - P.L.tile_prefix[b];
+    const uint32_t k = t - bt0;
     tbeg = bin.start + k * TILE;
     tn = min(TILE, bin.size - k * TILE);
     ipw = (tn + kWave * W - 1) / (kWave * W);
@@ -1107,14 +1111,15 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
   uint32_t t = r0;
   enter_bin(t);
   if (active) issue_loads(t);
+  __builtin_amdgcn_s_waitcnt(0x3F70);
   while (t < r1) {
-    if (t == P.L.tile_prefix[b]) running = 0;  // a new bin starts inside the range
+    if (t == bt0) running = 0;  // a new bin starts inside the range
     uint32_t tbeg, tn, ipw;
     tile_span(t, tbeg, tn, ipw);
     uint32_t dg[ITEMS];
     bool valid[ITEMS];
     const uint32_t next = t + 1;
-    const bool same = next < r1 && (whole_bin || P.L.tile_bin[next] == b);
+    const bool same = next < r1 && next < bt1;
     if (active) {
       // the tile into LDS in input order and its digits into registers; the
       // registers are then free for the next tile's loads, which stay in
@@ -1171,6 +1176,13 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
       }
       lds_barrier();
     }
+    // The next tile's loads have landed before this tile's stores leave, so
+    // the next tile does not wait for these stores (on gfx9 one in-order
+    // counter covers loads and stores).  The wait is on every path, as are
+    // the ones after the other places that issue loads, so that the compiler
+    // sees the tile's records complete at the top of the loop and places no
+    // wait of its own there.
+    __builtin_amdgcn_s_waitcnt(0x3F70);  // gfx9 encoding: vmcnt(0), lgkmcnt/expcnt not waited
     if (active) {
       bool oob = false;
       if (LINES && lines_on) {
@@ -1251,6 +1263,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
     if (t < r1 && !same) {
       enter_bin(t);
       if (active) issue_loads(t);
+      __builtin_amdgcn_s_waitcnt(0x3F70);
     }
   }
 }
