@@ -81,6 +81,10 @@ constexpr uint32_t kMidBigCap = 64;     // ranges waiting for a workgroup pass
 // Positions per lane of the enumeration phase: a range of at most 256 records
 // starting in a 64-position window ends within 5 windows.
 constexpr int kMidEsItems = 5;
+// Jobs of at most this many records skip the first pass and are finished by
+// one enumeration sort over the whole job; larger ones (even those below
+// tiny_max) take the first pass, whose buckets make the enumeration cheaper.
+constexpr uint32_t kMidDirectEs = 16;
 
 // Most workgroups of the histogram / carry-scan scatter grid.
 constexpr uint32_t kMaxRanges = 4096;

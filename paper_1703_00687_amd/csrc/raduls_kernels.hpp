@@ -1907,7 +1907,7 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
     (void)mid_wg_spread<KW>(L, tid, dk, 0u);
     bool by_slot;
     const uint32_t hb = pair_top<KW>(dk, 0u, by_slot);
-    if (m > tiny && hb > 0) {
+    if (m > min(tiny, kMidDirectEs) && hb > 0) {
       // first pass over the whole job
       const uint32_t lg = 32u - uint32_t(__clz(m));
       const uint32_t w = min(min(hb, uint32_t(kMidFirstBits)), lg);
