@@ -364,9 +364,16 @@ def bench_batch(args) -> dict:
         be = serve.GpuBackend(R, K, n_streams=3, max_batch=2048, max_records=budget // R)
         views = [recs[int(starts[j]):int(starts[j]) + int(sizes[j])] for j in range(nreq)]
         served_records = int(sizes[:nreq].sum())
+        import gc
         for mode, rho in (("closed", None), ("poisson", args.serve_load)):
             fill_batch(recs, starts, sizes)
             torch.cuda.synchronize()
+            # Python's cyclic collector would stop both the client and the
+            # server thread for up to ~0.15 s at a time while tens of
+            # thousands of requests are alive; a latency-sensitive client
+            # turns it off while it serves
+            gc.collect()
+            gc.disable()
             srv = serve.Server(be, R, budget, max_slots=4096).start()
             futs = []
             t0 = time.perf_counter()
@@ -386,6 +393,7 @@ def bench_batch(args) -> dict:
             for f in futs:
                 f.result(timeout=600)
             summ = srv.stop()
+            gc.enable()
             summ["wall_s"] = time.perf_counter() - t0
             if rho is not None:
                 summ["arrival_rate_req_s"] = rate
