@@ -120,3 +120,35 @@ def test_tuning_roundtrip_and_rejects():
 def test_strerror():
     for st in (b.OK, b.E_INVALID, b.E_ALIGN, b.E_TMP_SMALL, b.E_UNSUPPORTED, b.E_HIP, b.E_DEVICE):
         assert b.strerror(st) and b.strerror(st) != "unknown status"
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structs have the sizes and field offsets the C
+    header gives (compiled here with the host compiler)."""
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_1703_00687_amd import binding as b
+    gcc = shutil.which("gcc")
+    if gcc is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("no host compiler or HIP headers")
+    src = tmp_path / "layout.c"
+    src.write_text(
+        "#include <stdio.h>\n#include <stddef.h>\n#include \"raduls.h\"\n"
+        "int main(void) {\n"
+        "  printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(raduls_tuning),\n"
+        "         offsetof(raduls_tuning, lookback), offsetof(raduls_tuning, pair_hist),\n"
+        "         sizeof(raduls_stats), offsetof(raduls_stats, moved_records),\n"
+        "         offsetof(raduls_stats, pair_rounds), sizeof(raduls_array));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run([gcc, "-D__HIP_PLATFORM_AMD__", "-I", inc, "-I", "/opt/rocm/include", str(src),
+                    "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [ctypes.sizeof(b.raduls_tuning), b.raduls_tuning.lookback.offset,
+            b.raduls_tuning.pair_hist.offset, ctypes.sizeof(b.raduls_stats),
+            b.raduls_stats.moved_records.offset, b.raduls_stats.pair_rounds.offset,
+            ctypes.sizeof(b.raduls_array)]
+    assert got == want
