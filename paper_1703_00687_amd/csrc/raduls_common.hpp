@@ -85,6 +85,9 @@ constexpr int kMidEsItems = 5;
 // one enumeration sort over the whole job; larger ones (even those below
 // tiny_max) take the first pass, whose buckets make the enumeration cheaper.
 constexpr uint32_t kMidDirectEs = 16;
+// Jobs of at most one wave's worth of records go to a separate list and are
+// sorted by single waves in registers (k_tiny), not by a whole workgroup.
+constexpr uint32_t kTinyJob = kWave;
 
 // Most workgroups of the histogram / carry-scan scatter grid.
 constexpr uint32_t kMaxRanges = 4096;
@@ -164,7 +167,7 @@ struct Ctrl {
   uint32_t mid_claim;  // LDS-sort jobs handed out beyond the first one per workgroup
   uint32_t fused;      // 1: this round's histograms came from the top-level pair counts
   uint32_t pair_rounds;  // rounds that did so
-  uint32_t pad;
+  uint32_t tiny_count;   // jobs in the tiny-job list
   unsigned long long moved_records;
   unsigned long long large_records;
   unsigned long long batch_total;
@@ -184,6 +187,7 @@ struct Layout {
   uint32_t* wg_carry;     // [cap_ranges][kRadix] prefix carried into each range
   uint32_t* wg_flag;      // [cap_ranges] range starts a bin (1) / lies in one bin (2)
   MidJob* mid;
+  MidJob* tiny;           // [cap_mid] jobs of at most kTinyJob records
   Bin* copy;
   uint32_t* pair_part;    // [kPairRanges][kPairWords] per-range packed pair counts
   uint32_t* pair_hist;    // [2^16] pair counts of the whole array
@@ -219,7 +223,7 @@ struct Params {
   uint32_t* d_counts_out;
   uint32_t* d_offsets_out;
   // launch shapes
-  uint32_t grid_hist, grid_scatter, grid_classify, grid_mid, grid_copy;
+  uint32_t grid_hist, grid_scatter, grid_classify, grid_mid, grid_copy, grid_tiny;
   uint32_t mid_lds_bytes, scatter_lds_bytes;
 };
 

@@ -12,7 +12,8 @@
 //                          k_scatter_carry / k_scatter (look-back variant)
 //                                     stable scatter into the child bins
 //                          k_classify child bins -> next round / LDS jobs
-//   then                   k_mid      bins that fit in LDS, sorted there; tiny
+//   then                   k_tiny     jobs of at most 64 records, one wave each
+//                          k_mid      bins that fit in LDS, sorted there; tiny
 //                                     sub-bins by enumeration sort
 //                          k_copy     finished bins left in tmp -> recs
 #pragma once
@@ -283,9 +284,26 @@ __device__ __forceinline__ void push_large(const Params& P, uint32_t nxt, const 
   for (int q = 0; q < 8; ++q) df[q] = 0;
 }
 
-// Append an LDS-sort job for bin b of array a.
+// Slot in a list for every active lane with `want`: one atomic per wave on
+// the list's counter (many thousands of arrays push jobs at once; per-lane
+// atomics on one address would serialize).  All active lanes call.
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t* counter, bool want) {
+  const uint64_t mask = __ballot(want);
+  const uint32_t before = uint32_t(__popcll(mask & lanemask_lt()));
+  const int leader = mask ? __ffsll((long long)mask) - 1 : 0;
+  uint32_t base = 0;
+  if (want && int(lane_id()) == leader) base = atomicAdd(counter, uint32_t(__popcll(mask)));
+  base = uint32_t(__shfl(int(base), leader));
+  return base + before;
+}
+
+// Append a sort job for bin b of array a: to the tiny-job list if one wave
+// can hold it, else to the LDS-sort list.
 __device__ __forceinline__ void push_mid(const Params& P, const Bin& b, const ArrayDesc& a) {
-  const uint32_t i = atomicAdd(&P.L.ctrl->mid_count, 1u);
+  const bool tiny = b.size <= kTinyJob;
+  const uint32_t it = wave_reserve(&P.L.ctrl->tiny_count, tiny);
+  const uint32_t im = wave_reserve(&P.L.ctrl->mid_count, !tiny);
+  const uint32_t i = tiny ? it : im;
   if (i >= P.L.cap_mid) {
     atomicOr(&P.L.ctrl->error, kErrCapacity);
     return;
@@ -295,7 +313,7 @@ __device__ __forceinline__ void push_mid(const Params& P, const Bin& b, const Ar
   j.dst = a.recs + uint64_t(b.start) * P.R;
   j.size = b.size;
   j.pad[0] = j.pad[1] = j.pad[2] = 0;
-  P.L.mid[i] = j;
+  (tiny ? P.L.tiny : P.L.mid)[i] = j;
 }
 
 // Copy jobs for a finished run of records that sits in tmp.
@@ -1278,7 +1296,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
 template <int KW>
 __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
   __shared__ uint32_t s_cnt[kRadix], s_off[kRadix], s_scan[8];
-  __shared__ uint32_t s_js[kRadix], s_jn[kRadix], s_nj, s_jbase;
+  __shared__ uint32_t s_js[kRadix], s_jn[kRadix], s_jr[kRadix], s_nj, s_jbase, s_tbase;
   Ctrl* c = P.L.ctrl;
   const uint32_t nbins = min(c->large_count[cur], P.L.cap_large);
   const uint32_t nxt = cur ^ 1;
@@ -1337,14 +1355,16 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
       push_large(P, nxt, ch);
     }
     // greedy packing of the small children into jobs (one thread; cheap
-    // arithmetic on LDS), then one reservation in the job list and a
-    // parallel write of the descriptors
+    // arithmetic on LDS), then one reservation in each job list (jobs of
+    // at most kTinyJob records go to the tiny-job list) and a parallel write
+    // of the descriptors
     if (tid == 0) {
-      uint32_t js = 0, jn = 0, nj = 0;
+      uint32_t js = 0, jn = 0, nj = 0, nm = 0, nt = 0;
       auto flush = [&]() {
         if (jn > 0 && !(jn == 1 && cside == 0)) {  // a lone record in recs is in place
           s_js[nj] = js;
           s_jn[nj] = jn;
+          s_jr[nj] = jn <= kTinyJob ? (0x80000000u | nt++) : nm++;
           ++nj;
         }
         jn = 0;
@@ -1362,11 +1382,14 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
       }
       flush();
       s_nj = nj;
-      s_jbase = nj ? atomicAdd(&c->mid_count, nj) : 0u;
+      s_jbase = nm ? atomicAdd(&c->mid_count, nm) : 0u;
+      s_tbase = nt ? atomicAdd(&c->tiny_count, nt) : 0u;
     }
     __syncthreads();
     if (tid < s_nj) {
-      const uint32_t i = s_jbase + tid;
+      const uint32_t r = s_jr[tid];
+      const bool tiny = (r >> 31) != 0;
+      const uint32_t i = (tiny ? s_tbase : s_jbase) + (r & 0x7FFFFFFFu);
       if (i < P.L.cap_mid) {
         const ArrayDesc a = P.L.arrays[bin.array];
         const uint64_t st = uint64_t(bin.start) + s_js[tid];
@@ -1375,7 +1398,7 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
         j.dst = a.recs + st * P.R;
         j.size = s_jn[tid];
         j.pad[0] = j.pad[1] = j.pad[2] = 0;
-        P.L.mid[i] = j;
+        (tiny ? P.L.tiny : P.L.mid)[i] = j;
       } else {
         atomicOr(&c->error, kErrCapacity);
       }
@@ -2107,6 +2130,63 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
 
 // ------------------------------------------------------------ copies
 
+// Jobs of at most one wave of records (tiny bins, Sec. 3.3, and tiny arrays
+// of a batch): one wave per job sorts the job in registers with Batcher's
+// bitonic network over 64 (key, slot) pairs -- branch-free, the kind of
+// network Sec. 3.3 uses for tiny bins -- padded with pairs above any real
+// one; then lane r fetches the record of the r-th pair from the lane that
+// loaded it and stores it at position r.  The pairs are distinct, so the
+// order is the stable one.
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  const uint32_t lo = uint32_t(__shfl(int(uint32_t(v)), src));
+  const uint32_t hi = uint32_t(__shfl(int(uint32_t(v >> 32)), src));
+  return uint64_t(lo) | (uint64_t(hi) << 32);
+}
+
+template <int RW, int KW>
+__global__ void __launch_bounds__(kMidBlock) k_tiny(Params P) {
+  const Ctrl* c = P.L.ctrl;
+  const uint32_t n = min(c->tiny_count, P.L.cap_mid);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t waves = gridDim.x * uint32_t(kMidWaves);
+  for (uint32_t jb = blockIdx.x * uint32_t(kMidWaves) + (threadIdx.x >> 6); jb < n; jb += waves) {
+    const MidJob job = P.L.tiny[jb];
+    const uint32_t m = min(job.size, uint32_t(kWave));
+    uint64_t rec[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) rec[q] = 0;
+    if (lane < m) load_rec<RW>(job.src, lane, rec);
+    uint64_t key[KW];
+#pragma unroll
+    for (int q = 0; q < KW; ++q) key[q] = lane < m ? rec[q] : ~0ull;
+    if (lane < m) key[KW - 1] &= P.kmask;
+    uint32_t slot = lane;
+    // bitonic network: stages k = 2..64, steps j = k/2..1; lane keeps the
+    // smaller pair when it is the lower lane of an ascending block (or the
+    // upper lane of a descending one)
+#pragma unroll
+    for (uint32_t k = 2; k <= uint32_t(kWave); k <<= 1) {
+#pragma unroll
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        uint64_t ok[KW];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) ok[q] = shfl64(key[q], int(lane ^ j));
+        const uint32_t os = uint32_t(__shfl(int(slot), int(lane ^ j)));
+        const bool other_less = key_lt<KW>(ok, key) || (key_eq<KW>(ok, key) && os < slot);
+        const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+        const bool take = keep_min ? other_less : !other_less;
+#pragma unroll
+        for (int q = 0; q < KW; ++q) key[q] = take ? ok[q] : key[q];
+        slot = take ? os : slot;
+      }
+    }
+    uint64_t out[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) out[q] = shfl64(rec[q], int(slot));
+    if (lane < m) store_rec<RW>(job.dst, lane, out, false);
+  }
+}
+
 template <int RW>
 __global__ void __launch_bounds__(256) k_copy(Params P) {
   Ctrl* c = P.L.ctrl;
@@ -2234,6 +2314,7 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
     k_classify<KW><<<P.grid_classify, 256, 0, s>>>(P, cur);
   }
   prof_mark(kProfMid, 0, s);
+  k_tiny<RW, KW><<<P.grid_tiny, kMidBlock, 0, s>>>(P);
   k_mid<RW, KW><<<P.grid_mid, kMidBlock, P.mid_lds_bytes, s>>>(P);
   prof_mark(kProfMid, 1, s);
   k_copy<RW><<<P.grid_copy, 256, 0, s>>>(P);

@@ -70,7 +70,7 @@ bool use_pair(const Eff& e, uint64_t n, uint32_t K) {
 struct Shape {
   uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges, rounds, pair;
   uint64_t off_ctrl, off_arrays, off_large[2], off_hist[2], off_diff[2], off_tp, off_tb, off_status,
-      off_tail, off_carry, off_flag, off_mid, off_copy, off_pair_part, off_pair_hist, off_pair_d1,
+      off_tail, off_carry, off_flag, off_mid, off_tiny, off_copy, off_pair_part, off_pair_hist, off_pair_d1,
       bytes;
 };
 
@@ -114,6 +114,7 @@ Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const
   s.off_carry = take(uint64_t(s.cap_ranges) * kRadix * 4);
   s.off_flag = take(uint64_t(s.cap_ranges) * 4);
   s.off_mid = take(uint64_t(s.cap_mid) * sizeof(MidJob));
+  s.off_tiny = take(uint64_t(s.cap_mid) * sizeof(MidJob));
   s.off_copy = take(uint64_t(s.cap_copy) * sizeof(Bin));
   // per-range pair counts, one row per histogram workgroup (at most
   // kPairRanges of them when pairs are counted), and their sum
@@ -142,6 +143,7 @@ Layout make_layout(uint8_t* aux, const Shape& s) {
   L.wg_flag = reinterpret_cast<uint32_t*>(aux + s.off_flag);
   L.cap_ranges = s.cap_ranges;
   L.mid = reinterpret_cast<MidJob*>(aux + s.off_mid);
+  L.tiny = reinterpret_cast<MidJob*>(aux + s.off_tiny);
   L.copy = reinterpret_cast<Bin*>(aux + s.off_copy);
   L.pair_part = reinterpret_cast<uint32_t*>(aux + s.off_pair_part);
   L.pair_hist = reinterpret_cast<uint32_t*>(aux + s.off_pair_hist);
@@ -230,6 +232,7 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
   P.scatter_lds_bytes = scatter_lds_bytes(int(R / 8));
   P.mid_lds_bytes = mid_dynamic_lds(e.mid_max, int(R / 8));
   P.grid_mid = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_mid, cus));
+  P.grid_tiny = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_mid / kMidWaves + 1, 4 * cus));
   P.grid_copy = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_copy, 8 * cus));
 }
 
@@ -390,7 +393,7 @@ int raduls_check(const void* tmp_or_ws, uint64_t n, uint32_t rec_bytes, int ws_o
   stats->rounds = c.rounds;
   stats->large_bins = c.large_bins;
   stats->scattered_bins = c.scattered_bins;
-  stats->mid_jobs = c.mid_count;
+  stats->mid_jobs = c.mid_count + c.tiny_count;
   stats->copy_jobs = c.copy_count;
   stats->moved_records = c.moved_records;
   stats->large_records = c.large_records;
