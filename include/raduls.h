@@ -16,7 +16,9 @@
  * byte by default, as in the paper): per-bin digit histograms, exclusive
  * prefix scans into bucket offsets, a scatter of records into buckets, and
  * recursion into bins that are still large; small bins are finished inside one
- * workgroup's LDS and tiny bins by an enumeration sort (Sec. 2.2, Sec. 3.3).
+ * workgroup's LDS, tiny buckets there by an enumeration sort, and bins of at
+ * most 64 records by one wave with a bitonic sorting network (Sec. 2.2,
+ * Sec. 3.3).
  *
  * Conventions for every call:
  *   - All calls are host calls.  Device work is enqueued on `stream` (0 = the
@@ -91,7 +93,8 @@ typedef struct raduls_stats {
   uint32_t rounds;         /* radix rounds that found at least one large bin */
   uint32_t large_bins;     /* large bins processed over all rounds */
   uint32_t scattered_bins; /* large bins that were moved (not constant / all equal) */
-  uint32_t mid_jobs;       /* LDS sort jobs */
+  uint32_t mid_jobs;       /* bins finished by a final sort job: in one workgroup's LDS,
+                              or (at most 64 records) by one wave in registers */
   uint32_t copy_jobs;      /* tmp -> recs copies of finished bins */
   uint64_t moved_records;  /* records moved by global scatter passes */
   uint64_t large_records;  /* records in large bins, summed over rounds */
