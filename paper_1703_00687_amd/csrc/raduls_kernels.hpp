@@ -2131,59 +2131,91 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
 // ------------------------------------------------------------ copies
 
 // Jobs of at most one wave of records (tiny bins, Sec. 3.3, and tiny arrays
-// of a batch): one wave per job sorts the job in registers with Batcher's
-// bitonic network over 64 (key, slot) pairs -- branch-free, the kind of
-// network Sec. 3.3 uses for tiny bins -- padded with pairs above any real
-// one; then lane r fetches the record of the r-th pair from the lane that
-// loaded it and stores it at position r.  The pairs are distinct, so the
-// order is the stable one.
+// of a batch) are sorted in registers with Batcher's bitonic network over
+// the jobs' (key, slot) pairs -- branch-free, the kind of network Sec. 3.3
+// uses for tiny bins -- padded with pairs above any real one; then lane r of
+// a job fetches the record of the r-th pair from the lane that loaded it and
+// stores it at position r.  The pairs are distinct, so the order is the
+// stable one.
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
   const uint32_t lo = uint32_t(__shfl(int(uint32_t(v)), src));
   const uint32_t hi = uint32_t(__shfl(int(uint32_t(v >> 32)), src));
   return uint64_t(lo) | (uint64_t(hi) << 32);
 }
 
+// One pass of a wave over 64 / S consecutive tiny jobs (first, first + 1,
+// ...; ids from n on are empty), S lanes per job.  Lanes of a job form one
+// segment; the network's compare-exchanges stay inside it (partner lane ^ j
+// with j < S) and every segment ends ascending.
+template <int RW, int KW, int S>
+__device__ __forceinline__ void tiny_pass(const Params& P, uint32_t first, uint32_t n,
+                                          uint32_t lane) {
+  const uint32_t seg = lane / uint32_t(S), idx = lane % uint32_t(S);
+  const uint32_t jid = first + seg;
+  MidJob job{};
+  if (jid < n) job = P.L.tiny[jid];
+  const uint32_t m = jid < n ? min(job.size, uint32_t(S)) : 0u;
+  uint64_t rec[RW];
+#pragma unroll
+  for (int q = 0; q < RW; ++q) rec[q] = 0;
+  if (idx < m) load_rec<RW>(job.src, idx, rec);
+  uint64_t key[KW];
+#pragma unroll
+  for (int q = 0; q < KW; ++q) key[q] = idx < m ? rec[q] : ~0ull;
+  if (idx < m) key[KW - 1] &= P.kmask;
+  uint32_t slot = idx;
+  // bitonic network: stages k = 2..S, steps j = k/2..1; a lane keeps the
+  // smaller pair when it is the lower lane of an ascending block (or the
+  // upper lane of a descending one)
+#pragma unroll
+  for (uint32_t k = 2; k <= uint32_t(S); k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      uint64_t ok[KW];
+#pragma unroll
+      for (int q = 0; q < KW; ++q) ok[q] = shfl64(key[q], int(lane ^ j));
+      const uint32_t os = uint32_t(__shfl(int(slot), int(lane ^ j)));
+      const bool other_less = key_lt<KW>(ok, key) || (key_eq<KW>(ok, key) && os < slot);
+      const bool keep_min = ((idx & j) == 0) == ((idx & k) == 0);
+      const bool take = keep_min ? other_less : !other_less;
+#pragma unroll
+      for (int q = 0; q < KW; ++q) key[q] = take ? ok[q] : key[q];
+      slot = take ? os : slot;
+    }
+  }
+  uint64_t out[RW];
+#pragma unroll
+  for (int q = 0; q < RW; ++q) out[q] = shfl64(rec[q], int(seg * uint32_t(S) + slot));
+  if (idx < m) store_rec<RW>(job.dst, idx, out, false);
+}
+
+// Jobs come in groups of four per wave: four jobs of at most 16 records
+// share one pass (16 lanes each), jobs of at most 32 go two per pass, larger
+// ones one per pass (several bins per wave when they are small).
 template <int RW, int KW>
 __global__ void __launch_bounds__(kMidBlock) k_tiny(Params P) {
   const Ctrl* c = P.L.ctrl;
   const uint32_t n = min(c->tiny_count, P.L.cap_mid);
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t waves = gridDim.x * uint32_t(kMidWaves);
-  for (uint32_t jb = blockIdx.x * uint32_t(kMidWaves) + (threadIdx.x >> 6); jb < n; jb += waves) {
-    const MidJob job = P.L.tiny[jb];
-    const uint32_t m = min(job.size, uint32_t(kWave));
-    uint64_t rec[RW];
-#pragma unroll
-    for (int q = 0; q < RW; ++q) rec[q] = 0;
-    if (lane < m) load_rec<RW>(job.src, lane, rec);
-    uint64_t key[KW];
-#pragma unroll
-    for (int q = 0; q < KW; ++q) key[q] = lane < m ? rec[q] : ~0ull;
-    if (lane < m) key[KW - 1] &= P.kmask;
-    uint32_t slot = lane;
-    // bitonic network: stages k = 2..64, steps j = k/2..1; lane keeps the
-    // smaller pair when it is the lower lane of an ascending block (or the
-    // upper lane of a descending one)
-#pragma unroll
-    for (uint32_t k = 2; k <= uint32_t(kWave); k <<= 1) {
-#pragma unroll
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        uint64_t ok[KW];
-#pragma unroll
-        for (int q = 0; q < KW; ++q) ok[q] = shfl64(key[q], int(lane ^ j));
-        const uint32_t os = uint32_t(__shfl(int(slot), int(lane ^ j)));
-        const bool other_less = key_lt<KW>(ok, key) || (key_eq<KW>(ok, key) && os < slot);
-        const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
-        const bool take = keep_min ? other_less : !other_less;
-#pragma unroll
-        for (int q = 0; q < KW; ++q) key[q] = take ? ok[q] : key[q];
-        slot = take ? os : slot;
-      }
+  constexpr uint32_t G = 4;
+  for (uint32_t g = blockIdx.x * uint32_t(kMidWaves) + (threadIdx.x >> 6); g < (n + G - 1) / G;
+       g += waves) {
+    const uint32_t first = g * G;
+    uint32_t mx = 0;
+    if (lane < G && first + lane < n) mx = P.L.tiny[first + lane].size;
+    mx = max(mx, uint32_t(__shfl_xor(int(mx), 1)));
+    mx = max(mx, uint32_t(__shfl_xor(int(mx), 2)));
+    mx = uint32_t(__shfl(int(mx), 0));
+    if (mx <= 16) {
+      tiny_pass<RW, KW, 16>(P, first, n, lane);
+    } else if (mx <= 32) {
+      tiny_pass<RW, KW, 32>(P, first, n, lane);
+      tiny_pass<RW, KW, 32>(P, first + 2, n, lane);
+    } else {
+#pragma unroll 1
+      for (uint32_t u = 0; u < G; ++u) tiny_pass<RW, KW, kWave>(P, first + u, n, lane);
     }
-    uint64_t out[RW];
-#pragma unroll
-    for (int q = 0; q < RW; ++q) out[q] = shfl64(rec[q], int(slot));
-    if (lane < m) store_rec<RW>(job.dst, lane, out, false);
   }
 }
 
