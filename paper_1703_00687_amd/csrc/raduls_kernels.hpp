@@ -1658,6 +1658,33 @@ __device__ __forceinline__ void mid_wg_pass(const Params& P, MidLds& L, uint32_t
   ds = mid_wg_spread<KW>(L, tid, dk, ds);
   bool by_slot;
   const uint32_t hb = pair_top<KW>(dk, ds, by_slot);
+  if (KW == 1 && by_slot) {
+    // every key of the range is equal: its order is the order of its slots,
+    // read off a bitmap of them (the prefix count of set bits below a slot
+    // is its place), in one step instead of radix passes over slot bits
+    // (one-word keys only: with wider keys the registers run out, and those
+    // keys rarely repeat)
+    uint32_t* bits = L.cnt;        // bitmap of the range's slots
+    uint32_t* pre = L.cnt + 256;   // set bits before each bitmap word
+    const uint32_t nwords = (P.mid_max + 31u) / 32u;  // <= 256
+    for (uint32_t q = tid; q < nwords; q += kMidBlock) bits[q] = 0;
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (valid[j]) atomicOr(&bits[src[j] >> 5], 1u << (src[j] & 31u));
+    lds_barrier();
+    block_exclusive_scan256(tid < nwords ? uint32_t(__popc(bits[tid])) : 0u, pre, L.scan);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (valid[j]) {
+        const uint32_t wd = src[j] >> 5;
+        L.perm[s + pre[wd] + uint32_t(__popc(bits[wd] & ((1u << (src[j] & 31u)) - 1u)))] =
+            uint16_t(src[j]);
+      }
+    }
+    lds_barrier();
+    return;
+  }
   const uint32_t w = min(P.digit_bits, hb);
   const uint32_t lob = hb - w;
   uint32_t dg[ITEMS];
@@ -1716,6 +1743,38 @@ __device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32
   for (int q = 0; q < kRadix / kWave; ++q) wc[lane * 4 + q] = 0;
   __builtin_amdgcn_wave_barrier();
   asm volatile("" ::: "memory");
+  if (KW == 1 && by_slot) {
+    // every key of the range is equal: its order is the order of its slots,
+    // read off a bitmap of them in this wave's 256 counter words (8192 bits,
+    // more than any slot): a slot's place is the number of set bits below it
+    // (one-word keys only, as in the workgroup pass)
+#pragma unroll
+    for (int j = 0; j < WI; ++j)
+      if (valid[j]) atomicOr(&wc[src[j] >> 5], 1u << (src[j] & 31u));
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sum += uint32_t(__popc(wc[lane * 4 + q]));
+    const uint32_t start = wave_inclusive_scan(sum) - sum;  // set bits before word 4 * lane
+    // (all reads of this range's perm entries are done, so places are
+    // written as they are found)
+#pragma unroll
+    for (int j = 0; j < WI; ++j) {
+      const uint32_t wd = valid[j] ? src[j] >> 5 : 0u;  // every lane takes part in the shuffle
+      uint32_t place = uint32_t(__shfl(int(start), int(wd >> 2)));
+#pragma unroll
+      for (uint32_t q = 0; q < 3; ++q)
+        place += q < (wd & 3u) ? uint32_t(__popc(wc[(wd & ~3u) + q])) : 0u;
+      place += uint32_t(__popc(wc[wd] & ((1u << (src[j] & 31u)) - 1u)));
+      if (valid[j]) L.perm[s + place] = uint16_t(src[j]);
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+    return;
+  }
   uint32_t dg[WI], r[WI];
 #pragma unroll
   for (int j = 0; j < WI; ++j) {
