@@ -1354,36 +1354,59 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
       ch.flags = 0;
       push_large(P, nxt, ch);
     }
-    // greedy packing of the small children into jobs (one thread; cheap
-    // arithmetic on LDS), then one reservation in each job list (jobs of
-    // at most kTinyJob records go to the tiny-job list) and a parallel write
-    // of the descriptors
-    if (tid == 0) {
+    // no child small enough for a sort job (the usual case at the top level)
+    if (!__syncthreads_or(tid < nb && h > 0 && h <= P.mid_max)) continue;
+    // greedy packing of the small children into jobs, in digit order: each
+    // wave runs the same scalar loop, lane l holding the counts and offsets
+    // of digits 4l..4l+3 (read out with readlane, so the loop waits on no
+    // memory), and thread 0 records the jobs in LDS; then one reservation in
+    // each job list (jobs of at most kTinyJob records go to the tiny-job
+    // list) and a parallel write of the descriptors
+    {
+      const uint32_t lane = tid & (kWave - 1);
+      int cq[4], oq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t d = 4 * lane + q;
+        cq[q] = d < nb ? int(s_cnt[d]) : 0;
+        oq[q] = d < nb ? int(s_off[d]) : 0;
+      }
+      const uint32_t M = P.mid_max;
       uint32_t js = 0, jn = 0, nj = 0, nm = 0, nt = 0;
       auto flush = [&]() {
         if (jn > 0 && !(jn == 1 && cside == 0)) {  // a lone record in recs is in place
-          s_js[nj] = js;
-          s_jn[nj] = jn;
-          s_jr[nj] = jn <= kTinyJob ? (0x80000000u | nt++) : nm++;
+          if (tid == 0) {
+            s_js[nj] = js;
+            s_jn[nj] = jn;
+            s_jr[nj] = jn <= kTinyJob ? (0x80000000u | nt) : nm;
+          }
+          if (jn <= kTinyJob) ++nt;
+          else ++nm;
           ++nj;
         }
         jn = 0;
       };
-      for (uint32_t d = 0; d < nb; ++d) {
-        const uint32_t cd = s_cnt[d];
-        if (cd == 0) continue;
-        if (cd > P.mid_max) {
-          flush();
-          continue;
+      const uint32_t nl = (nb + 3) / 4;
+      for (uint32_t l = 0; l < nl; ++l) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t cd = uint32_t(__builtin_amdgcn_readlane(cq[q], int(l)));
+          if (cd == 0) continue;
+          if (cd > M) {
+            flush();
+            continue;
+          }
+          if (jn + cd > M) flush();
+          if (jn == 0) js = uint32_t(__builtin_amdgcn_readlane(oq[q], int(l)));
+          jn += cd;
         }
-        if (jn + cd > P.mid_max) flush();
-        if (jn == 0) js = s_off[d];
-        jn += cd;
       }
       flush();
-      s_nj = nj;
-      s_jbase = nm ? atomicAdd(&c->mid_count, nm) : 0u;
-      s_tbase = nt ? atomicAdd(&c->tiny_count, nt) : 0u;
+      if (tid == 0) {
+        s_nj = nj;
+        s_jbase = nm ? atomicAdd(&c->mid_count, nm) : 0u;
+        s_tbase = nt ? atomicAdd(&c->tiny_count, nt) : 0u;
+      }
     }
     __syncthreads();
     if (tid < s_nj) {
