@@ -1356,12 +1356,15 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
     }
     // no child small enough for a sort job (the usual case at the top level)
     if (!__syncthreads_or(tid < nb && h > 0 && h <= P.mid_max)) continue;
-    // greedy packing of the small children into jobs, in digit order: each
-    // wave runs the same scalar loop, lane l holding the counts and offsets
-    // of digits 4l..4l+3 (read out with readlane, so the loop waits on no
-    // memory), and thread 0 records the jobs in LDS; then one reservation in
-    // each job list (jobs of at most kTinyJob records go to the tiny-job
-    // list) and a parallel write of the descriptors
+    // greedy packing of the small children into jobs, in digit order: every
+    // wave runs the same branch-free scalar loop, lane l holding the counts
+    // and offsets of digits 4l..4l+3 (read out with readlane, so the loop
+    // waits on no memory; with branches it took ~0.2 us per digit).  Every
+    // thread writes the job being built to entry nj of the job table (the
+    // same value from every thread); nj advances when a job is complete, so
+    // the entry is rewritten until then.  Then one reservation in each job
+    // list (jobs of at most kTinyJob records go to the tiny-job list) and a
+    // parallel write of the descriptors.
     {
       const uint32_t lane = tid & (kWave - 1);
       int cq[4], oq[4];
@@ -1372,36 +1375,42 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
         oq[q] = d < nb ? int(s_off[d]) : 0;
       }
       const uint32_t M = P.mid_max;
+      // (a lone record in recs is in place)
+      const uint32_t lone_moves = __builtin_amdgcn_readfirstlane(uint32_t(cside)) != 0 ? 1u : 0u;
       uint32_t js = 0, jn = 0, nj = 0, nm = 0, nt = 0;
-      auto flush = [&]() {
-        if (jn > 0 && !(jn == 1 && cside == 0)) {  // a lone record in recs is in place
-          if (tid == 0) {
-            s_js[nj] = js;
-            s_jn[nj] = jn;
-            s_jr[nj] = jn <= kTinyJob ? (0x80000000u | nt) : nm;
-          }
-          if (jn <= kTinyJob) ++nt;
-          else ++nm;
-          ++nj;
-        }
-        jn = 0;
+      // (every write lands below kRadix: a job is complete only once a later
+      // child or the final call closes it, and its entry is written before
+      // nj advances past it)
+      // (flags as 0/1 integers combined with bitwise operators, so that the
+      // compiler selects instead of branching)
+      auto add = [&](uint32_t cd, uint32_t od) {
+        const uint32_t big = cd > M ? 1u : 0u;
+        const uint32_t small = (cd != 0 ? 1u : 0u) & (big ^ 1u);
+        const uint32_t cut = big | (small & (jn + cd > M ? 1u : 0u));  // the job ends before this child
+        const uint32_t done = cut & (jn > 0 ? 1u : 0u) & ((jn > 1 ? 1u : 0u) | lone_moves);
+        const uint32_t tj = jn <= kTinyJob ? 1u : 0u;
+        s_js[nj] = js;
+        s_jn[nj] = jn;
+        s_jr[nj] = tj ? (0x80000000u | nt) : nm;
+        nt += done & tj;
+        nm += done & (tj ^ 1u);
+        nj += done;
+        jn = cut ? 0u : jn;
+        js = (small & (jn == 0 ? 1u : 0u)) ? od : js;
+        jn += small ? cd : 0u;
       };
       const uint32_t nl = (nb + 3) / 4;
+      // the LDS reads and scalar loads above complete here, so that the
+      // compiler's wait for them is not placed at the head of the loop (where
+      // it would wait for the loop's own LDS writes on every iteration)
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // gfx9 encoding: lgkmcnt(0) only
       for (uint32_t l = 0; l < nl; ++l) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t cd = uint32_t(__builtin_amdgcn_readlane(cq[q], int(l)));
-          if (cd == 0) continue;
-          if (cd > M) {
-            flush();
-            continue;
-          }
-          if (jn + cd > M) flush();
-          if (jn == 0) js = uint32_t(__builtin_amdgcn_readlane(oq[q], int(l)));
-          jn += cd;
-        }
+        for (int q = 0; q < 4; ++q)
+          add(uint32_t(__builtin_amdgcn_readlane(cq[q], int(l))),
+              uint32_t(__builtin_amdgcn_readlane(oq[q], int(l))));
       }
-      flush();
+      add(M + 1, 0);  // closes the last job
       if (tid == 0) {
         s_nj = nj;
         s_jbase = nm ? atomicAdd(&c->mid_count, nm) : 0u;
