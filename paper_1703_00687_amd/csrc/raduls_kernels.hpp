@@ -1359,10 +1359,9 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
     // greedy packing of the small children into jobs, in digit order: every
     // wave runs the same branch-free scalar loop, lane l holding the counts
     // and offsets of digits 4l..4l+3 (read out with readlane, so the loop
-    // waits on no memory; with branches it took ~0.2 us per digit).  Every
-    // thread writes the job being built to entry nj of the job table (the
-    // same value from every thread); nj advances when a job is complete, so
-    // the entry is rewritten until then.  Then one reservation in each job
+    // waits on no memory; with branches it took ~0.2 us per digit).  Thread
+    // 0 writes the job being built to entry nj of the job table; nj advances
+    // when a job is complete, so the entry is rewritten until then.  Then one reservation in each job
     // list (jobs of at most kTinyJob records go to the tiny-job list) and a
     // parallel write of the descriptors.
     {
@@ -1389,9 +1388,11 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
         const uint32_t cut = big | (small & (jn + cd > M ? 1u : 0u));  // the job ends before this child
         const uint32_t done = cut & (jn > 0 ? 1u : 0u) & ((jn > 1 ? 1u : 0u) | lone_moves);
         const uint32_t tj = jn <= kTinyJob ? 1u : 0u;
-        s_js[nj] = js;
-        s_jn[nj] = jn;
-        s_jr[nj] = tj ? (0x80000000u | nt) : nm;
+        if (tid == 0) {  // (one lane: many lanes writing one LDS word serialize)
+          s_js[nj] = js;
+          s_jn[nj] = jn;
+          s_jr[nj] = tj ? (0x80000000u | nt) : nm;
+        }
         nt += done & tj;
         nm += done & (tj ^ 1u);
         nj += done;
