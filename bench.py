@@ -11,12 +11,14 @@ compares one batched call over 65,536 uneven arrays with one call per array
 and serves the same arrays as a request stream.
 
 Prints one JSON line.  `value` is records sorted per second over the timed
-steps.  `roofline` covers the dominant kernel, the top-level scatter, from HIP
-events recorded around its launch in every timed step: algorithmic bytes per
-launch = 2 * n * R (every record read once and written once) over its mean
-duration, against the 8 TB/s HBM peak.  `cpu_baseline` is the CPU oracle
-(std::stable_sort, one thread) timed on a bounded sample of the same
-workload.
+steps.  `roofline` covers the dominant kernel class: of the three passes that
+move every record once (top-level scatter, second-round scatter, LDS sort), the
+one with the largest time, from HIP events recorded around its launch in every
+timed step: algorithmic bytes per launch = 2 * n * R (every record read once
+and written once) over its mean duration, against the 8 TB/s HBM peak;
+`move_passes` gives the same fraction for each of the three.  `cpu_baseline` is
+the CPU oracle's stable sort timed on the host: in libstdc++ parallel mode on
+all the cores the process may use (`value`, `cores`) and on one thread.
 """
 
 from __future__ import annotations
@@ -36,7 +38,6 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "records sorted/s and % of HBM roofline (16B recs, 2^28); batched vs plain"
 PROFILE_SLOTS = ["top_hist", "top_scatter", "round2_hist", "round2_scatter", "lds_sort"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_top_scatter_uniform16.json")
 
 
 def log(msg: str) -> None:
@@ -81,15 +82,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(n: int) -> float | None:
-    """HBM bytes per top-scatter launch from committed PMC counters, if they
-    were taken on the current kernel source for this n."""
+def traffic_file(phase: str, workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{phase}_{workload}.json")
+
+
+def load_traffic(workload: str, n: int, rec_bytes: int, phase: str) -> float | None:
+    """HBM bytes per launch of the roofline kernel class from committed PMC
+    counters, if they were taken on the current kernel source for this
+    workload and size."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(phase, workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("n") != n:
+    if (t.get("kernel_source_hash") != kernel_source_hash() or t.get("n") != n
+            or t.get("rec_bytes") != rec_bytes):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -148,27 +155,60 @@ def check_sorted_device(out, src, n, R, K):
     return bool((p[1:][eq] > p[:-1][eq]).all())
 
 
-def cpu_baseline(name: str, log2n: int) -> dict:
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name: str, log2n: int, par_log2n: int) -> dict:
+    """The oracle's stable sort timed on the host: on all the cores this
+    process may use (the parallel variant, over 2^par_log2n records) and on
+    one thread (over the first 2^log2n records).  `value` is the all-cores
+    rate."""
     import oracle
     from paper_1703_00687_amd import workloads as wl
-    n = 1 << log2n
-    host, k = wl.make(name, n)
+    cores = len(os.sched_getaffinity(0))
+    n_par = 1 << par_log2n
+    host, k = wl.make(name, n_par)
     oracle.sort(host[:1024], k)  # load/build outside the timing
     t0 = time.perf_counter()
-    out = oracle.sort(host, k)
-    dt = time.perf_counter() - t0
-    assert oracle.check_sorted(out[: 1 << 16], k)
-    return {"value": n / dt, "unit": "records/s", "cores": 1, "kind": "oracle",
-            "sample": f"first 2^{log2n} records of the same {name} workload "
-                      f"(std::stable_sort, one thread, {dt:.1f} s)"}
+    out_par, used = oracle.sort_parallel(host, k, cores)
+    dt_par = time.perf_counter() - t0
+    assert oracle.check_sorted(out_par[: 1 << 16], k)
+    del out_par
+    n1 = 1 << log2n
+    t0 = time.perf_counter()
+    out1 = oracle.sort(host[:n1], k)
+    dt1 = time.perf_counter() - t0
+    assert oracle.check_sorted(out1[: 1 << 16], k)
+    model = cpu_model()
+    return {"value": n_par / dt_par, "unit": "records/s", "cores": used, "kind": "oracle",
+            "sample": f"first 2^{par_log2n} records of the same {name} workload: the oracle's stable "
+                      f"sort in libstdc++ parallel mode on {used} threads ({dt_par:.1f} s), {model}",
+            "cpu_model": model,
+            "single_thread": {"value": n1 / dt1, "unit": "records/s", "cores": 1,
+                              "sample": f"first 2^{log2n} records, std::stable_sort, one thread "
+                                        f"({dt1:.1f} s)"}}
 
 
-def time_sorts(src, n, R, K, steps, warm, verify, roof="top_scatter"):
-    """Sort `steps` resident copies of src (after `warm` untimed sorts) with
-    the library's profile events around the kernel class `roof` only, then
-    the same steps again on fresh copies with events around every kernel
-    class.  Returns (ms per step on the GPU clock, mean duration of `roof` in
-    the timed steps, mean phase times of the second pass, device stats,
+# The passes that move every record once (read + write of n * R bytes).
+MOVE_PASSES = ["top_scatter", "round2_scatter", "lds_sort"]
+
+
+def time_sorts(src, n, R, K, steps, warm, verify, roof=None):
+    """Sort `steps` resident copies of src (after `warm` untimed sorts), first
+    with the library's profile events around every kernel class (the phase
+    times), then -- on fresh copies -- the timed steps, with events only
+    around the roofline kernel class `roof` (default: the move pass with the
+    largest phase time).  The last timed step's output is verified before
+    anything else touches it.  Returns (ms per step on the GPU clock, roof,
+    mean duration of roof in the timed steps, phase means, device stats,
     verified)."""
     import torch
     from paper_1703_00687_amd import binding as b
@@ -192,9 +232,29 @@ def time_sorts(src, n, R, K, steps, warm, verify, roof="top_scatter"):
         raise RuntimeError(f"device error in warm-up: {stats}")
     log(f"[bench] warm-up done; stats {stats}")
 
-    # the timed steps carry only the events around the roofline kernel (each
-    # event recorded between two kernels leaves a gap of several microseconds
-    # on the stream)
+    # phase times: events around each kernel class (each event recorded
+    # between two kernels leaves a gap of several microseconds on the stream,
+    # so these steps are not the timed ones)
+    for i in range(steps):
+        b.raduls_set_profile_events(step_events[i])
+        b.raduls_sort(copies[warm + i], tmp, n, R, K)
+    torch.cuda.synchronize()
+    b.raduls_set_profile_events([])
+    st, stats = b.raduls_check(tmp, n, R, False)
+    if st != b.OK:
+        raise RuntimeError(f"device error in the phase-timed steps: {stats}")
+    phases = {}
+    for j, name in enumerate(PROFILE_SLOTS):
+        vals = [hip.elapsed_ms(ev[2 * j], ev[2 * j + 1]) for ev in step_events]
+        phases[name] = sum(vals) / len(vals)
+    if roof is None:
+        roof = max(MOVE_PASSES, key=lambda k: phases[k])
+    log(f"[bench] phase times {phases}; roofline kernel class: {roof}")
+
+    # the timed steps, on fresh copies of the input, with events only around
+    # the roofline kernel class
+    for i in range(steps):
+        copies[warm + i].copy_(src)
     jr = PROFILE_SLOTS.index(roof)
     roof_events = [[ev[k] if k // 2 == jr else None for k in range(2 * nslot)]
                    for ev in step_events]
@@ -218,41 +278,21 @@ def time_sorts(src, n, R, K, steps, warm, verify, roof="top_scatter"):
     st, stats = b.raduls_check(tmp, n, R, False)
     if st != b.OK:
         raise RuntimeError(f"device error in timed steps: {stats}")
-    # the same steps again on fresh copies of the input, with the library's
-    # events around each kernel class, for the phase times
-    for i in range(steps):
-        copies[warm + i].copy_(src)
-    torch.cuda.synchronize()
-    for i in range(steps):
-        b.raduls_set_profile_events(step_events[i])
-        b.raduls_sort(copies[warm + i], tmp, n, R, K)
-    torch.cuda.synchronize()
-    b.raduls_set_profile_events([])
-    st, stats = b.raduls_check(tmp, n, R, False)
-    if st != b.OK:
-        raise RuntimeError(f"device error in the phase-timed steps: {stats}")
-    log(f"[bench] phase-timed {steps} more steps")
-    phases = {}
-    for j, name in enumerate(PROFILE_SLOTS):
-        vals = [hip.elapsed_ms(ev[2 * j], ev[2 * j + 1]) for ev in step_events]
-        phases[name] = sum(vals) / len(vals)
     for ev in step_events:
         hip.destroy(ev)
     del tmp
     verified = None
+    last = copies[-1]  # the last timed step's output, untouched since
+    del copies
+    torch.cuda.empty_cache()
     if verify:
-        last = copies[-1]
-        del copies
-        torch.cuda.empty_cache()
         verified = check_sorted_device(last, src, n, R, K)
         if not verified:
             raise RuntimeError("sorted output failed the sort property check")
-        log("[bench] last step's output verified on the device")
-        del last
-    else:
-        del copies
+        log("[bench] the last timed step's output verified on the device")
+    del last
     torch.cuda.empty_cache()
-    return gpu_ms / steps, roof_ms, phases, stats, verified
+    return gpu_ms / steps, roof, roof_ms, phases, stats, verified
 
 
 SWEEP_SHAPES = [(8, 8), (16, 8), (16, 16), (24, 8), (24, 16), (32, 8), (32, 16), (48, 8),
@@ -269,7 +309,7 @@ def rec_sweep(log2n: int, verify: bool) -> list:
     for R, K in SWEEP_SHAPES:
         log(f"[sweep] R={R} K={K} n=2^{log2n}")
         src = wl.sweep_records_torch(n, R, K)
-        ms, _, ph, stats, ok = time_sorts(src, n, R, K, 3, 1, verify)
+        ms, _, _, ph, stats, ok = time_sorts(src, n, R, K, 3, 1, verify)
         del src
         torch.cuda.empty_cache()
         out.append({"rec_bytes": R, "key_bytes": K, "n": n, "ms": round(ms, 3),
@@ -524,7 +564,9 @@ def main() -> int:
     ap.add_argument("--log2n", type=int, default=None,
                     help="records = 2^log2n (default: the workload's size)")
     ap.add_argument("--cpu-sample-log2", type=int, default=None,
-                    help="oracle sample, 2^k records (default 25, or the whole input if smaller)")
+                    help="one-thread oracle sample, 2^k records (default 25, or the whole input if smaller)")
+    ap.add_argument("--cpu-par-log2", type=int, default=None,
+                    help="all-cores oracle sample, 2^k records (default: the whole input up to 2^28)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--batch-count", type=int, default=65536)
@@ -561,19 +603,25 @@ def main() -> int:
     src = wl.make_torch(name, n, device=dev)
     torch.cuda.synchronize()
     pass_bytes = 2 * n * R
-    # the dominant kernel: the first scatter that moves every record (the
-    # deep32 keys' constant top digits are skipped, so there it is round 2)
-    roof_phase = "round2_scatter" if name == "deep32" else "top_scatter"
-    ms_per_step, scat_ms, phases, stats, verified = time_sorts(
-        src, n, R, K, steps, warm, not args.no_verify, roof_phase)
-    achieved = pass_bytes / (scat_ms * 1e-3) / 1e9
-    traffic = load_traffic(n) if name == "uniform16" else None
+    ms_per_step, roof, roof_ms, phases, stats, verified = time_sorts(
+        src, n, R, K, steps, warm, not args.no_verify)
+    achieved = pass_bytes / (roof_ms * 1e-3) / 1e9
+    traffic = load_traffic(name, n, R, roof)
+    rw, kw = R // 8, (K + 7) // 8
+    roof_kernel = {"top_scatter": f"k_scatter_carry<{rw},{kw},1>",
+                   "round2_scatter": f"k_scatter_carry<{rw},{kw},0>",
+                   "lds_sort": f"k_tiny<{rw},{kw}> + k_mid<{rw},{kw}>"}[roof]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": f"k_scatter_carry<{R // 8},{(K + 7) // 8},"
-                          f"{1 if roof_phase == 'top_scatter' else 0}> ({roof_phase})",
-                "bytes_per_launch": pass_bytes, "mean_launch_ms": round(scat_ms, 4)}
+                "kernel": f"{roof_kernel} ({roof}, the move pass with the largest time)",
+                "bytes_per_launch": pass_bytes, "mean_launch_ms": round(roof_ms, 4)}
+    # every pass that moves each record once, with its fraction of the peak
+    # (from the phase-timed steps)
+    passes = {k: {"ms": round(phases[k], 4),
+                  "gbs": round(pass_bytes / (phases[k] * 1e-3) / 1e9, 1),
+                  "frac": round(pass_bytes / (phases[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+              for k in MOVE_PASSES if phases[k] > 0.05}
     phase_gbs = {
         "top_hist": n * R / (phases["top_hist"] * 1e-3) / 1e9,
         "top_scatter": pass_bytes / (phases["top_scatter"] * 1e-3) / 1e9,
@@ -608,8 +656,10 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         clog2 = min(log2n, 25) if args.cpu_sample_log2 is None else args.cpu_sample_log2
-        log(f"[bench] CPU oracle on 2^{clog2} records of {name}")
-        cpu = cpu_baseline(name, clog2)
+        plog2 = min(log2n, 28) if args.cpu_par_log2 is None else args.cpu_par_log2
+        log(f"[bench] CPU oracle on 2^{plog2} records of {name} (all cores), 2^{clog2} (one thread)")
+        cpu = cpu_baseline(name, clog2, plog2)
+        log(f"[bench] CPU oracle: {cpu}")
 
     line = {
         "metric": METRIC,
@@ -627,6 +677,7 @@ def main() -> int:
         "config": {"workload": f"{name}: " + WORKLOAD_DESC[name].format(l=log2n),
                    "n": n, "rec_bytes": R, "key_bytes": K},
         "roofline": roofline,
+        "move_passes": passes,
         "cpu_baseline": cpu,
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "phases_gbs": {k: round(v, 1) for k, v in phase_gbs.items()},

@@ -116,6 +116,33 @@ int raduls_tmp_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint64_
 int raduls_sort(void *recs, void *tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
                 hipStream_t stream);
 
+/* A bin of the recursion: records [start, start + size) of the array that
+ * share every key bit from `bits` up (bits 0 .. bits-1 are still to be
+ * sorted); they sit in recs (side 0) or in the ping-pong half of tmp (side 1)
+ * at the same offsets. */
+typedef struct raduls_bin {
+  uint32_t start;
+  uint32_t size;
+  uint32_t bits;
+  uint32_t side;
+} raduls_bin;
+
+/* Recursion inspection (Sec. 1: after each radix phase the array is split
+ * into bins that are processed independently; Sec. 3.1-3.2: bins larger
+ * than the LDS capacity get another global pass).  Runs the first `rounds`
+ * (>= 1) global rounds of raduls_sort on recs (tmp as for raduls_sort) and
+ * none of the later stages, then SYNCHRONIZES the stream and writes to the
+ * HOST array `bins` (room for `cap` entries) the bins larger than mid_max
+ * that those rounds left for the next round, in list order; *count receives
+ * their number (which may exceed cap).  Afterwards the records are stably
+ * partitioned into bins, each on the side its entry names; neither buffer
+ * holds the sorted result.  For tests and diagnosis; n <= mid_max runs no
+ * round and returns *count = 0.  Returns RADULS_E_DEVICE if the device
+ * recorded an error. */
+int raduls_inspect_rounds(void *recs, void *tmp, uint64_t n, uint32_t rec_bytes,
+                          uint32_t key_bytes, uint32_t rounds, raduls_bin *bins, uint32_t cap,
+                          uint32_t *count, hipStream_t stream);
+
 /* One array of a batch: device pointers recs (n*R bytes) and tmp (at least
  * n*R bytes; no auxiliary tail needed), and its record count. */
 typedef struct raduls_array {

@@ -36,7 +36,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(
-            ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp, _SRC]
+            ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC]
         )
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -56,6 +56,9 @@ def _load():
     lib.oracle_validate.restype = ctypes.c_int
     lib.oracle_sort.argtypes = [u8p, u8p, u64, u32, u32]
     lib.oracle_sort.restype = ctypes.c_int
+    lib.oracle_sort_parallel.argtypes = [u8p, u8p, u64, u32, u32, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int)]
+    lib.oracle_sort_parallel.restype = ctypes.c_int
     lib.oracle_histogram.argtypes = [u8p, u64, u32, u32, u32, u32, u8p]
     lib.oracle_histogram.restype = ctypes.c_int
     lib.oracle_exclusive_scan.argtypes = [u8p, u64, u64, u8p]
@@ -107,6 +110,19 @@ def sort(recs: np.ndarray, key_bytes: int) -> np.ndarray:
     out = np.empty_like(a)
     _check(_load().oracle_sort(_ptr(a), _ptr(out), n, R, key_bytes), "oracle_sort")
     return out
+
+
+def sort_parallel(recs: np.ndarray, key_bytes: int, threads: int = 0) -> tuple[np.ndarray, int]:
+    """The same stable sort on several cores (libstdc++ parallel mode over
+    OpenMP; `threads` = 0 takes all available).  Used only for the CPU
+    baseline; returns (sorted records, threads used)."""
+    a = _as_records(recs)
+    n, R = a.shape
+    out = np.empty_like(a)
+    used = ctypes.c_int(0)
+    _check(_load().oracle_sort_parallel(_ptr(a), _ptr(out), n, R, key_bytes, threads,
+                                        ctypes.byref(used)), "oracle_sort_parallel")
+    return out, int(used.value)
 
 
 def histogram(recs: np.ndarray, key_bytes: int, bits: int, width: int) -> np.ndarray:

@@ -22,10 +22,13 @@
 // starts at bits = 8K and moves towards 0.  With width 8 and bits a multiple
 // of 8 the digit is one key byte, as in the paper.
 
+#include <omp.h>
+
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <numeric>
+#include <parallel/algorithm>
 #include <vector>
 
 namespace {
@@ -152,6 +155,30 @@ int oracle_sort(const uint8_t* in, uint8_t* out, uint64_t n, uint32_t R, uint32_
     return key_less(in + x * R, in + y * R, K);
   });
   gather(in, out, order, R);
+  return ST_OK;
+}
+
+// The same definition computed on several cores, used only as the CPU
+// baseline of the benchmark (the paper's comparison includes a parallel
+// library sort, Sec. 4.2): the same stable sort by the same comparator, run
+// as libstdc++'s parallel-mode stable sort (a multiway mergesort) over
+// `threads` OpenMP threads (0: all available), and a parallel gather.  Both
+// sorts are stable, so the output is identical to oracle_sort's.  `used`
+// receives the number of threads.
+int oracle_sort_parallel(const uint8_t* in, uint8_t* out, uint64_t n, uint32_t R, uint32_t K,
+                         int threads, int* used) {
+  int st = validate(n, R, K);
+  if (st != ST_OK) return st;
+  const int nt = threads > 0 ? threads : omp_get_max_threads();
+  if (used) *used = nt;
+  std::vector<uint64_t> order(n);
+  std::iota(order.begin(), order.end(), uint64_t(0));
+  __gnu_parallel::stable_sort(
+      order.begin(), order.end(),
+      [&](uint64_t x, uint64_t y) { return key_less(in + x * R, in + y * R, K); },
+      __gnu_parallel::multiway_mergesort_tag(nt));
+#pragma omp parallel for num_threads(nt) schedule(static)
+  for (int64_t i = 0; i < int64_t(n); ++i) std::memcpy(out + i * R, in + order[i] * R, R);
   return ST_OK;
 }
 

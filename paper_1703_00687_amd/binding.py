@@ -63,6 +63,11 @@ class raduls_stats(ctypes.Structure):
         return {name: int(getattr(self, name)) for name, _ in self._fields_ if name != "reserved"}
 
 
+class raduls_bin(ctypes.Structure):
+    _fields_ = [("start", ctypes.c_uint32), ("size", ctypes.c_uint32), ("bits", ctypes.c_uint32),
+                ("side", ctypes.c_uint32)]
+
+
 class raduls_array(ctypes.Structure):
     _fields_ = [("recs", ctypes.c_void_p), ("tmp", ctypes.c_void_p), ("n", ctypes.c_uint64)]
 
@@ -96,6 +101,8 @@ def load() -> ctypes.CDLL:
         "raduls_set_tuning": (i32, [ctypes.POINTER(raduls_tuning)]),
         "raduls_get_tuning": (i32, [ctypes.POINTER(raduls_tuning)]),
         "raduls_mid_capacity": (u32, [u32, u32]),
+        "raduls_inspect_rounds": (i32, [vp, vp, u64, u32, u32, u32, ctypes.POINTER(raduls_bin), u32,
+                                        ctypes.POINTER(ctypes.c_uint32), vp]),
         "raduls_set_profile_events": (i32, [ctypes.POINTER(ctypes.c_void_p), u32]),
         "raduls_strerror": (ctypes.c_char_p, [i32]),
     }
@@ -112,6 +119,7 @@ def exported_symbols() -> list[str]:
         "raduls_tmp_bytes", "raduls_sort", "raduls_batch_ws_bytes", "raduls_sort_batch",
         "raduls_step_ws_bytes", "raduls_histogram", "raduls_partition", "raduls_check",
         "raduls_set_tuning", "raduls_get_tuning", "raduls_mid_capacity", "raduls_strerror",
+        "raduls_inspect_rounds",
         "raduls_set_profile_events",
     ]
 
@@ -240,6 +248,19 @@ def raduls_set_profile_events(events: Sequence[int]) -> None:
 
 def raduls_mid_capacity(rec_bytes: int, key_bytes: int) -> int:
     return int(load().raduls_mid_capacity(rec_bytes, key_bytes))
+
+
+def raduls_inspect_rounds(recs, tmp, n: int, rec_bytes: int, key_bytes: int, rounds: int,
+                          cap: int = 1 << 20, stream=None) -> list[tuple[int, int, int, int]]:
+    """Run the first `rounds` global rounds only and return the large bins
+    they left, as (start, size, bits, side) tuples (synchronizes)."""
+    arr = (raduls_bin * max(cap, 1))()
+    cnt = ctypes.c_uint32(0)
+    _check(load().raduls_inspect_rounds(_ptr(recs), _ptr(tmp), n, rec_bytes, key_bytes, rounds, arr,
+                                        cap, ctypes.byref(cnt), _stream(stream)),
+           "raduls_inspect_rounds")
+    k = min(int(cnt.value), cap)
+    return [(arr[i].start, arr[i].size, arr[i].bits, arr[i].side) for i in range(k)]
 
 
 def raduls_strerror(status: int) -> str:

@@ -43,7 +43,7 @@ __host__ __device__ constexpr uint32_t scatter_lds_bytes(int rw) {
 constexpr int kMidBlock = 1024;
 constexpr int kMidWaves = kMidBlock / kWave;
 constexpr uint32_t kLdsBytes = 160 * 1024;
-constexpr uint32_t kMidStaticLds = 6 * 1024;  // static LDS of the LDS sorter (upper bound)
+constexpr uint32_t kMidStaticLds = 11 * 1024;  // static LDS of the LDS sorter (upper bound)
 // Widest digit of a job's first pass; its counters are 16-bit, two per
 // word (the words also hold the 256 counters of each wave in single-wave
 // passes).
@@ -211,6 +211,7 @@ struct Params {
   uint32_t pair;          // 1: the top-level histogram also counts digit pairs
   uint32_t pair_min_bins; // fewest second-round bins that take the pair counts
   uint32_t rounds;
+  uint32_t inspect;       // 1: stop after the rounds (no LDS, tiny or copy kernels)
   uint32_t mode;
   uint32_t count;          // arrays
   uint64_t total_cap;      // batch: records the workspace was sized for

@@ -42,6 +42,9 @@ __device__ __forceinline__ RADULS_GLOBAL T* gmem(T* p) {
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
 
+// A value the same in every lane, made a scalar (wave-uniform) one.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Workgroup barrier for LDS hand-offs.  __syncthreads() also orders global
 // memory, which makes every wave wait for all of its outstanding global loads
 // and stores (vmcnt 0) at each barrier; no barrier in these kernels publishes
@@ -1475,8 +1478,11 @@ __device__ __forceinline__ int bm_next(const uint32_t* bm, int p, int hi) {
 // order; every pass permutes `perm`, the slots (input positions) in sorted
 // order.
 struct MidLds {
-  uint64_t* key;    // [T * kstride] records of the job, input order (key words first)
-  uint32_t kstride; // words per record
+  uint64_t* kp;     // [KW][T] key words of the job's records in input order: word q of
+                    // record i at kp[q * T + i] (planes, so that neighbouring slots sit
+                    // in neighbouring banks)
+  uint64_t* pay;    // [T][RW - KW] payload words of the job's records, input order
+  uint32_t T;       // records per key plane (the job capacity)
   uint64_t kmask;   // mask of the key bytes in the top key word
   uint16_t* perm;   // [T] position -> slot
   uint32_t* cnt;    // [kMidCounterWords] digit counters / offsets of a pass
@@ -1488,7 +1494,7 @@ struct MidLds {
   uint32_t* nbig;
   uint32_t* nlist;  // [2]
   uint32_t* claim;  // next entry of the current list to claim
-  uint32_t* scan;   // [kMidWaves]
+  uint32_t* scan;   // [kMidWaves], 16-byte aligned
   unsigned long long* diff;  // [kMidWaves * (KW + 1)]
 };
 
@@ -1499,7 +1505,7 @@ struct MidLds {
 template <int KW>
 __device__ __forceinline__ void slot_key(const MidLds& L, uint32_t slot, uint64_t (&k)[KW]) {
 #pragma unroll
-  for (int q = 0; q < KW; ++q) k[q] = L.key[uint64_t(slot) * L.kstride + q];
+  for (int q = 0; q < KW; ++q) k[q] = L.kp[uint32_t(q) * L.T + slot];
   k[KW - 1] &= L.kmask;
 }
 
@@ -1577,40 +1583,81 @@ __device__ __forceinline__ void mid_scan_route_one(const Params& P, MidLds& L, u
   }
 }
 
+constexpr int kMidScanPer = int(kMidCounterWords / kMidBlock);  // counter words per thread
+
+// Offsets of a first pass are below 2^13; bit 15 of a counter half marks a
+// bucket that is left to the per-record enumeration sort (see k_mid).
+constexpr uint32_t kOffMask = 0x1FFFu, kOffFlag = 0x8000u;
+static_assert(uint32_t(kMidBlock) * mid_lane_items(1) <= kOffMask, "a job's offsets fit 13 bits");
+
 // Exclusive scan of the nd (even, <= 2 * kMidCounterWords) packed counters
 // in place over the workgroup, routing every non-empty digit's sub-range of
 // the range that starts at s (with `first`, only those left to later passes;
-// see mid_scan_route_one).  All threads call; ends with a barrier.
-__device__ __forceinline__ void mid_scan_route(const Params& P, MidLds& L, uint32_t tid, uint32_t s,
-                                               uint32_t nd, uint32_t wave_cap, bool first) {
-  constexpr int kPer = kMidCounterWords / kMidBlock;
-  const uint32_t lane = tid & 63, wave = tid >> 6;
+// see mid_scan_route_one).  Thread t scans words [t * per, t * per + per).
+// With KEEP every thread also keeps the counts (cw) and the starts (ow) of
+// the digits of its words, packed two 16-bit values per word like the
+// counters (0 counts for words past nd).  All threads call; ends with a
+// barrier.
+template <bool KEEP>
+__device__ __forceinline__ void mid_scan_route_k(const Params& P, MidLds& L, uint32_t tid, uint32_t s,
+                                                 uint32_t nd, uint32_t wave_cap, bool first,
+                                                 uint32_t (&cw)[kMidScanPer], uint32_t (&ow)[kMidScanPer]) {
+  constexpr int kPer = kMidScanPer;
+  const uint32_t lane = tid & 63, wave = uni(tid >> 6);
   const uint32_t nw = nd >> 1;
   const uint32_t per = (nw + kMidBlock - 1) / kMidBlock;
   const uint32_t base = tid * per;
   uint32_t v[kPer], sum = 0;
+  if (per == uint32_t(kPer)) {
+    const uint4 q = reinterpret_cast<const uint4*>(L.cnt)[tid];
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  } else {
 #pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    v[k] = (uint32_t(k) < per && base + k < nw) ? L.cnt[base + k] : 0u;
-    sum += (v[k] & 0xFFFFu) + (v[k] >> 16);
+    for (int k = 0; k < kPer; ++k) v[k] = (uint32_t(k) < per && base + k < nw) ? L.cnt[base + k] : 0u;
   }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) sum += (v[k] & 0xFFFFu) + (v[k] >> 16);
   const uint32_t incl = wave_inclusive_scan(sum);
   if (lane == 63) L.scan[wave] = incl;
   lds_barrier();
   uint32_t run = incl - sum;
-  for (uint32_t w = 0; w < wave; ++w) run += L.scan[w];
+  // the totals of the waves before this one: a prefix over lanes 0..15
+  {
+    const uint32_t tv = lane < uint32_t(kMidWaves) ? L.scan[lane] : 0u;
+    const uint32_t ti = wave_inclusive_scan(tv);
+    run += uint32_t(__builtin_amdgcn_readlane(int(ti - tv), int(wave)));
+  }
+  uint32_t out[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
+    const uint32_t c0 = v[k] & 0xFFFFu, c1 = v[k] >> 16;
+    out[k] = run | ((run + c0) << 16);
+    if (KEEP) {
+      cw[k] = v[k];
+      ow[k] = out[k];
+    }
     if (uint32_t(k) < per && base + k < nw) {
-      const uint32_t c0 = v[k] & 0xFFFFu, c1 = v[k] >> 16;
-      L.cnt[base + k] = run | ((run + c0) << 16);
       if (c0) mid_scan_route_one(P, L, s + run, c0, wave_cap, first);
-      run += c0;
-      if (c1) mid_scan_route_one(P, L, s + run, c1, wave_cap, first);
-      run += c1;
+      if (c1) mid_scan_route_one(P, L, s + run + c0, c1, wave_cap, first);
+      run += c0 + c1;
     }
   }
+  if (per == uint32_t(kPer)) {
+    reinterpret_cast<uint4*>(L.cnt)[tid] = make_uint4(out[0], out[1], out[2], out[3]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (uint32_t(k) < per && base + k < nw) L.cnt[base + k] = out[k];
+  }
   lds_barrier();
+}
+__device__ __forceinline__ void mid_scan_route(const Params& P, MidLds& L, uint32_t tid, uint32_t s,
+                                               uint32_t nd, uint32_t wave_cap, bool first) {
+  uint32_t cw[kMidScanPer], ow[kMidScanPer];
+  mid_scan_route_k<false>(P, L, tid, s, nd, wave_cap, first, cw, ow);
 }
 
 // Workgroup pass: records with slots src[] and digits dg[] (ITEMS per thread,
@@ -1858,7 +1905,6 @@ __device__ __forceinline__ uint32_t vzero() {
   asm volatile("v_mov_b32 %0, 0" : "=v"(z));
   return z;
 }
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 struct JobV {  // a job descriptor in vector registers
   uint32_t w[5];
 };
@@ -1880,7 +1926,7 @@ __device__ __forceinline__ MidJob uni_job(const JobV& v) {
 // Records [0, m) of a job (source `src`) into registers, all loads in flight
 // together, and the first record's key words, unmasked (every thread's
 // reference for the key spread; masking them here would wait for the load);
-// m = 0 loads nothing.
+// m = 0 loads nothing.  Items past m keep what they held (never used).
 template <int RW, int KW, int ITEMS>
 __device__ __forceinline__ void mid_fetch(const uint8_t* src, uint32_t m, uint32_t tid,
                                           uint64_t (&kr)[ITEMS][RW], uint64_t (&key0)[KW]) {
@@ -1890,23 +1936,137 @@ __device__ __forceinline__ void mid_fetch(const uint8_t* src, uint32_t m, uint32
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const uint32_t i = j * kMidBlock + tid;
-#pragma unroll
-    for (int q = 0; q < RW; ++q) kr[j][q] = 0;
     if (i < m) load_rec<RW>(src, i, kr[j]);
   }
+}
+
+// Digit [lob, lob + w) of a masked key; a single shift for one-word keys.
+template <int KW>
+__device__ __forceinline__ uint32_t key_digit(const uint64_t (&k)[KW], uint32_t lob, uint32_t w) {
+  if constexpr (KW == 1) {
+    return uint32_t(k[0] >> lob) & ((1u << w) - 1u);
+  } else {
+    return digit_of<KW>(k, lob, w);
+  }
+}
+
+// Record i of a job from registers into LDS: key words to their planes,
+// payload words to the record's payload row.
+template <int RW, int KW>
+__device__ __forceinline__ void mid_put(const MidLds& L, uint32_t i, const uint64_t (&w)[RW]) {
+  constexpr int PW = RW - KW;
+#pragma unroll
+  for (int q = 0; q < KW; ++q) L.kp[uint32_t(q) * L.T + i] = w[q];
+  if constexpr (PW > 0) {
+    if constexpr (PW % 2 == 0) {
+      u64x2* d = reinterpret_cast<u64x2*>(L.pay + i * uint32_t(PW));
+#pragma unroll
+      for (int q = 0; q < PW / 2; ++q) {
+        u64x2 v;
+        v.x = w[KW + 2 * q];
+        v.y = w[KW + 2 * q + 1];
+        d[q] = v;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < PW; ++q) L.pay[i * uint32_t(PW) + q] = w[KW + q];
+    }
+  }
+}
+
+// Record `slot` of a job from LDS (unmasked key words, then payload).
+template <int RW, int KW>
+__device__ __forceinline__ void mid_get(const MidLds& L, uint32_t slot, uint64_t (&w)[RW]) {
+  constexpr int PW = RW - KW;
+#pragma unroll
+  for (int q = 0; q < KW; ++q) w[q] = L.kp[uint32_t(q) * L.T + slot];
+  if constexpr (PW > 0) {
+    if constexpr (PW % 2 == 0) {
+      const u64x2* s = reinterpret_cast<const u64x2*>(L.pay + slot * uint32_t(PW));
+#pragma unroll
+      for (int q = 0; q < PW / 2; ++q) {
+        const u64x2 v = s[q];
+        w[KW + 2 * q] = v.x;
+        w[KW + 2 * q + 1] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < PW; ++q) w[KW + q] = L.pay[slot * uint32_t(PW) + q];
+    }
+  }
+}
+
+// Sorts the positions [st, st + cn) of perm, 2 <= cn <= N, in registers:
+// the members' slots and then their keys are read together, each member's
+// place is the number of members whose (key, slot) pair is smaller, and the
+// slots are written back in that order.  Positions past the bucket reread
+// its last member and count for nobody.
+template <int KW, int N>
+__device__ __forceinline__ void mid_sort_bucket(const MidLds& L, uint32_t st, uint32_t cn) {
+  uint32_t sv[N], rk[N];
+  uint64_t kv[N][KW];
+#pragma unroll
+  for (int v = 0; v < N; ++v) sv[v] = L.perm[st + min(uint32_t(v), cn - 1u)];
+#pragma unroll
+  for (int v = 0; v < N; ++v) {
+    slot_key<KW>(L, sv[v], kv[v]);
+    rk[v] = 0;
+  }
+#pragma unroll
+  for (int x = 0; x < N; ++x) {
+#pragma unroll
+    for (int y = x + 1; y < N; ++y) {
+      const bool yx = key_lt<KW>(kv[y], kv[x]) || (sv[y] < sv[x] && key_eq<KW>(kv[y], kv[x]));
+      const bool in = uint32_t(y) < cn;
+      rk[x] += (in && yx) ? 1u : 0u;
+      rk[y] += (in && !yx) ? 1u : 0u;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < N; ++v)
+    if (uint32_t(v) < cn) L.perm[st + rk[v]] = uint16_t(sv[v]);
+}
+
+// Sorts the positions [st, st + cn) of perm, 2 <= cn <= 64, with one wave:
+// lane v holds member v's slot and key, and counts the members whose (key,
+// slot) pair is smaller as they are broadcast one by one; then it writes its
+// slot to its place (one wave's LDS accesses stay in order, so every read of
+// the bucket precedes these writes).
+template <int KW>
+__device__ __forceinline__ void mid_wave_sort_bucket(const MidLds& L, uint32_t st, uint32_t cn,
+                                                     uint32_t lane) {
+  const uint32_t sv = L.perm[st + min(lane, cn - 1u)];
+  uint64_t kv[KW];
+  slot_key<KW>(L, sv, kv);
+  uint32_t rk = 0;
+  for (uint32_t u = 0; u < cn; ++u) {
+    uint64_t ku[KW];
+#pragma unroll
+    for (int q = 0; q < KW; ++q) {
+      const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(kv[q])), int(u)));
+      const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(kv[q] >> 32)), int(u)));
+      ku[q] = uint64_t(lo) | (uint64_t(hi) << 32);
+    }
+    const uint32_t su = uint32_t(__builtin_amdgcn_readlane(int(sv), int(u)));
+    rk += (key_lt<KW>(ku, kv) || (su < sv && key_eq<KW>(ku, kv))) ? 1u : 0u;
+  }
+  if (lane < cn) L.perm[st + rk] = uint16_t(sv);
 }
 
 // Sorts jobs of at most mid_max records entirely in LDS (the small-bin case of
 // Sec. 3.2, with LDS in the role of the cache).  A job's records are read from
 // HBM once and kept in LDS in input order; every pass permutes a 16-bit slot
 // array instead of moving records.  The first pass splits the job on up to
-// kMidFirstBits of the highest bits in which its keys differ.  Sub-ranges
-// still larger than tiny_max get further passes, by the whole workgroup when
-// they exceed one wave's capacity, else by single waves in parallel, round by
-// round.  Ranges of at most tiny_max records are finished by enumeration sort
-// (Sec. 2.2, 3.3): each record's place is the number of (key, slot) pairs
-// below its own.  The job is written out in order, each thread gathering its
-// records from LDS through the permutation, in coalesced stores.
+// kMidFirstBits of the highest bits in which its keys differ, with the digits
+// taken from keys still in registers.  Its buckets of at most tiny_max records
+// are finished at once by enumeration sort (Sec. 2.2, 3.3): each record's
+// place is the number of (key, slot) pairs of its bucket below its own, every
+// thread stepping through the buckets of all its records together so that
+// their LDS reads overlap.  Sub-ranges still larger than tiny_max get further
+// passes, by the whole workgroup when they exceed one wave's capacity, else by
+// single waves in parallel, round by round, and their tiny ranges are again
+// finished by enumeration sort.  The job is written out in order, each thread
+// gathering its records from LDS through the permutation, in coalesced stores.
 //
 // Jobs are pipelined so that no wave waits for HBM in the middle of a job:
 // workgroups claim jobs from a shared counter (after a first one of their
@@ -1919,22 +2079,41 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
   constexpr int W = kMidWaves;
   constexpr int WI = mid_wave_items(RW);
   constexpr int ITEMS = mid_items(RW, KW);
+  // keys of the job's records stay in registers through the first pass
+  // (digits and the enumeration sort's own key without LDS reads) when they
+  // are short; longer ones are read back from their LDS planes
+  constexpr bool kKeep = KW <= 2;
+  constexpr int KK = kKeep ? KW : 1;
+  // first-pass buckets of 2..kOwnMax records are sorted in registers by one
+  // thread each (pairs only for long keys: the registers run out), larger
+  // ones up to 64 records by one wave each
+  constexpr uint32_t kOwnMax = kKeep ? 4u : 2u;
+  constexpr uint32_t kEsCap = 1024;    // entries of the workgroup's list of such buckets
+  constexpr uint32_t kEsWaveCap = 128; // entries of its list of buckets sorted by a wave
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ uint32_t s_big[kMidBigCap];
   __shared__ uint32_t s_list[2][kMidListCap];
   __shared__ uint32_t s_nbig, s_nlist[2], s_claim, s_next, s_next2;
-  __shared__ uint32_t s_scan[W];
+  __shared__ __align__(16) uint32_t s_scan[W];
   __shared__ unsigned long long s_diff[W * (KW + 1)];
+  __shared__ uint32_t s_hb[2];  // highest differing key bit + 1 of a job, by job parity
+  __shared__ uint32_t s_flag[2];  // a job's first pass left buckets for the fallback enumeration sort
+  __shared__ uint32_t s_esn[2];  // a job's listed buckets: thread list | wave list << 16
+  __shared__ uint32_t s_es[kEsCap], s_wbk[kEsWaveCap];
 
-  const uint32_t T = P.mid_max;
+  const uint32_t T = P.mid_max;  // largest job (<= the LDS layout's capacity)
+  // the LDS layout is laid out for the largest job of this record width, so
+  // that its offsets are compile-time constants
+  constexpr uint32_t TC = mid_cap(RW, KW);
   MidLds L;
-  L.key = reinterpret_cast<uint64_t*>(smem);
-  L.kstride = RW;
+  L.kp = reinterpret_cast<uint64_t*>(smem);
+  L.pay = L.kp + TC * uint32_t(KW);
+  L.T = TC;
   L.kmask = P.kmask;
-  L.perm = reinterpret_cast<uint16_t*>(L.key + uint64_t(T) * RW);
-  L.cnt = reinterpret_cast<uint32_t*>(L.perm + align_up(T, 2));
+  L.perm = reinterpret_cast<uint16_t*>(L.kp + TC * uint32_t(RW));
+  L.cnt = reinterpret_cast<uint32_t*>(L.perm + align_up(TC, 2));
   L.bm = L.cnt + kMidCounterWords;
-  L.bmb = L.bm + (T >> 5) + 2;
+  L.bmb = L.bm + (TC >> 5) + 2;
   L.big = s_big;
   L.list0 = s_list[0];
   L.list1 = s_list[1];
@@ -1952,11 +2131,17 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
   if (blockIdx.x >= njobs) return;
 
   MidJob job = P.L.mid[blockIdx.x];  // job i
-  uint64_t kr[ITEMS][RW], key0[KW];
+  uint64_t kr[ITEMS][RW] = {}, key0[KW];
   mid_fetch<RW, KW, ITEMS>(job.src, job.size <= T ? job.size : 0u, threadIdx.x, kr, key0);
   if (threadIdx.x == 0) {
     s_next = G + atomicAdd(&c->mid_claim, 1u);
     s_next2 = G + atomicAdd(&c->mid_claim, 1u);
+    s_hb[0] = 0;
+    s_hb[1] = 0;
+    s_flag[0] = 0;
+    s_flag[1] = 0;
+    s_esn[0] = 0;
+    s_esn[1] = 0;
   }
   __syncthreads();
   bool have1 = s_next < njobs;  // job i+1 exists
@@ -1967,7 +2152,7 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
   // placed at its head
   __builtin_amdgcn_s_waitcnt(0);
 
-  for (;;) {
+  for (uint32_t par = 0;; par ^= 1u) {
     // the thread index is made opaque per job so that the per-item
     // addresses derived from it are recomputed instead of held in registers
     // across the whole loop
@@ -1977,22 +2162,23 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
     if (job.size > T && tid == 0) atomicOr(&c->error, kErrMidSize);
     const uint32_t m = job.size <= T ? job.size : 0u;
 
-    // the records (already in registers) into LDS; the keys' spread against
-    // the first key
-    uint64_t dk[KW];
+    // the records (already in registers) into LDS; their keys kept; the
+    // keys' spread against the first key
+    uint64_t dk[KW], kk[ITEMS][KK];
 #pragma unroll
     for (int q = 0; q < KW; ++q) dk[q] = 0;
     key0[KW - 1] &= P.kmask;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       const uint32_t i = j * kMidBlock + tid;
+      uint64_t k[KW];
+      key_of<KW>(kr[j], P.kmask, k);
+#pragma unroll
+      for (int q = 0; q < KK; ++q) kk[j][q] = k[q];
       if (i < m) {
-        uint64_t k[KW];
-        key_of<KW>(kr[j], P.kmask, k);
 #pragma unroll
         for (int q = 0; q < KW; ++q) dk[q] |= k[q] ^ key0[q];
-#pragma unroll
-        for (int q = 0; q < RW; ++q) L.key[uint64_t(i) * RW + q] = kr[j][q];
+        mid_put<RW, KW>(L, i, kr[j]);
       }
     }
     // into the freed registers the records of job i+1; then the descriptor of
@@ -2012,90 +2198,202 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
       L.bm[q] = 0;
       L.bmb[q] = 0;
     }
-    for (uint32_t q = tid; q < kMidCounterWords; q += kMidBlock) L.cnt[q] = 0;
+    static_assert(kMidCounterWords == 4 * kMidBlock, "one 16-byte clear per thread");
+    reinterpret_cast<uint4*>(L.cnt)[tid] = make_uint4(0, 0, 0, 0);
     if (tid == 0) {
       s_nbig = 0;
       s_nlist[0] = 0;
       s_nlist[1] = 0;
     }
-    // slots of a job start in input order, so only the keys can differ
-    (void)mid_wg_spread<KW>(L, tid, dk, 0u);
-    bool by_slot;
-    const uint32_t hb = pair_top<KW>(dk, 0u, by_slot);
+    // the job's highest differing key bit: per wave, then the workgroup's
+    // maximum by one LDS atomic per wave (slots start in input order, so only
+    // the keys can differ)
+    {
+      uint64_t o[KW];
+#pragma unroll
+      for (int q = 0; q < KW; ++q) o[q] = wave_or(dk[q]);
+      const int tb = top_bit<KW>(o);
+      if (lane == 0 && tb >= 0) atomicMax(&s_hb[par], uint32_t(tb + 1));
+    }
+    lds_barrier();
+    const uint32_t hb = uni(s_hb[par]);
+    // (the other parity's words were last read before this job's barriers)
+    // (a zero made at the point of use: a zero kept in registers across the
+    // loop gets spilled, and its reload would wait for the prefetch loads)
+    if (tid == 0) {
+      const uint32_t z = vzero();
+      s_hb[par ^ 1u] = z;
+      s_flag[par ^ 1u] = z;
+      s_esn[par ^ 1u] = z;
+    }
+    bool windows = false;  // tiny ranges left for the window enumeration sort
+    bool later = false;    // ranges left for later passes
     if (m > min(tiny, kMidDirectEs) && hb > 0) {
-      // first pass over the whole job
+      // first pass over the whole job, on digits from the kept keys: about
+      // two buckets per record (2^w >= 2m), so that most buckets hold one
+      // record or none
       const uint32_t lg = 32u - uint32_t(__clz(m));
-      const uint32_t w = min(min(hb, uint32_t(kMidFirstBits)), lg);
+      const uint32_t w = min(min(hb, uint32_t(kMidFirstBits)), lg + 1u);
       const uint32_t lob = hb - w;
-      uint32_t src[ITEMS], dg[ITEMS];
-      bool valid[ITEMS];
+      const uint32_t nd = 1u << w;
+      uint32_t dg[ITEMS], r[ITEMS];
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
         const uint32_t i = j * kMidBlock + tid;
-        valid[j] = i < m;
-        src[j] = i;
-        dg[j] = 0;
-        if (valid[j]) {
-          uint64_t k[KW];
-          slot_key<KW>(L, i, k);
-          dg[j] = digit_of<KW>(k, lob, w);
+        uint64_t k[KW];
+        if constexpr (kKeep) {
+#pragma unroll
+          for (int q = 0; q < KW; ++q) k[q] = kk[j][q];
+        } else {
+          slot_key<KW>(L, i < m ? i : 0u, k);
+        }
+        dg[j] = i < m ? key_digit<KW>(k, lob, w) : 0u;
+        r[j] = i < m ? pair_count(L.cnt, dg[j]) : 0u;
+      }
+      lds_barrier();
+      uint32_t cw[kMidScanPer], ow[kMidScanPer];
+      mid_scan_route_k<true>(P, L, tid, 0, nd, wave_cap, true, cw, ow);
+      // Buckets of 2..tiny_max records are finished by enumeration sort once
+      // every record is placed.  The thread that scanned a bucket's counters
+      // lists it: buckets of 2..kOwnMax records in the thread list, larger
+      // ones up to 64 in the wave list (a wave reserves room in both for all
+      // of its lanes' entries with one atomic on a packed pair of counts).
+      // After the places are written a thread sorts one bucket of the thread
+      // list in registers and a wave one of the wave list, so that the work
+      // is spread evenly over lanes whatever the buckets' sizes.  A bucket
+      // that finds its list full is marked in bit 15 of its (13-bit) offset
+      // and left, like buckets of more than 64 records, to the per-record
+      // fallback.
+      const uint32_t lim1 = min(kOwnMax, tiny), lim2 = min(uint32_t(kWave), tiny);
+      uint32_t own1 = 0, own2 = 0;
+      bool fb = false;
+#pragma unroll
+      for (int k = 0; k < kMidScanPer; ++k) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t cn = (cw[k] >> (16 * h)) & 0xFFFFu;
+          own1 |= (cn >= 2 && cn <= lim1) ? (1u << (2 * k + h)) : 0u;
+          own2 |= (cn > lim1 && cn >= 2 && cn <= lim2) ? (1u << (2 * k + h)) : 0u;
+          fb = fb || (cn > lim2 && cn <= tiny);
         }
       }
-      mid_wg_place<ITEMS>(P, L, tid, 0, w, src, dg, valid, wave_cap, true);
-      // buckets of at most tiny_max records are finished here by enumeration
-      // sort (Sec. 2.2, 3.3): each record's place in its bucket is the number
-      // of (key, slot) pairs in the bucket below its own; the bucket bounds
-      // are the digit offsets just computed
-      const uint32_t nd = 1u << w;
-      uint32_t fin[ITEMS];
+      const uint32_t no = uint32_t(__popc(own1)) | (uint32_t(__popc(own2)) << 16);
+      const uint32_t incl = wave_inclusive_scan(no);
+      uint32_t wb = 0;
+      if (lane == 63 && incl) wb = atomicAdd(&s_esn[par], incl);
+      uint32_t idx = uint32_t(__builtin_amdgcn_readlane(int(wb), 63)) + incl - no;
+      // every record to its place (its bucket's offset from the scanned
+      // counters, masked: owners may be marking buckets meanwhile)
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
-        fin[j] = ~0u;
-        if (!valid[j]) continue;
-        const uint32_t b0 = pair_get(L.cnt, dg[j]);
-        const uint32_t b1 = dg[j] + 1 < nd ? pair_get(L.cnt, dg[j] + 1) : m;
-        if (b1 - b0 < 2 || b1 - b0 > tiny) continue;
-        uint64_t kp[KW];
-        slot_key<KW>(L, src[j], kp);
-        uint32_t r = 0;
-        // with multi-word keys four members per step, their slots and then
-        // their keys read together (positions past the bucket reread its
-        // last member and are not counted), so that a bucket of up to four
-        // costs one round trip for the slots and one for the keys; with
-        // one-word keys the extra instructions cost more than they save, and
-        // with more than four words the registers run out
-        constexpr uint32_t kStep = KW >= 2 && KW <= 4 ? 4u : 1u;
-        for (uint32_t q = b0; q < b1; q += kStep) {
-          uint32_t sq[kStep];
-#pragma unroll
-          for (uint32_t u = 0; u < kStep; ++u) sq[u] = L.perm[kStep > 1 ? min(q + u, b1 - 1) : q];
-#pragma unroll
-          for (uint32_t u = 0; u < kStep; ++u) {
-            uint64_t kq[KW];
-            slot_key<KW>(L, sq[u], kq);
-            r += (q + u < b1 && (key_lt<KW>(kq, kp) || (sq[u] < src[j] && key_eq<KW>(kq, kp)))) ? 1u : 0u;
-          }
-        }
-        fin[j] = b0 + r;
+        const uint32_t i = j * kMidBlock + tid;
+        const uint32_t d = dg[j];
+        const uint32_t lo = (L.cnt[d >> 1] >> ((d & 1u) << 4)) & kOffMask;
+        if (i < m) L.perm[lo + r[j]] = uint16_t(i);
       }
-      lds_barrier();  // every read of perm is done
+      // this thread's list entries (a select over its counter words per entry)
+      uint32_t both = own1 | own2;
+      while (both) {
+        const uint32_t bit = uint32_t(__ffs(both)) - 1u;
+        both &= both - 1u;
+        uint32_t wc = cw[0], wo = ow[0];
 #pragma unroll
-      for (int j = 0; j < ITEMS; ++j)
-        if (fin[j] != ~0u) L.perm[fin[j]] = uint16_t(src[j]);
+        for (int k = 1; k < kMidScanPer; ++k) {
+          wc = (bit >> 1) == uint32_t(k) ? cw[k] : wc;
+          wo = (bit >> 1) == uint32_t(k) ? ow[k] : wo;
+        }
+        const uint32_t sh = (bit & 1u) << 4;
+        const uint32_t ent = ((wo >> sh) & 0xFFFFu) | (((wc >> sh) & 0xFFFFu) << 16);
+        const bool first = (own1 >> bit) & 1u;
+        const uint32_t at = first ? (idx & 0xFFFFu) : (idx >> 16);
+        if (first && at < kEsCap) {
+          s_es[at] = ent;
+        } else if (!first && at < kEsWaveCap) {
+          s_wbk[at] = ent;
+        } else {
+          // (this thread alone writes its counter words in this phase; the
+          // others only read their offsets, masked)
+          const uint32_t wi = tid * ((nd / 2 + kMidBlock - 1) / kMidBlock) + (bit >> 1);
+          L.cnt[wi] |= kOffFlag << sh;
+          fb = true;
+        }
+        idx += first ? 1u : 0x10000u;
+      }
+      if (fb) s_flag[par] = 1u;
       lds_barrier();
+      const bool fallback = s_flag[par] != 0;
+      // (the lists of ranges for later passes were filled by the scan)
+      later = (s_nbig | s_nlist[0]) != 0;
+      // the listed buckets; nobody else touches their positions, so no
+      // barrier is needed
+      const uint32_t esn = s_esn[par];
+      for (uint32_t e = tid; e < min(esn & 0xFFFFu, kEsCap); e += kMidBlock) {
+        const uint32_t ent = s_es[e];
+        mid_sort_bucket<KW, kOwnMax>(L, ent & 0xFFFFu, ent >> 16);
+      }
+      for (uint32_t e = wave; e < min(esn >> 16, kEsWaveCap); e += W) {
+        const uint32_t ent = uni(s_wbk[e]);
+        mid_wave_sort_bucket<KW>(L, ent & 0xFFFFu, ent >> 16, lane);
+      }
+      if (fallback) {
+        // buckets of 65..tiny_max records and marked ones: each member
+        // counts the (key, slot) pairs of its bucket below its own
+        uint32_t fin[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+          const uint32_t i = j * kMidBlock + tid;
+          const uint32_t d = dg[j];
+          const uint32_t wd = L.cnt[d >> 1];
+          const uint32_t wn = L.cnt[min((d >> 1) + 1, (nd >> 1) - 1)];
+          const uint32_t h0 = (d & 1u) ? wd >> 16 : wd & 0xFFFFu;
+          const uint32_t lo = h0 & kOffMask;
+          const uint32_t hi = (d & 1u) ? (d + 1 < nd ? wn & kOffMask : m) : (wd >> 16) & kOffMask;
+          const uint32_t cnt = hi - lo;
+          fin[j] = ~0u;
+          if (!(i < m && ((cnt > uint32_t(kWave) && cnt <= tiny) || (h0 & kOffFlag)))) continue;
+          uint64_t kp[KW];
+          slot_key<KW>(L, i, kp);
+          uint32_t rnk = 0;
+          // with multi-word keys four members per step, their slots and then
+          // their keys read together (positions past the bucket reread its
+          // last member and are not counted)
+          constexpr uint32_t kStep = KW >= 2 && KW <= 4 ? 4u : 1u;
+          for (uint32_t q = lo; q < hi; q += kStep) {
+            uint32_t sq[kStep];
+#pragma unroll
+            for (uint32_t u = 0; u < kStep; ++u) sq[u] = L.perm[kStep > 1 ? min(q + u, hi - 1) : q];
+#pragma unroll
+            for (uint32_t u = 0; u < kStep; ++u) {
+              uint64_t kq[KW];
+              slot_key<KW>(L, sq[u], kq);
+              rnk += (q + u < hi && (key_lt<KW>(kq, kp) || (sq[u] < i && key_eq<KW>(kq, kp)))) ? 1u : 0u;
+            }
+          }
+          fin[j] = lo + rnk;
+        }
+        lds_barrier();  // every read of perm is done
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+          if (fin[j] != ~0u) L.perm[fin[j]] = uint16_t(j * kMidBlock + tid);
+        lds_barrier();
+      }
+      // (the later passes touch only ranges above tiny_max, which these
+      // buckets are not part of, and the write-out waits at a barrier)
     } else {
       // one key (already in slot order), or a job small enough for the
       // enumeration sort below
       for (uint32_t i = tid; i < m; i += kMidBlock) L.perm[i] = uint16_t(i);
       if (tid == 0) L.bm[0] = 1u;
-      if (hb > 0)
+      if (hb > 0) {
+        windows = true;
         for (uint32_t q = tid; q < (m + 31) >> 5; q += kMidBlock)
           L.bmb[q] = q < (m >> 5) ? ~0u : ((1u << (m & 31)) - 1u);
+      }
       lds_barrier();
     }
     // ranges too large for one wave
     bool passes = false;  // (uniform: taken from LDS counters after barriers)
-    for (;;) {
+    for (; later;) {
       const uint32_t nbig = min(s_nbig, kMidBigCap);
       if (nbig == 0) break;
       passes = true;
@@ -2106,7 +2404,7 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
       mid_wg_pass<KW, ITEMS>(P, L, tid, e & 0xFFFFu, e >> 16, wave_cap);
     }
     // medium ranges: one wave each, round by round
-    for (uint32_t cur = 0;; cur ^= 1) {
+    for (uint32_t cur = 0; later; cur ^= 1) {
       const uint32_t nl = min(s_nlist[cur], kMidListCap);
       if (nl == 0) break;
       passes = true;
@@ -2127,13 +2425,14 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
       if (tid == 0) s_nlist[cur] = 0;
     }
     if (passes) lds_barrier();  // without later passes perm is complete already
+    windows = windows || passes;
 
     // ---- tiny ranges the later passes produced (inside positions marked in
     // bmb): enumeration sort; everything else is in place.  A range belongs
     // to the wave that owns the 64-position window its first position falls
     // in, so each wave reads, ranks and rewrites only positions no other wave
-    // touches.
-    const uint32_t nwin = (m + kWave - 1) / kWave;
+    // touches.  Without later passes the first pass finished every range.
+    const uint32_t nwin = windows ? (m + kWave - 1) / kWave : 0u;
     for (uint32_t k = wave; k < nwin; k += W) {
       const uint32_t w0 = k * kWave;
       if ((L.bmb[w0 >> 5] | L.bmb[(w0 >> 5) + 1]) == 0) continue;
@@ -2161,7 +2460,10 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
         uint64_t kp[KW];
         slot_key<KW>(L, slot[h], kp);
         uint32_t r = 0;
-        constexpr int kStep = KW >= 2 && KW <= 4 ? 4 : 1;  // as in the first pass
+        // four members per step with multi-word keys: their slots and then
+        // their keys read together (positions past the range reread its last
+        // member and are not counted)
+        constexpr int kStep = KW >= 2 && KW <= 4 ? 4 : 1;
         for (int q = s; q < e; q += kStep) {
           uint32_t sq[kStep];
 #pragma unroll
@@ -2195,21 +2497,31 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
     lds_barrier();
     const uint32_t idx3 = s_next;
     // the job in order: each thread gathers records from LDS through the
-    // permutation and stores them coalesced
+    // permutation and stores them coalesced (the slots of all its positions
+    // read first, with no branch, so that those reads overlap)
+    {
+      uint32_t sl[ITEMS];
+      bool bad = false;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const uint32_t p = j * kMidBlock + tid;
-      if (p < m) {
-        uint32_t sl = L.perm[p];
-        if (sl >= m) {  // never taken while the passes above keep perm a permutation
-          atomicOr(&c->error, kErrBounds);
-          sl = 0;
-        }
-        uint64_t r[RW];
-#pragma unroll
-        for (int q = 0; q < RW; ++q) r[q] = L.key[uint64_t(sl) * RW + q];
-        store_rec<RW>(reinterpret_cast<uint8_t*>(job.dst), p, r, false);
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t p = j * kMidBlock + tid;
+        sl[j] = L.perm[p < m ? p : 0u];
       }
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t p = j * kMidBlock + tid;
+        // (never out of range while the passes above keep perm a permutation)
+        bad = bad || (p < m && sl[j] >= m);
+        sl[j] = sl[j] < m ? sl[j] : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t p = j * kMidBlock + tid;
+        uint64_t r[RW];
+        mid_get<RW, KW>(L, sl[j], r);
+        if (p < m) store_rec<RW>(reinterpret_cast<uint8_t*>(job.dst), p, r, false);
+      }
+      if (bad) atomicOr(&c->error, kErrBounds);
     }
     lds_barrier();  // the records are rewritten by the next job
     if (!have1) break;
@@ -2437,6 +2749,7 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
     if (r <= 1) prof_mark(slot + 1, 1, s);
     k_classify<KW><<<P.grid_classify, 256, 0, s>>>(P, cur);
   }
+  if (P.inspect) return hipGetLastError();
   prof_mark(kProfMid, 0, s);
   k_tiny<RW, KW><<<P.grid_tiny, kMidBlock, 0, s>>>(P);
   k_mid<RW, KW><<<P.grid_mid, kMidBlock, P.mid_lds_bytes, s>>>(P);

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "raduls.h"
 #include "raduls_common.hpp"
@@ -230,7 +231,7 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
                                  : std::max<uint32_t>(1, std::min<uint32_t>(s.cap_tiles, 2 * cus));
   P.grid_classify = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_large, 4 * cus));
   P.scatter_lds_bytes = scatter_lds_bytes(int(R / 8));
-  P.mid_lds_bytes = mid_dynamic_lds(e.mid_max, int(R / 8));
+  P.mid_lds_bytes = mid_dynamic_lds(mid_capacity(R / 8, (K + 7) / 8), int(R / 8));
   P.grid_mid = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_mid, cus));
   P.grid_tiny = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_mid / kMidWaves + 1, 4 * cus));
   P.grid_copy = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_copy, 8 * cus));
@@ -295,6 +296,56 @@ int raduls_sort(void* recs, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t 
   P.n = n;
   if (n <= e.mid_max) P.rounds = 0;
   return launch(P, rec_bytes, key_bytes, stream);
+}
+
+int raduls_inspect_rounds(void* recs, void* tmp, uint64_t n, uint32_t rec_bytes,
+                          uint32_t key_bytes, uint32_t rounds, raduls_bin* bins, uint32_t cap,
+                          uint32_t* count, hipStream_t stream) {
+  int st = check_shape(rec_bytes, key_bytes);
+  if (st) return st;
+  if (!count || (cap && !bins)) return RADULS_E_INVALID;
+  *count = 0;
+  if (n >= (1ull << 32)) return RADULS_E_UNSUPPORTED;
+  if (rounds == 0) return RADULS_E_INVALID;
+  if (!recs || !tmp) return RADULS_E_INVALID;
+  if (misaligned(recs) || misaligned(tmp)) return RADULS_E_ALIGN;
+  const Eff e = effective(current_tuning(), rec_bytes, key_bytes);
+  const Shape s = plan_shape(n, 1, rec_bytes, key_bytes, e, false, use_pair(e, n, key_bytes));
+  const uint64_t need = aux_offset(n, rec_bytes) + s.bytes;
+  if (overlap(recs, n * rec_bytes, tmp, need)) return RADULS_E_INVALID;
+  st = check_room(tmp, need);
+  if (st) return st;
+  if (n <= e.mid_max) return RADULS_OK;  // no round: the whole array is one LDS job
+  Params P;
+  uint8_t* aux = static_cast<uint8_t*>(tmp) + aux_offset(n, rec_bytes);
+  fill_params(P, e, s, aux, rec_bytes, key_bytes, kModeSort, 1);
+  P.recs = static_cast<uint8_t*>(recs);
+  P.tmp = static_cast<uint8_t*>(tmp);
+  P.n = n;
+  P.rounds = std::min(rounds, s.rounds);
+  P.inspect = 1;
+  st = launch(P, rec_bytes, key_bytes, stream);
+  if (st) return st;
+  if (hipStreamSynchronize(stream) != hipSuccess) return RADULS_E_HIP;
+  Ctrl c;
+  if (hipMemcpy(&c, P.L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) return RADULS_E_HIP;
+  const uint32_t side = P.rounds & 1;
+  const uint32_t nb = std::min(c.large_count[side], P.L.cap_large);
+  *count = nb;
+  const uint32_t take = std::min(nb, cap);
+  if (take) {
+    std::vector<Bin> host(take);
+    if (hipMemcpy(host.data(), P.L.large[side], take * sizeof(Bin), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return RADULS_E_HIP;
+    for (uint32_t i = 0; i < take; ++i) {
+      bins[i].start = host[i].start;
+      bins[i].size = host[i].size;
+      bins[i].bits = host[i].bits;
+      bins[i].side = host[i].side;
+    }
+  }
+  return c.error ? RADULS_E_DEVICE : RADULS_OK;
 }
 
 int raduls_batch_ws_bytes(uint32_t count, uint64_t total_n, uint32_t rec_bytes,

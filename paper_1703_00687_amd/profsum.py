@@ -61,7 +61,7 @@ def _per_kernel(path: str, counter: str) -> dict:
     return vals
 
 
-def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, n: int,
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, n: int, rec_bytes: int,
             command: str, out_json: str, out_md: str) -> dict:
     f = _per_kernel(fetch_csv, "FETCH_SIZE")
     w = _per_kernel(write_csv, "WRITE_SIZE")
@@ -71,7 +71,7 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, n: int
     w_scale = copy_bytes / (statistics.mean(big_copy_w) * 1024)
     kf = statistics.mean(f[kernel]) * 1024 * f_scale
     kw = statistics.mean(w[kernel]) * 1024 * w_scale
-    rec = {"kernel": kernel, "n": n, "kernel_source_hash": kernel_source_hash(),
+    rec = {"kernel": kernel, "n": n, "rec_bytes": rec_bytes, "kernel_source_hash": kernel_source_hash(),
            "fetch_bytes_per_launch": kf, "write_bytes_per_launch": kw,
            "hbm_bytes_per_launch": kf + kw, "fetch_scale": f_scale, "write_scale": w_scale,
            "calibration": f"{COPY_KERNEL} of {copy_bytes} bytes", "command": command}
@@ -93,7 +93,7 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, n: int
             continue
         lines.append(f"| {short(k)} | {len(fv)} | {fm:.3f} (max) | {wm:.3f} (max) |")
     lines += ["", f"Dominant kernel `{short(kernel)}`: {kf / 1e9:.3f} GB read + {kw / 1e9:.3f} GB written "
-              f"per launch = {(kf + kw) / 1e9:.3f} GB (algorithmic 2nR = {2 * n * 16 / 1e9:.3f} GB)."]
+              f"per launch = {(kf + kw) / 1e9:.3f} GB (algorithmic 2nR = {2 * n * rec_bytes / 1e9:.3f} GB)."]
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     return rec
@@ -112,6 +112,7 @@ if __name__ == "__main__":
     p.add_argument("--kernel", required=True)
     p.add_argument("--copy-bytes", type=int, required=True)
     p.add_argument("--n", type=int, required=True)
+    p.add_argument("--rec-bytes", type=int, required=True)
     p.add_argument("--command", required=True)
     p.add_argument("--out-json", required=True)
     p.add_argument("--out-md", required=True)
@@ -119,5 +120,5 @@ if __name__ == "__main__":
     if a.mode == "trace":
         trace(a.stats_csv, a.command, a.out)
     else:
-        print(json.dumps(traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.n, a.command,
-                                 a.out_json, a.out_md)))
+        print(json.dumps(traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.n, a.rec_bytes,
+                                 a.command, a.out_json, a.out_md)))

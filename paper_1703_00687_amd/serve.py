@@ -50,6 +50,7 @@ class Request:
     t_done: float = 0.0
     tmp: Any = None
     cancelled: bool = False
+    ready: Any = None             # backend token: the input has been written
 
 
 @dataclass
@@ -142,8 +143,17 @@ class GpuBackend:
                         for _ in range(n_streams)]
         self.graphs = [None] * n_streams
         self.use_graphs = use_graphs
+        self.capacity_bytes = max_records * rec_bytes  # scratch the arena holds for requests
         if use_graphs:
             self._capture()
+
+    def producer_event(self, recs) -> Any:
+        """An event on the submitting thread's current stream: the sort of
+        `recs` waits for it, so work that stream queued to write the input
+        (not yet finished at submission) comes first."""
+        ev = self.torch.cuda.Event()
+        ev.record(self.torch.cuda.current_stream(recs.device))
+        return ev
 
     def _capture(self):
         torch = self.torch
@@ -187,6 +197,12 @@ class GpuBackend:
             h[i, 2] = r.n
         ev = torch.cuda.Event()
         with torch.cuda.stream(s):
+            for r in reqs:
+                if r.ready is not None:
+                    s.wait_event(r.ready)  # the producer's writes of the input come first
+                # the caching allocator must not hand the input's memory to
+                # another stream's work before this sort is done with it
+                r.recs.record_stream(s)
             bt.desc.copy_(hd, non_blocking=True)
             if self.graphs[stream_idx] is not None:
                 self.graphs[stream_idx].replay()
@@ -220,6 +236,13 @@ class Server:
                  max_batch: int | None = None, poll_s: float = 2e-5):
         self.backend = backend
         self.rec_bytes = rec_bytes
+        cap = getattr(backend, "capacity_bytes", None)
+        if cap is not None and budget_bytes > cap:
+            # an admitted batch could then never get its scratch from the
+            # backend and would be retried for ever
+            raise ValueError(f"budget {budget_bytes} B exceeds the backend's scratch {cap} B")
+        if max_batch is not None and max_batch > backend.max_batch:
+            raise ValueError(f"max_batch {max_batch} exceeds the backend's {backend.max_batch}")
         self.budget = budget_bytes
         self.free = budget_bytes
         self.max_slots = max_slots
@@ -252,6 +275,9 @@ class Server:
                 return req.future
             if self.stats.t_first == 0.0:
                 self.stats.t_first = req.t_arrival
+            mark = getattr(self.backend, "producer_event", None)
+            if mark is not None:
+                req.ready = mark(recs)
             self.pending.append(req)
             self.lock.notify_all()
         return req.future

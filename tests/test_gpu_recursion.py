@@ -1,0 +1,99 @@
+"""GPU: the recursion's bins after round l, pinned against the oracle.
+
+After each radix phase the array is split into bins that are processed
+independently (Sec. 1); bins still larger than the LDS capacity get another
+global pass (Sec. 3.1-3.2).  raduls_inspect_rounds runs only the first l
+global rounds and returns the large bins they left.  Each one must be a
+maximal run of the oracle's sorted output whose keys agree on every bit from
+the bin's `bits` up, larger than mid_max, and its records (on the side the
+entry names) must be exactly those of that run in input order (every pass is
+a stable partition; the payload holds the input index).  With uniform keys
+and a fixed digit width no digit is skipped, so the list must also be exactly
+the oracle's bins at level l (oracle.bins_at_level) that exceed mid_max."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import tuned
+from paper_1703_00687_amd import binding as b
+from paper_1703_00687_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def masked_keys(recs: np.ndarray, key_bytes: int, bits: int) -> np.ndarray:
+    """The key bytes with key bits [0, bits) cleared."""
+    k = np.ascontiguousarray(recs[:, :key_bytes]).copy()
+    full = bits // 8
+    k[:, :min(full, key_bytes)] = 0
+    if bits % 8 and full < key_bytes:
+        k[:, full] &= np.uint8(0xFF ^ ((1 << (bits % 8)) - 1))
+    return k
+
+
+def check_round(host, key_bytes, idx_word, rounds, exact_level_width=None):
+    n, R = host.shape
+    mid_max = b.raduls_get_tuning()["mid_max"] or b.raduls_mid_capacity(R, key_bytes)
+    mid_max = min(mid_max, b.raduls_mid_capacity(R, key_bytes))
+    recs = torch.from_numpy(host.reshape(-1).copy()).cuda()
+    tmp = torch.empty(b.raduls_tmp_bytes(n, R, key_bytes), dtype=torch.uint8, device="cuda")
+    bins = b.raduls_inspect_rounds(recs, tmp, n, R, key_bytes, rounds)
+    sides = [recs.cpu().numpy().reshape(n, R), tmp[:n * R].cpu().numpy().reshape(n, R)]
+    srt = oracle.sort(host, key_bytes)
+    idx = srt.view("<u8")[:, idx_word]
+    covered = np.zeros(n, dtype=bool)
+    for start, size, bits, side in bins:
+        assert size > mid_max and start + size <= n and side in (0, 1)
+        assert 0 < bits <= 8 * key_bytes
+        assert not covered[start:start + size].any(), "bins overlap"
+        covered[start:start + size] = True
+        mk = masked_keys(srt[max(start - 1, 0):start + size + 1], key_bytes, bits)
+        body = mk[(1 if start > 0 else 0):][:size]
+        assert (body == body[0]).all(), "a bin's records differ above its bits"
+        if start > 0:
+            assert not np.array_equal(mk[0], body[0]), "bin is not maximal (left)"
+        if start + size < n:
+            assert not np.array_equal(mk[-1], body[0]), "bin is not maximal (right)"
+        expect = srt[start:start + size][np.argsort(idx[start:start + size], kind="stable")]
+        assert np.array_equal(sides[side][start:start + size], expect), \
+            "a bin's records are not the stable partition"
+    if exact_level_width is not None:
+        starts, sizes = oracle.bins_at_level(srt, key_bytes, exact_level_width, rounds)
+        want = sorted((int(s), int(z)) for s, z in zip(starts, sizes) if z > mid_max)
+        got = sorted((s, z) for s, z, _, _ in bins)
+        assert got == want
+        assert all(bt == 8 * key_bytes - exact_level_width * rounds for _, _, bt, _ in bins)
+    return bins
+
+
+@pytest.mark.parametrize("rounds", [1, 2, 3])
+def test_bins_uniform_four_bit_digits(rounds):
+    host = wl.uniform16(1 << 20, seed=41)
+    with tuned(digit_bits=4, mid_max=64):
+        bins = check_round(host, 8, 1, rounds, exact_level_width=4)
+    assert len(bins) == 16 ** rounds
+
+
+@pytest.mark.parametrize("rounds", [1, 2, 3])
+def test_bins_skewed_keys(rounds):
+    host = wl.zipf16(1 << 20, seed=42, values=1 << 12)
+    check_round(host, 8, 1, rounds)
+
+
+@pytest.mark.parametrize("rounds", [1, 2])
+def test_bins_deep_keys_skip_constant_digits(rounds):
+    host = wl.deep32(1 << 20, seed=43)
+    bins = check_round(host, 16, 2, rounds)
+    if rounds == 1:
+        # the top 44 key bits are zero for every record: the first round's
+        # children already lie below them
+        assert bins and all(bt <= 84 for _, _, bt, _ in bins)
+
+
+def test_bins_small_input_runs_no_round():
+    host = wl.uniform16(1000, seed=44)
+    recs = torch.from_numpy(host.reshape(-1).copy()).cuda()
+    tmp = torch.empty(b.raduls_tmp_bytes(1000, 16, 8), dtype=torch.uint8, device="cuda")
+    assert b.raduls_inspect_rounds(recs, tmp, 1000, 16, 8, 1) == []

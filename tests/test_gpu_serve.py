@@ -65,3 +65,35 @@ def test_results_identical_alone_and_in_the_mix(use_graphs):
         assert np.array_equal(o.cpu().numpy(), a)
     assert summary["requests"] == len(hosts) and summary["failed"] == 0
     assert summary["batches"] >= 2
+
+
+def test_submit_orders_after_the_producing_stream():
+    # inputs written on a side stream and submitted at once, with no global
+    # synchronize: each sort must wait for its input's writes
+    hosts = _requests(40, seed=31, max_log2=18)
+    budget = 64 << 20
+    be = serve.GpuBackend(16, 8, n_streams=3, max_batch=16, max_records=budget // 16,
+                          use_graphs=True)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=budget, max_slots=32).start()
+    srcs = [torch.from_numpy(h.copy()).cuda() for h in hosts]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    futs, outs = [], []
+    with torch.cuda.stream(side):
+        for s in srcs:
+            d = torch.empty_like(s)
+            torch.cuda._sleep(200_000)  # keeps the side stream busy past submission
+            d.copy_(s)
+            outs.append(d)
+            futs.append(srv.submit(d))
+    res = [f.result(timeout=60) for f in futs]
+    srv.stop()
+    torch.cuda.synchronize()
+    for r, h in zip(res, hosts):
+        assert np.array_equal(r.cpu().numpy(), oracle.sort(h, 8))
+
+
+def test_budget_larger_than_backend_scratch_is_refused():
+    be = serve.GpuBackend(16, 8, n_streams=1, max_batch=4, max_records=1024, use_graphs=False)
+    with pytest.raises(ValueError):
+        serve.Server(be, rec_bytes=16, budget_bytes=1024 * 16 + 1, max_slots=4)

@@ -41,6 +41,18 @@ def test_sort_equals_python_sorted(r, k):
 
 
 @pytest.mark.parametrize("r,k", SHAPES)
+@pytest.mark.parametrize("threads", [1, 2, 4, 0])
+def test_parallel_sort_equals_python_sorted(r, k, threads):
+    # the CPU-baseline variant (several threads) against Python's own stable
+    # sort; large enough that every thread gets a share of the merge
+    for seed, distinct in ((11, None), (12, 3), (13, 200)):
+        recs = rand_recs(seed * 100 + r + k, 5000, r, k, distinct)
+        out, used = oracle.sort_parallel(recs, k, threads)
+        assert used >= 1 and (threads == 0 or used == threads)
+        assert np.array_equal(out, python_sorted(recs, k))
+
+
+@pytest.mark.parametrize("r,k", SHAPES)
 def test_sort_equals_numpy_lexsort(r, k):
     recs = rand_recs(r * 7 + k, 20000, r, k, distinct=3000)
     order = np.lexsort([recs[:, j] for j in range(k)])  # last column is primary

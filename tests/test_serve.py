@@ -202,3 +202,11 @@ def test_arena_first_fit_and_coalescing():
     a.release(0, 2000)
     a.release(z, 1000)
     assert a.free == [(0, 4096)]
+
+
+def test_budget_above_backend_capacity_is_refused():
+    be = FakeBackend(n_streams=1, max_batch=4)
+    be.capacity_bytes = 1000
+    with pytest.raises(ValueError):
+        serve.Server(be, rec_bytes=16, budget_bytes=1001, max_slots=4)
+    serve.Server(be, rec_bytes=16, budget_bytes=1000, max_slots=4)  # at the capacity: fine
