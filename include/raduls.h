@@ -51,7 +51,8 @@ typedef enum raduls_status {
   RADULS_E_TMP_SMALL = -3,   /* tmp / ws smaller than the size query returned */
   RADULS_E_UNSUPPORTED = -4, /* R not a multiple of 8 in [8, 64], or n >= 2^32 */
   RADULS_E_HIP = -5,         /* a HIP runtime call or kernel launch failed */
-  RADULS_E_DEVICE = -6       /* raduls_check(): the device recorded an error */
+  RADULS_E_DEVICE = -6,      /* raduls_check(): the device recorded an error */
+  RADULS_E_SCRATCH = -7      /* raduls_sort_static: n needs more than the static workspace */
 } raduls_status;
 
 /* Tuning knobs (process-global; set them before enqueuing sorts, never while
@@ -115,6 +116,22 @@ int raduls_tmp_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint64_
  * stably sorted records. */
 int raduls_sort(void *recs, void *tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
                 hipStream_t stream);
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture that must not allocate, tight serving loops, harnesses that forbid
+ * hipMalloc: raduls_sort with its auxiliary workspace (bin lists, histograms,
+ * job queues) in a static device array of 64 MiB that the library holds on
+ * every GPU it runs on until the process ends, instead of the tail of tmp.
+ * tmp needs only n*R bytes.  Allocates and frees nothing.  The top-level
+ * digit-pair counts (tuning pair_hist) are never used here.  Returns
+ * RADULS_E_SCRATCH when the workspace for n records does not fit the array
+ * (with 16-byte records and default tuning about 2^26 records fit).  Every
+ * call on one GPU uses that GPU's one array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other threads)
+ * race and must be serialized by the caller.  raduls_check(tmp, ...) does
+ * not apply to these calls (the counters are not in tmp). */
+int raduls_sort_static(void *recs, void *tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
+                       hipStream_t stream);
 
 /* A bin of the recursion: records [start, start + size) of the array that
  * share every key bit from `bits` up (bits 0 .. bits-1 are still to be

@@ -24,6 +24,7 @@ E_TMP_SMALL = -3
 E_UNSUPPORTED = -4
 E_HIP = -5
 E_DEVICE = -6
+E_SCRATCH = -7
 
 
 class RadulsError(RuntimeError):
@@ -92,6 +93,7 @@ def load() -> ctypes.CDLL:
     sig = {
         "raduls_tmp_bytes": (i32, [u64, u32, u32, u64p]),
         "raduls_sort": (i32, [vp, vp, u64, u32, u32, vp]),
+        "raduls_sort_static": (i32, [vp, vp, u64, u32, u32, vp]),
         "raduls_batch_ws_bytes": (i32, [u32, u64, u32, u32, u64p]),
         "raduls_sort_batch": (i32, [vp, u32, u64, u32, u32, vp, u64, vp]),
         "raduls_step_ws_bytes": (i32, [u64, u32, u32, u64p]),
@@ -119,7 +121,7 @@ def exported_symbols() -> list[str]:
         "raduls_tmp_bytes", "raduls_sort", "raduls_batch_ws_bytes", "raduls_sort_batch",
         "raduls_step_ws_bytes", "raduls_histogram", "raduls_partition", "raduls_check",
         "raduls_set_tuning", "raduls_get_tuning", "raduls_mid_capacity", "raduls_strerror",
-        "raduls_inspect_rounds",
+        "raduls_inspect_rounds", "raduls_sort_static",
         "raduls_set_profile_events",
     ]
 
@@ -169,6 +171,14 @@ def raduls_sort(recs, tmp, n: int, rec_bytes: int, key_bytes: int, stream=None,
     st = load().raduls_sort(_ptr(recs), _ptr(tmp), n, rec_bytes, key_bytes, _stream(stream))
     if raise_on_error:
         _check(st, "raduls_sort")
+    return st
+
+
+def raduls_sort_static(recs, tmp, n: int, rec_bytes: int, key_bytes: int, stream=None,
+                       raise_on_error: bool = True) -> int:
+    st = load().raduls_sort_static(_ptr(recs), _ptr(tmp), n, rec_bytes, key_bytes, _stream(stream))
+    if raise_on_error:
+        _check(st, "raduls_sort_static")
     return st
 
 

@@ -256,6 +256,32 @@ int launch(const Params& P, uint32_t R, uint32_t K, hipStream_t stream) {
 
 uint64_t aux_offset(uint64_t n, uint32_t R) { return align_up(n * R, 256); }
 
+// The auxiliary workspace of raduls_sort_static: a device array of fixed
+// size that every GPU the library runs on holds until the process ends.  In
+// host code its name stands for a host-side shadow, not a device address:
+// kernels get the address hipGetSymbolAddress returns for the current
+// device, taken once per device.
+constexpr uint64_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+int static_scratch(void** out) {
+  static std::mutex mu;
+  static void* ptr[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return RADULS_E_HIP;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return RADULS_E_HIP;
+    }
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return RADULS_OK;
+}
+
 }  // namespace
 }  // namespace raduls
 
@@ -291,6 +317,34 @@ int raduls_sort(void* recs, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t 
   Params P;
   fill_params(P, e, s, static_cast<uint8_t*>(tmp) + aux_offset(n, rec_bytes), rec_bytes,
               key_bytes, kModeSort, 1);
+  P.recs = static_cast<uint8_t*>(recs);
+  P.tmp = static_cast<uint8_t*>(tmp);
+  P.n = n;
+  if (n <= e.mid_max) P.rounds = 0;
+  return launch(P, rec_bytes, key_bytes, stream);
+}
+
+int raduls_sort_static(void* recs, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
+                       hipStream_t stream) {
+  int st = check_shape(rec_bytes, key_bytes);
+  if (st) return st;
+  if (n >= (1ull << 32)) return RADULS_E_UNSUPPORTED;
+  if (n <= 1) return RADULS_OK;
+  if (!recs || !tmp) return RADULS_E_INVALID;
+  if (misaligned(recs) || misaligned(tmp)) return RADULS_E_ALIGN;
+  const Eff e = effective(current_tuning(), rec_bytes, key_bytes);
+  // (the top-level digit-pair counts, a speed option, are not used: their
+  // rows alone would take as much room as the rest of the workspace)
+  const Shape s = plan_shape(n, 1, rec_bytes, key_bytes, e, false, false);
+  if (s.bytes > kStaticScratchBytes) return RADULS_E_SCRATCH;
+  if (overlap(recs, n * rec_bytes, tmp, n * rec_bytes)) return RADULS_E_INVALID;
+  st = check_room(tmp, n * rec_bytes);
+  if (st) return st;
+  void* aux = nullptr;
+  st = static_scratch(&aux);
+  if (st) return st;
+  Params P;
+  fill_params(P, e, s, static_cast<uint8_t*>(aux), rec_bytes, key_bytes, kModeSort, 1);
   P.recs = static_cast<uint8_t*>(recs);
   P.tmp = static_cast<uint8_t*>(tmp);
   P.n = n;
@@ -490,6 +544,7 @@ const char* raduls_strerror(int status) {
     case RADULS_E_UNSUPPORTED: return "unsupported record size or record count";
     case RADULS_E_HIP: return "HIP runtime error";
     case RADULS_E_DEVICE: return "device reported an error";
+    case RADULS_E_SCRATCH: return "the static workspace is too small for this many records";
     default: return "unknown status";
   }
 }

@@ -118,7 +118,8 @@ def test_tuning_roundtrip_and_rejects():
 
 
 def test_strerror():
-    for st in (b.OK, b.E_INVALID, b.E_ALIGN, b.E_TMP_SMALL, b.E_UNSUPPORTED, b.E_HIP, b.E_DEVICE):
+    for st in (b.OK, b.E_INVALID, b.E_ALIGN, b.E_TMP_SMALL, b.E_UNSUPPORTED, b.E_HIP, b.E_DEVICE,
+               b.E_SCRATCH):
         assert b.strerror(st) and b.strerror(st) != "unknown status"
 
 
