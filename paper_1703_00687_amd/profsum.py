@@ -3,6 +3,9 @@
 ``trace``: turns ``*_kernel_stats.csv`` (from ``--kernel-trace --stats
 --output-format csv``) into a short table of per-kernel calls and durations.
 
+``sq``: turns a ``*_counter_collection.csv`` of SQ counters into per-kernel
+instruction counts and per-CU times.
+
 ``traffic``: turns two ``*_counter_collection.csv`` files (``--pmc
 FETCH_SIZE`` and ``--pmc WRITE_SIZE`` runs of the same command) into HBM
 bytes per launch of one kernel.  Each counter is scaled by what it reads for
@@ -42,9 +45,13 @@ def short(name: str) -> str:
 def trace(stats_csv: str, command: str, out: str) -> None:
     rows = list(csv.DictReader(open(stats_csv)))
     lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+             "Every kernel of the library and the runtime's copy kernel; torch's own kernels "
+             "(input generation, restores, the output check) are left out.", "",
              "| kernel | calls | mean us | min us | max us | total us | % |",
              "|---|---|---|---|---|---|---|"]
     for r in rows:
+        if "raduls::" not in r["Name"] and COPY_KERNEL not in r["Name"]:
+            continue
         lines.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['TotalDurationNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
@@ -99,6 +106,35 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, n: int
     return rec
 
 
+def sq(counter_csv: str, command: str, out: str, clock_ghz: float = 2.4, cus: int = 256) -> None:
+    """SQ counters per kernel: the largest launch of each kernel (the ones
+    that do the work), summed over the chip, and the per-CU time the vector
+    ALUs alone need (one wave-level VALU instruction per cycle per CU)."""
+    per: dict = {}
+    for r in csv.DictReader(open(counter_csv)):
+        d = per.setdefault(r["Kernel_Name"], {}).setdefault(r["Dispatch_Id"], {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    lines = ["# SQ counters per kernel", "", f"Command: `{command}`", "",
+             "Values are the largest launch of each kernel, summed over the chip. Per CU: "
+             "wave-level VALU and SALU instructions and LDS bank-conflict cycles divided by "
+             f"{cus} CUs, as time at {clock_ghz} GHz (a CU issues at most one wave-level VALU "
+             "and one SALU instruction per cycle).", "",
+             "| kernel | VALU instr | SALU instr | LDS instr | LDS bank-conflict cycles | "
+             "VALU per CU (ms) | SALU per CU (ms) | bank conflicts per CU (ms) |",
+             "|---|---|---|---|---|---|---|---|"]
+    for k, ds in sorted(per.items()):
+        best = max(ds.values(), key=lambda v: v.get("SQ_INSTS_VALU", 0.0))
+        va, sa = best.get("SQ_INSTS_VALU", 0.0), best.get("SQ_INSTS_SALU", 0.0)
+        la, bc = best.get("SQ_INSTS_LDS", 0.0), best.get("SQ_LDS_BANK_CONFLICT", 0.0)
+        if va < 1e6:
+            continue
+        ms = lambda x: x / cus / (clock_ghz * 1e6)
+        lines.append(f"| {short(k)} | {va:.3g} | {sa:.3g} | {la:.3g} | {bc:.3g} | {ms(va):.2f} | "
+                     f"{ms(sa):.2f} | {ms(bc):.2f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -116,9 +152,15 @@ if __name__ == "__main__":
     p.add_argument("--command", required=True)
     p.add_argument("--out-json", required=True)
     p.add_argument("--out-md", required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("counter_csv")
+    q.add_argument("--command", required=True)
+    q.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.mode == "trace":
         trace(a.stats_csv, a.command, a.out)
+    elif a.mode == "sq":
+        sq(a.counter_csv, a.command, a.out)
     else:
         print(json.dumps(traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.n, a.rec_bytes,
                                  a.command, a.out_json, a.out_md)))
