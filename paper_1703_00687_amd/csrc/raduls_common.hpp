@@ -85,9 +85,15 @@ constexpr int kMidEsItems = 5;
 // one enumeration sort over the whole job; larger ones (even those below
 // tiny_max) take the first pass, whose buckets make the enumeration cheaper.
 constexpr uint32_t kMidDirectEs = 16;
-// Jobs of at most one wave's worth of records go to a separate list and are
-// sorted by single waves in registers (k_tiny), not by a whole workgroup.
-constexpr uint32_t kTinyJob = kWave;
+// Jobs of at most kTinyJob records go to a separate list and are sorted by
+// single waves in registers (k_tiny), not by a whole workgroup: up to 64
+// records with one record per lane, up to 128 or 256 with two or four (four
+// only for keys of at most two words and records of at most four, whose
+// pairs and records still fit the registers).
+constexpr uint32_t kTinyJob = 4 * kWave;
+__host__ __device__ constexpr uint32_t tiny_job_max(int rw, int kw) {
+  return kw <= 2 && rw <= 4 ? 4u * kWave : 2u * kWave;
+}
 
 // Most workgroups of the histogram / carry-scan scatter grid.
 constexpr uint32_t kMaxRanges = 4096;
@@ -203,6 +209,7 @@ struct Params {
   uint32_t R, K;
   uint64_t kmask;         // mask of the key bytes in the top key word
   uint32_t digit_bits;    // 1..8
+  uint32_t tiny_job;      // largest job of the wave-level sorter (tiny_job_max)
   uint32_t tiny_max;
   uint32_t mid_max;       // <= LDS capacity
   uint32_t tile;          // records per scatter tile

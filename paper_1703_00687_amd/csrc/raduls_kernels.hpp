@@ -303,7 +303,7 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t* counter, bool want) {
 // Append a sort job for bin b of array a: to the tiny-job list if one wave
 // can hold it, else to the LDS-sort list.
 __device__ __forceinline__ void push_mid(const Params& P, const Bin& b, const ArrayDesc& a) {
-  const bool tiny = b.size <= kTinyJob;
+  const bool tiny = b.size <= P.tiny_job;
   const uint32_t it = wave_reserve(&P.L.ctrl->tiny_count, tiny);
   const uint32_t im = wave_reserve(&P.L.ctrl->mid_count, !tiny);
   const uint32_t i = tiny ? it : im;
@@ -1365,7 +1365,7 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
     // waits on no memory; with branches it took ~0.2 us per digit).  Thread
     // 0 writes the job being built to entry nj of the job table; nj advances
     // when a job is complete, so the entry is rewritten until then.  Then one reservation in each job
-    // list (jobs of at most kTinyJob records go to the tiny-job list) and a
+    // list (jobs of at most tiny_job records go to the tiny-job list) and a
     // parallel write of the descriptors.
     {
       const uint32_t lane = tid & (kWave - 1);
@@ -1390,7 +1390,7 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
         const uint32_t small = (cd != 0 ? 1u : 0u) & (big ^ 1u);
         const uint32_t cut = big | (small & (jn + cd > M ? 1u : 0u));  // the job ends before this child
         const uint32_t done = cut & (jn > 0 ? 1u : 0u) & ((jn > 1 ? 1u : 0u) | lone_moves);
-        const uint32_t tj = jn <= kTinyJob ? 1u : 0u;
+        const uint32_t tj = jn <= P.tiny_job ? 1u : 0u;
         if (tid == 0) {  // (one lane: many lanes writing one LDS word serialize)
           s_js[nj] = js;
           s_jn[nj] = jn;
@@ -2593,15 +2593,125 @@ __device__ __forceinline__ void tiny_pass(const Params& P, uint32_t first, uint3
   if (idx < m) store_rec<RW>(job.dst, idx, out, false);
 }
 
+// One wave sorts one job of 65..64E records with Batcher's bitonic network
+// over its (key, slot) pairs, E pairs per lane: lane l holds positions
+// l * E .. l * E + E - 1, so compare-exchanges at distances below E stay
+// inside a lane and longer ones exchange with lane l ^ (j / E).  Positions
+// past the job hold pairs above any real one.  The sorted slots go to the
+// wave's permutation in LDS; then lane l writes positions e * 64 + l
+// (coalesced), each record read from the job's source by its slot (the key
+// loads brought those lines into the cache); all of them are read before
+// the first is written, since the source may be the destination.
+template <int RW, int KW, int E>
+__device__ __forceinline__ void tiny_pass_wide(const Params& P, uint32_t jid, uint32_t lane,
+                                               uint16_t* perm) {
+  constexpr uint32_t N = uint32_t(kWave) * E;
+  const MidJob job = P.L.tiny[jid];
+  const uint32_t m = min(job.size, N);
+  const RADULS_GLOBAL uint64_t* src = gmem(reinterpret_cast<const uint64_t*>(job.src));
+  uint64_t key[E][KW];
+  uint32_t slot[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t p = lane * E + uint32_t(e);
+    slot[e] = p;
+    const uint32_t pl = p < m ? p : 0u;  // (every lane loads; padding is replaced below)
+#pragma unroll
+    for (int q = 0; q < KW; ++q) key[e][q] = src[uint64_t(pl) * RW + q];
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const bool pad = lane * E + uint32_t(e) >= m;
+    key[e][KW - 1] &= P.kmask;
+#pragma unroll
+    for (int q = 0; q < KW; ++q) key[e][q] = pad ? ~0ull : key[e][q];
+  }
+  // (stage and step loops stay loops: unrolled, the network of every key
+  // width made the code too large to compile in reasonable time)
+#pragma unroll 1
+  for (uint32_t k = 2; k <= N; k <<= 1) {
+#pragma unroll 1
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j >= uint32_t(E)) {
+        const int partner = int(lane ^ (j / E));
+        const bool lower = (lane & (j / E)) == 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          uint64_t ok[KW];
+#pragma unroll
+          for (int q = 0; q < KW; ++q) ok[q] = shfl64(key[e][q], partner);
+          const uint32_t os = uint32_t(__shfl(int(slot[e]), partner));
+          const bool other_less = key_lt<KW>(ok, key[e]) || (key_eq<KW>(ok, key[e]) && os < slot[e]);
+          const bool up = ((lane * E + uint32_t(e)) & k) == 0;
+          const bool take = (lower == up) ? other_less : !other_less;
+#pragma unroll
+          for (int q = 0; q < KW; ++q) key[e][q] = take ? ok[q] : key[e][q];
+          slot[e] = take ? os : slot[e];
+        }
+      } else {
+        // inside a lane: distance 1, or 2 when E = 4
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+#pragma unroll
+          for (int jj = 1; jj < E; jj <<= 1) {
+            if (uint32_t(jj) != j || (e & jj) != 0) continue;
+            const int f = e + jj;
+            const bool up = ((lane * E + uint32_t(e)) & k) == 0;
+            const bool f_less =
+                key_lt<KW>(key[f], key[e]) || (key_eq<KW>(key[f], key[e]) && slot[f] < slot[e]);
+            const bool swap = up ? f_less : !f_less;  // (pairs are distinct)
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+              const uint64_t x = key[e][q], y = key[f][q];
+              key[e][q] = swap ? y : x;
+              key[f][q] = swap ? x : y;
+            }
+            const uint32_t sx = slot[e], sy = slot[f];
+            slot[e] = swap ? sy : sx;
+            slot[f] = swap ? sx : sy;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) perm[lane * E + uint32_t(e)] = uint16_t(slot[e]);
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+  // every record of the job is read before any is written: source and
+  // destination are the same buffer when the job sits in its output already
+  uint64_t rec[E][RW];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t q = uint32_t(e) * kWave + lane;
+    load_rec<RW>(job.src, perm[q < m ? q : 0u], rec[e]);
+  }
+  __builtin_amdgcn_s_waitcnt(0x3F70);  // gfx9 encoding: vmcnt(0)
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t q = uint32_t(e) * kWave + lane;
+    if (q < m) store_rec<RW>(job.dst, q, rec[e], false);
+  }
+  // (the next job rewrites perm only after every lane has read it)
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Jobs come in groups of four per wave: four jobs of at most 16 records
 // share one pass (16 lanes each), jobs of at most 32 go two per pass, larger
-// ones one per pass (several bins per wave when they are small).
+// ones one per pass (several bins per wave when they are small), those of
+// more than 64 records with two or four records per lane.
 template <int RW, int KW>
 __global__ void __launch_bounds__(kMidBlock) k_tiny(Params P) {
+  __shared__ uint16_t s_perm[kMidWaves][kTinyJob];
   const Ctrl* c = P.L.ctrl;
   const uint32_t n = min(c->tiny_count, P.L.cap_mid);
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t waves = gridDim.x * uint32_t(kMidWaves);
+  uint16_t* perm = s_perm[threadIdx.x >> 6];
   constexpr uint32_t G = 4;
   for (uint32_t g = blockIdx.x * uint32_t(kMidWaves) + (threadIdx.x >> 6); g < (n + G - 1) / G;
        g += waves) {
@@ -2618,7 +2728,16 @@ __global__ void __launch_bounds__(kMidBlock) k_tiny(Params P) {
       tiny_pass<RW, KW, 32>(P, first + 2, n, lane);
     } else {
 #pragma unroll 1
-      for (uint32_t u = 0; u < G; ++u) tiny_pass<RW, KW, kWave>(P, first + u, n, lane);
+      for (uint32_t u = 0; u < G && first + u < n; ++u) {
+        const uint32_t sz = __builtin_amdgcn_readfirstlane(P.L.tiny[first + u].size);
+        if (sz <= uint32_t(kWave)) {
+          tiny_pass<RW, KW, kWave>(P, first + u, n, lane);
+        } else if (sz <= 2u * kWave) {
+          tiny_pass_wide<RW, KW, 2>(P, first + u, lane, perm);
+        } else if constexpr (KW <= 2 && RW <= 4) {
+          tiny_pass_wide<RW, KW, 4>(P, first + u, lane, perm);
+        }
+      }
     }
   }
 }

@@ -211,6 +211,7 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
   const uint32_t top = K - 8 * ((K - 1) / 8);  // key bytes in the top word, 1..8
   P.kmask = top == 8 ? ~0ull : ((1ull << (8 * top)) - 1);
   P.digit_bits = e.digit_bits;
+  P.tiny_job = tiny_job_max(int(R / 8), int((K + 7) / 8));
   P.tiny_max = e.tiny_max;
   P.mid_max = e.mid_max;
   P.tile = e.tile;
