@@ -478,65 +478,83 @@ def bench_batch(args) -> dict:
     return out
 
 
-TINY_SIZES = [2, 3, 4, 8, 16, 32, 64, 128, 256, 1024, 4096]
+TINY_SIZES = [2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 1024, 4096]
+# The small-array sorters compared per record layout (the GPU counterpart of
+# the paper's comparison of tiny-bin sorters by record layout, Sec. 4.1):
+# the wave-level bitonic network, one enumeration sort over the whole array
+# in LDS, and the LDS sorter's counting pass followed by enumeration sort of
+# its buckets.
+TINY_METHODS = {"network": {},
+                "es": {"wave_job_max": 1, "es_job_max": 256, "tiny_max": 256},
+                "hybrid": {"wave_job_max": 1}}
+TINY_LAYOUTS = [(8, 8), (16, 8), (32, 16), (16, 16)]
 
 
-def tiny_sweep(total_log2: int, verify: bool) -> list:
-    """Many arrays of n 16-byte records each (uint64 key uniform, payload =
-    global index), 2^total_log2 records in all, sorted by one batched call:
-    every array is one LDS-sorter job, so this times the tiny-bin sorters
-    (enumeration sort up to tiny_max records, LDS passes above) per record."""
+def tiny_sweep(total_log2: int, verify: bool, methods=None, layouts=None, sizes=None) -> list:
+    """Many arrays of n records each (key words uniform, then the array's
+    record index where there is room, then random words), 2^total_log2
+    records in all, sorted by one batched call: every array is one sort job,
+    so this times the small-array sorters per record, for each method and
+    record layout."""
     import numpy as np
     import torch
     import oracle
     from paper_1703_00687_amd import binding as b
     from paper_1703_00687_amd import workloads as wl
-    R, K = 16, 8
     dev = torch.device("cuda:0")
     out = []
-    for n in TINY_SIZES:
-        count = (1 << total_log2) // n
-        total = count * n
-        src = wl.uniform16_torch(total, seed=8, device=dev)
-        recs = torch.empty_like(src)
-        tmp = torch.empty_like(src)
-        bt = b.Batch(count, total, R, K, device=dev)
-        h = bt.host_desc.numpy()
-        starts = np.arange(count, dtype=np.int64) * n
-        h[:, 0] = recs.data_ptr() + starts * R
-        h[:, 1] = tmp.data_ptr() + starts * R
-        h[:, 2] = n
-        bt.desc.copy_(bt.host_desc)
-        times = []
-        for rep in range(4):
-            recs.copy_(src)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            bt.launch()
-            e1.record()
-            torch.cuda.synchronize()
-            if rep:
-                times.append(e0.elapsed_time(e1))
-        st, stats = bt.check()
-        if st != b.OK:
-            raise RuntimeError(f"tiny sweep n={n}: device error {stats}")
-        ms = sorted(times)[len(times) // 2]
-        ok = None
-        if verify:
-            rng = np.random.default_rng(n)
-            ok = True
-            for j in rng.choice(count, size=min(32, count), replace=False):
-                a = int(j) * n
-                if not np.array_equal(recs[a:a + n].cpu().numpy(), oracle.sort(src[a:a + n].cpu().numpy(), K)):
-                    ok = False
-            if not ok:
-                raise RuntimeError(f"tiny sweep n={n}: an array differs from the oracle")
-        out.append({"n": n, "arrays": count, "ms": round(ms, 3),
-                    "ns_per_record": round(ms * 1e6 / total, 3), "mid_jobs": stats["mid_jobs"],
-                    "verified": ok})
-        log(f"[tiny] {out[-1]}")
-        del src, recs, tmp, bt
-        torch.cuda.empty_cache()
+    for R, K in (layouts or TINY_LAYOUTS):
+        for method, knobs in (methods or TINY_METHODS).items():
+            for n in (sizes or TINY_SIZES):
+                if method != "network" and n > 256:
+                    continue
+                count = (1 << total_log2) // n
+                total = count * n
+                src = wl.sweep_records_torch(total, R, K, device=dev)
+                recs = torch.empty_like(src)
+                tmp = torch.empty_like(src)
+                prev = b.raduls_set_tuning(**knobs)
+                try:
+                    bt = b.Batch(count, total, R, K, device=dev)
+                    h = bt.host_desc.numpy()
+                    starts = np.arange(count, dtype=np.int64) * n
+                    h[:, 0] = recs.data_ptr() + starts * R
+                    h[:, 1] = tmp.data_ptr() + starts * R
+                    h[:, 2] = n
+                    bt.desc.copy_(bt.host_desc)
+                    times = []
+                    for rep in range(4):
+                        recs.copy_(src)
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record()
+                        bt.launch()
+                        e1.record()
+                        torch.cuda.synchronize()
+                        if rep:
+                            times.append(e0.elapsed_time(e1))
+                    st, stats = bt.check()
+                finally:
+                    b.raduls_set_tuning(**prev)
+                if st != b.OK:
+                    raise RuntimeError(f"tiny sweep {method} R={R} n={n}: device error {stats}")
+                ms = sorted(times)[len(times) // 2]
+                ok = None
+                if verify:
+                    rng = np.random.default_rng(n)
+                    ok = True
+                    for j in rng.choice(count, size=min(16, count), replace=False):
+                        a = int(j) * n
+                        if not np.array_equal(recs[a:a + n].cpu().numpy(),
+                                              oracle.sort(src[a:a + n].cpu().numpy(), K)):
+                            ok = False
+                    if not ok:
+                        raise RuntimeError(f"tiny sweep {method} R={R} n={n}: an array differs from the oracle")
+                out.append({"rec_bytes": R, "key_bytes": K, "method": method, "n": n, "arrays": count,
+                            "ms": round(ms, 3), "ns_per_record": round(ms * 1e6 / total, 4),
+                            "verified": ok})
+                log(f"[tiny] {out[-1]}")
+                del src, recs, tmp, bt
+                torch.cuda.empty_cache()
     return out
 
 
@@ -582,8 +600,9 @@ def main() -> int:
                     help="also sort records of 8-64 B with 8/16 B keys (2^--sweep-log2 each)")
     ap.add_argument("--sweep-log2", type=int, default=28)
     ap.add_argument("--tiny-sweep", action="store_true",
-                    help="also sort many arrays of 2..4096 records (2^--tiny-log2 records per size)")
-    ap.add_argument("--tiny-log2", type=int, default=24)
+                    help="also sort many arrays of 2..4096 records (2^--tiny-log2 records per size), "
+                         "by every small-array method and record layout")
+    ap.add_argument("--tiny-log2", type=int, default=22)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -80,7 +80,15 @@ typedef struct raduls_tuning {
                             its histograms from those counts instead of reading its bins
                             again (its scatter then gives each bin one workgroup); 2: never.
                             Costs 128 KiB of tmp per histogram workgroup (at most 64 MiB) */
-  uint32_t reserved[9];
+  uint32_t wave_job_max; /* sort jobs (tiny bins, tiny arrays) of at most this many records are
+                            sorted by one wave with a bitonic network (Sec. 3.3), larger ones by
+                            a workgroup in LDS; 1 turns the wave sorter off; default and upper
+                            bound 256 (128 for keys of more than 16 bytes or records of more
+                            than 32) */
+  uint32_t es_job_max;   /* LDS sort jobs of at most this many records skip the counting pass and
+                            are finished by one enumeration sort (Sec. 2.2); 1..tiny_max
+                            (default 16) */
+  uint32_t reserved[7];
 } raduls_tuning;
 
 /* Device-side counters left in the workspace by the last sort that used it. */

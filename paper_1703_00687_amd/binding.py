@@ -42,7 +42,9 @@ class raduls_tuning(ctypes.Structure):
         ("nontemporal", ctypes.c_uint32),
         ("lookback", ctypes.c_uint32),
         ("pair_hist", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 9),
+        ("wave_job_max", ctypes.c_uint32),
+        ("es_job_max", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 7),
     ]
 
 
@@ -74,7 +76,7 @@ class raduls_array(ctypes.Structure):
 
 
 TUNING_FIELDS = ("digit_bits", "tiny_max", "mid_max", "grid_blocks", "nontemporal", "lookback",
-                 "pair_hist")
+                 "pair_hist", "wave_job_max", "es_job_max")
 
 _lib = None
 

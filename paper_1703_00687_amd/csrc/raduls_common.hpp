@@ -81,9 +81,10 @@ constexpr uint32_t kMidBigCap = 64;     // ranges waiting for a workgroup pass
 // Positions per lane of the enumeration phase: a range of at most 256 records
 // starting in a 64-position window ends within 5 windows.
 constexpr int kMidEsItems = 5;
-// Jobs of at most this many records skip the first pass and are finished by
-// one enumeration sort over the whole job; larger ones (even those below
-// tiny_max) take the first pass, whose buckets make the enumeration cheaper.
+// Jobs of at most this many records (by default; tuning es_job_max) skip the
+// first pass and are finished by one enumeration sort over the whole job;
+// larger ones (even those below tiny_max) take the first pass, whose buckets
+// make the enumeration cheaper.
 constexpr uint32_t kMidDirectEs = 16;
 // Jobs of at most kTinyJob records go to a separate list and are sorted by
 // single waves in registers (k_tiny), not by a whole workgroup: up to 64
@@ -209,7 +210,8 @@ struct Params {
   uint32_t R, K;
   uint64_t kmask;         // mask of the key bytes in the top key word
   uint32_t digit_bits;    // 1..8
-  uint32_t tiny_job;      // largest job of the wave-level sorter (tiny_job_max)
+  uint32_t tiny_job;      // largest job of the wave-level sorter (<= tiny_job_max; 0: none)
+  uint32_t es_job;        // LDS jobs of at most this many records: one enumeration sort
   uint32_t tiny_max;
   uint32_t mid_max;       // <= LDS capacity
   uint32_t tile;          // records per scatter tile

@@ -2228,7 +2228,7 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
     }
     bool windows = false;  // tiny ranges left for the window enumeration sort
     bool later = false;    // ranges left for later passes
-    if (m > min(tiny, kMidDirectEs) && hb > 0) {
+    if (m > min(tiny, P.es_job) && hb > 0) {
       // first pass over the whole job, on digits from the kept keys: about
       // two buckets per record (2^w >= 2m), so that most buckets hold one
       // record or none

@@ -39,6 +39,7 @@ uint32_t mid_capacity(uint32_t rw, uint32_t kw) { return mid_cap(int(rw), int(kw
 
 struct Eff {  // tuning after defaults and clamps, for one record width
   uint32_t digit_bits, tiny_max, mid_max, tile, nontemporal, grid_blocks, lookback, pair_hist;
+  uint32_t wave_job, es_job;
 };
 
 Eff effective(const raduls_tuning& t, uint32_t R, uint32_t K) {
@@ -57,6 +58,10 @@ Eff effective(const raduls_tuning& t, uint32_t R, uint32_t K) {
   e.grid_blocks = t.grid_blocks;
   e.lookback = t.lookback ? 1 : 0;
   e.pair_hist = t.pair_hist == 2 ? 0 : 1;
+  const uint32_t wmax = tiny_job_max(int(rw), int((K + 7) / 8));
+  e.wave_job = t.wave_job_max ? std::min(t.wave_job_max, wmax) : wmax;
+  if (e.wave_job == 1) e.wave_job = 0;  // off: every job goes to the LDS sorter
+  e.es_job = std::min(t.es_job_max ? t.es_job_max : kMidDirectEs, e.tiny_max);
   return e;
 }
 
@@ -211,7 +216,8 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
   const uint32_t top = K - 8 * ((K - 1) / 8);  // key bytes in the top word, 1..8
   P.kmask = top == 8 ? ~0ull : ((1ull << (8 * top)) - 1);
   P.digit_bits = e.digit_bits;
-  P.tiny_job = tiny_job_max(int(R / 8), int((K + 7) / 8));
+  P.tiny_job = e.wave_job;
+  P.es_job = e.es_job;
   P.tiny_max = e.tiny_max;
   P.mid_max = e.mid_max;
   P.tile = e.tile;
@@ -509,7 +515,8 @@ int raduls_check(const void* tmp_or_ws, uint64_t n, uint32_t rec_bytes, int ws_o
 
 int raduls_set_tuning(const raduls_tuning* tuning) {
   if (!tuning) return RADULS_E_INVALID;
-  if (tuning->digit_bits > 8 || tuning->tiny_max > 256 || tuning->nontemporal > 2)
+  if (tuning->digit_bits > 8 || tuning->tiny_max > 256 || tuning->nontemporal > 2 ||
+      tuning->wave_job_max > kTinyJob || tuning->es_job_max > 256)
     return RADULS_E_INVALID;
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   g_tuning = *tuning;

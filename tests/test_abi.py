@@ -137,8 +137,9 @@ def test_struct_layouts_match_the_header(tmp_path):
     src.write_text(
         "#include <stdio.h>\n#include <stddef.h>\n#include \"raduls.h\"\n"
         "int main(void) {\n"
-        "  printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(raduls_tuning),\n"
+        "  printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(raduls_tuning),\n"
         "         offsetof(raduls_tuning, lookback), offsetof(raduls_tuning, pair_hist),\n"
+        "         offsetof(raduls_tuning, wave_job_max), offsetof(raduls_tuning, es_job_max),\n"
         "         sizeof(raduls_stats), offsetof(raduls_stats, moved_records),\n"
         "         offsetof(raduls_stats, pair_rounds), sizeof(raduls_array),\n"
         "         sizeof(raduls_bin), offsetof(raduls_bin, side));\n"
@@ -150,7 +151,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
                                           text=True).stdout.split()]
     want = [ctypes.sizeof(b.raduls_tuning), b.raduls_tuning.lookback.offset,
-            b.raduls_tuning.pair_hist.offset, ctypes.sizeof(b.raduls_stats),
+            b.raduls_tuning.pair_hist.offset, b.raduls_tuning.wave_job_max.offset,
+            b.raduls_tuning.es_job_max.offset, ctypes.sizeof(b.raduls_stats),
             b.raduls_stats.moved_records.offset, b.raduls_stats.pair_rounds.offset,
             ctypes.sizeof(b.raduls_array), ctypes.sizeof(b.raduls_bin), b.raduls_bin.side.offset]
     assert got == want

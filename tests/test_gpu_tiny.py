@@ -142,3 +142,22 @@ def test_tiny_and_lds_jobs_in_one_batch():
     out, starts = _batch_sort(np.concatenate(arrays), sizes, 16, 8)
     for a, s in zip(arrays, starts):
         assert np.array_equal(out[s:s + a.shape[0]], oracle.sort(a, 8))
+
+
+@pytest.mark.parametrize("knobs", [{"wave_job_max": 1}, {"wave_job_max": 1, "es_job_max": 256, "tiny_max": 256},
+                                   {"wave_job_max": 100, "es_job_max": 40}, {"wave_job_max": 64}])
+@pytest.mark.parametrize("r,k", [(16, 8), (32, 16), (8, 5)])
+def test_small_array_methods_against_the_oracle(knobs, r, k):
+    """The same arrays of 1..300 records through each small-array method the
+    tuning can select (wave network off or capped, one enumeration sort over
+    whole jobs of up to 256 records)."""
+    from gpu_helpers import tuned
+    rng = np.random.default_rng(r + k)
+    arrays = [wl.random_records(rng, n, r, k, distinct_keys=d)
+              for n in list(range(1, 70)) + [100, 127, 128, 129, 200, 255, 256, 257, 300]
+              for d in (None, 3)]
+    sizes = np.array([a.shape[0] for a in arrays], dtype=np.int64)
+    with tuned(**knobs):
+        out, starts = _batch_sort(np.concatenate(arrays), sizes, r, k)
+    for a, s in zip(arrays, starts):
+        assert np.array_equal(out[s:s + a.shape[0]], oracle.sort(a, k))
