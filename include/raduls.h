@@ -109,7 +109,8 @@ typedef struct raduls_stats {
   uint64_t large_records;  /* records in large bins, summed over rounds */
   uint32_t pair_rounds;    /* 1 if the second round took its histograms from the
                               top-level digit pair counts (tuning pair_hist) */
-  uint32_t reserved;
+  uint32_t eq_bins;        /* large bins that one key dominated, split three ways on it
+                              (keys below, equal to, above it) instead of on a digit */
 } raduls_stats;
 
 /* Bytes of `tmp` that raduls_sort needs for n records: n*R for the scatter
@@ -144,12 +145,16 @@ int raduls_sort_static(void *recs, void *tmp, uint64_t n, uint32_t rec_bytes, ui
 /* A bin of the recursion: records [start, start + size) of the array that
  * share every key bit from `bits` up (bits 0 .. bits-1 are still to be
  * sorted); they sit in recs (side 0) or in the ping-pong half of tmp (side 1)
- * at the same offsets. */
+ * at the same offsets.  flags bit 0: the next round splits the bin on one key
+ * that dominates it (keys below, equal to, above it); bit 1: the bin is one
+ * side of such a split, a key range inside a run of records sharing the bits
+ * from `bits` up rather than the whole run. */
 typedef struct raduls_bin {
   uint32_t start;
   uint32_t size;
   uint32_t bits;
   uint32_t side;
+  uint32_t flags;
 } raduls_bin;
 
 /* Recursion inspection (Sec. 1: after each radix phase the array is split

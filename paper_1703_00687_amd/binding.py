@@ -59,7 +59,7 @@ class raduls_stats(ctypes.Structure):
         ("moved_records", ctypes.c_uint64),
         ("large_records", ctypes.c_uint64),
         ("pair_rounds", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("eq_bins", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -68,7 +68,7 @@ class raduls_stats(ctypes.Structure):
 
 class raduls_bin(ctypes.Structure):
     _fields_ = [("start", ctypes.c_uint32), ("size", ctypes.c_uint32), ("bits", ctypes.c_uint32),
-                ("side", ctypes.c_uint32)]
+                ("side", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class raduls_array(ctypes.Structure):
@@ -265,14 +265,14 @@ def raduls_mid_capacity(rec_bytes: int, key_bytes: int) -> int:
 def raduls_inspect_rounds(recs, tmp, n: int, rec_bytes: int, key_bytes: int, rounds: int,
                           cap: int = 1 << 20, stream=None) -> list[tuple[int, int, int, int]]:
     """Run the first `rounds` global rounds only and return the large bins
-    they left, as (start, size, bits, side) tuples (synchronizes)."""
+    they left, as (start, size, bits, side, flags) tuples (synchronizes)."""
     arr = (raduls_bin * max(cap, 1))()
     cnt = ctypes.c_uint32(0)
     _check(load().raduls_inspect_rounds(_ptr(recs), _ptr(tmp), n, rec_bytes, key_bytes, rounds, arr,
                                         cap, ctypes.byref(cnt), _stream(stream)),
            "raduls_inspect_rounds")
     k = min(int(cnt.value), cap)
-    return [(arr[i].start, arr[i].size, arr[i].bits, arr[i].side) for i in range(k)]
+    return [(arr[i].start, arr[i].size, arr[i].bits, arr[i].side, arr[i].flags) for i in range(k)]
 
 
 def raduls_strerror(status: int) -> str:

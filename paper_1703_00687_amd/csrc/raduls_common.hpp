@@ -138,6 +138,17 @@ struct ArrayDesc {  // same layout as raduls_array
   uint64_t n;
 };
 
+// Bin flags.  kBinEq: the next round splits the bin three ways on its
+// equality key (keys below it, equal to it, above it) instead of on a digit.
+// kBinRange: the bin is one side of such a split, a key range inside a run of
+// records that share all key bits above `bits`, not the whole run.
+constexpr uint8_t kBinEq = 1;
+constexpr uint8_t kBinRange = 2;
+// Extra rounds that a sort of many records allows for equality splits (a
+// split consumes a round but no key bit), and the samples that decide one.
+constexpr uint32_t kEqRounds = 2;
+constexpr uint32_t kEqSamples = 16, kEqDominant = 12;
+
 // A bin (a contiguous run of records that share all key bits above `bits`)
 // or an LDS sort job / copy job over such runs.  16 bytes.
 struct Bin {
@@ -175,6 +186,7 @@ struct Ctrl {
   uint32_t fused;      // 1: this round's histograms came from the top-level pair counts
   uint32_t pair_rounds;  // rounds that did so
   uint32_t tiny_count;   // jobs in the tiny-job list
+  uint32_t eq_bins;      // bins marked for an equality split
   unsigned long long moved_records;
   unsigned long long large_records;
   unsigned long long batch_total;
@@ -187,6 +199,7 @@ struct Layout {
   Bin* large[2];
   uint32_t* hist[2];      // [cap_large][kRadix]
   uint64_t* diff[2];      // [cap_large][8]
+  uint64_t* eqkey[2];     // [cap_large][8] equality key of a kBinEq bin (masked key words)
   uint32_t* tile_prefix;  // [cap_large + 1]
   uint32_t* tile_bin;     // [cap_tiles]: bin index of each tile of the round
   uint64_t* status;       // [cap_tiles][kRadix] look-back status words
@@ -219,7 +232,9 @@ struct Params {
   uint32_t lookback;      // 1: decoupled look-back scatter, 0: carry scan
   uint32_t pair;          // 1: the top-level histogram also counts digit pairs
   uint32_t pair_min_bins; // fewest second-round bins that take the pair counts
-  uint32_t rounds;
+  uint32_t rounds;         // rounds launched
+  uint32_t round_budget;  // rounds a full sort launches (equality splits must fit in them)
+  uint32_t eq_split;      // 1: classify may mark dominated bins for an equality split
   uint32_t inspect;       // 1: stop after the rounds (no LDS, tiny or copy kernels)
   uint32_t mode;
   uint32_t count;          // arrays

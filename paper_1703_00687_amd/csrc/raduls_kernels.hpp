@@ -156,6 +156,35 @@ __device__ __forceinline__ int top_bit(const uint64_t (&d)[KW]) {
   return r;
 }
 
+// How a large bin's records are bucketed in a round: by the digit
+// [lob, lob + w) of the key (Sec. 1), or, for a bin marked for an equality
+// split (kBinEq), into 0: keys below its equality key, 1: that key, 2: keys
+// above it (the key bits stay to be sorted in both ranges).
+template <int KW>
+struct Bucketing {
+  uint32_t lob, w, nb;
+  bool eq;
+  uint64_t k[KW];
+  __device__ __forceinline__ uint32_t of(const uint64_t (&key)[KW]) const {
+    if (eq) return key_eq<KW>(key, k) ? 1u : (key_lt<KW>(key, k) ? 0u : 2u);
+    return digit_of<KW>(key, lob, w);
+  }
+};
+// The bucketing of bin b of large list `list` (its equality key, if any, is
+// read from that list's key table).
+template <int KW>
+__device__ __forceinline__ Bucketing<KW> bucketing(const Params& P, const Bin& bin, uint32_t list,
+                                                   uint32_t b) {
+  Bucketing<KW> d;
+  d.eq = (bin.flags & kBinEq) != 0;
+  d.w = d.eq ? 2u : min(P.digit_bits, uint32_t(bin.bits));
+  d.lob = d.eq ? uint32_t(bin.bits) : uint32_t(bin.bits) - d.w;
+  d.nb = 1u << d.w;
+#pragma unroll
+  for (int q = 0; q < KW; ++q) d.k[q] = d.eq ? P.L.eqkey[list][uint64_t(b) * 8 + q] : 0ull;
+  return d;
+}
+
 // Wave-wide OR, returned to every lane: DPP reductions inside each row of 16
 // lanes, then the rows combined through the broadcasts of lanes 15 and 31,
 // after which lane 63 holds the total.
@@ -277,7 +306,11 @@ __device__ __forceinline__ bool push_bin(Bin* list, uint32_t* count, uint32_t ca
 
 // Append a bin to the next large list and clear its histogram and key-spread
 // rows (they are accumulated with atomics by the next round's k_hist).
-__device__ __forceinline__ void push_large(const Params& P, uint32_t nxt, const Bin& b) {
+// Pushes a large bin for the next round (with its equality key when it is
+// marked kBinEq) and clears its histogram row and key spread.
+template <int KW>
+__device__ __forceinline__ void push_large(const Params& P, uint32_t nxt, const Bin& b,
+                                           const uint64_t (&eqk)[KW]) {
   uint32_t i;
   if (!push_bin(P.L.large[nxt], &P.L.ctrl->large_count[nxt], P.L.cap_large, b, &P.L.ctrl->error, &i))
     return;
@@ -285,6 +318,41 @@ __device__ __forceinline__ void push_large(const Params& P, uint32_t nxt, const 
   for (int q = 0; q < kRadix / 4; ++q) h[q] = make_uint4(0, 0, 0, 0);
   uint64_t* df = P.L.diff[nxt] + uint64_t(i) * 8;
   for (int q = 0; q < 8; ++q) df[q] = 0;
+  if (b.flags & kBinEq) {
+#pragma unroll
+    for (int q = 0; q < KW; ++q) P.L.eqkey[nxt][uint64_t(i) * 8 + q] = eqk[q];
+  }
+}
+
+// Whether a large bin about to be pushed is dominated by one key: the
+// Boyer-Moore majority candidate of kEqSamples evenly spaced records, kept
+// when at least kEqDominant of the samples equal it.  `base` is the bin's
+// first record; R the record size.
+template <int KW>
+__device__ bool dominant_key(const uint8_t* base, uint32_t size, uint32_t R, uint64_t kmask,
+                             uint64_t (&cand)[KW]) {
+  const RADULS_GLOBAL uint8_t* b8 = gmem(base);
+  uint32_t votes = 0;
+  for (uint32_t i = 0; i < kEqSamples; ++i) {
+    const uint64_t pos = (uint64_t(2 * i + 1) * size) / (2 * kEqSamples);
+    uint64_t k[KW];
+    key_of<KW>(reinterpret_cast<const RADULS_GLOBAL uint64_t*>(b8 + pos * R), kmask, k);
+    if (votes == 0) {
+#pragma unroll
+      for (int q = 0; q < KW; ++q) cand[q] = k[q];
+      votes = 1;
+    } else {
+      votes += key_eq<KW>(k, cand) ? 1u : uint32_t(-1);
+    }
+  }
+  uint32_t same = 0;
+  for (uint32_t i = 0; i < kEqSamples; ++i) {
+    const uint64_t pos = (uint64_t(2 * i + 1) * size) / (2 * kEqSamples);
+    uint64_t k[KW];
+    key_of<KW>(reinterpret_cast<const RADULS_GLOBAL uint64_t*>(b8 + pos * R), kmask, k);
+    same += key_eq<KW>(k, cand) ? 1u : 0u;
+  }
+  return same >= kEqDominant;
 }
 
 // Slot in a list for every active lane with `want`: one atomic per wave on
@@ -408,7 +476,10 @@ static __global__ void __launch_bounds__(256) k_seed_batch(Params P) {
     b.bits = uint16_t(8 * P.K);
     b.side = 0;
     b.flags = 0;
-    if (d.n > P.mid_max) push_large(P, 0, b);
+    if (d.n > P.mid_max) {
+      const uint64_t none[1] = {};
+      push_large<1>(P, 0, b, none);
+    }
     else if (d.n >= 2) push_mid(P, b, d);
   }
 }
@@ -480,7 +551,7 @@ __device__ uint32_t pair_decide(const Params& P, uint32_t cur, uint32_t nb, uint
       else hi = mid;
     }
     s_d1[t] = lo;
-    if (bn.bits != bits || bn.side != 1 || bn.array != 0 || s_pre[lo] != bn.start ||
+    if (bn.bits != bits || bn.side != 1 || bn.array != 0 || bn.flags != 0 || s_pre[lo] != bn.start ||
         root[lo] != bn.size || s_nz[lo] < 2)
       atomicAnd(&s_ok, 0u);
   }
@@ -645,6 +716,7 @@ __global__ void __launch_bounds__(kScatterBlock, TOP == 2 ? 1 : 8) k_hist(Params
   const uint8_t* src = bin.side ? arr.tmp : arr.recs;
   uint64_t key0[KW];
   key_of<KW>(gmem(reinterpret_cast<const uint64_t*>(src)) + uint64_t(bin.start) * RW, P.kmask, key0);
+  Bucketing<KW> bk = bucketing<KW>(P, bin, cur, b);
 
   // the tile to load: its bin (bl) and that bin's tiles, records and source,
   // kept in registers so that the loads of a tile wait for nothing (a load of
@@ -697,14 +769,14 @@ __global__ void __launch_bounds__(kScatterBlock, TOP == 2 ? 1 : 8) k_hist(Params
         arr = P.L.arrays[bin.array];
         src = bin.side ? arr.tmp : arr.recs;
         key_of<KW>(gmem(reinterpret_cast<const uint64_t*>(src)) + uint64_t(bin.start) * RW, P.kmask, key0);
+        bk = bucketing<KW>(P, bin, cur, b);
       }
       b_end = b + 1 < nbins ? tp[b + 1] : 0xFFFFFFFFu;
     }
     if (tid == 0) P.L.tile_bin[t] = b;
     const uint32_t tn = tnr;
     const uint32_t ipw = (tn + kWave * W - 1) / (kWave * W);
-    const uint32_t w = min(P.digit_bits, uint32_t(bin.bits));
-    const uint32_t lob = bin.bits - w;
+    const uint32_t lob = bk.lob;
     uint32_t dg[ITEMS];
     bool valid[ITEMS];
 #pragma unroll
@@ -714,7 +786,7 @@ __global__ void __launch_bounds__(kScatterBlock, TOP == 2 ? 1 : 8) k_hist(Params
       dg[j] = 0;
       kt[j][KW - 1] &= P.kmask;
       if (valid[j]) {
-        dg[j] = digit_of<KW>(kt[j], lob, w);
+        dg[j] = bk.of(kt[j]);
 #pragma unroll
         for (int q = 0; q < KW; ++q) dacc[q] |= kt[j][q] ^ key0[q];
       }
@@ -897,9 +969,8 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(Params P, uint32_t cu
     const ArrayDesc arr = P.L.arrays[bin.array];
     const uint8_t* src = bin.side ? arr.tmp : arr.recs;
     uint8_t* dst = bin.side ? arr.recs : arr.tmp;
-    const uint32_t w = min(P.digit_bits, uint32_t(bin.bits));
-    const uint32_t lob = bin.bits - w;
-    const uint32_t nb = 1u << w;
+    const Bucketing<KW> bk = bucketing<KW>(P, bin, cur, b);
+    const uint32_t nb = bk.nb;
 
     if (!LOOKBACK && k == 0) running = 0;  // a new bin starts inside the range
     const uint32_t h = tid < nb ? P.L.hist[cur][uint64_t(b) * kRadix + tid] : 0;
@@ -933,12 +1004,12 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(Params P, uint32_t cu
         load_rec<RW>(src, uint64_t(tbeg) + i, rec[j]);
         uint64_t key[KW];
         key_of<KW>(rec[j], P.kmask, key);
-        dg[j] = digit_of<KW>(key, lob, w);
+        dg[j] = bk.of(key);
       }
     }
     uint16_t* wc = s_cnt + wave * kRadix;
     for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
-    wave_rank<ITEMS>(dg, valid, w, wc, rank);
+    wave_rank<ITEMS>(dg, valid, bk.w, wc, rank);
     __syncthreads();
     block_digit_scan<W>(s_cnt, s_tot, s_off, s_scan);
 
@@ -1081,7 +1152,8 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
   // state of the bin the current tile belongs to (uniform), including its
   // tile range [bt0, bt1), kept in registers: a global load inside the tile
   // loop would make it wait for every store still in flight
-  uint32_t b = 0, w = 0, lob = 0, nb = 0, bt0 = 0, bt1 = 0;
+  uint32_t b = 0, nb = 0, bt0 = 0, bt1 = 0;
+  Bucketing<KW> bk{};
   Bin bin{};
   const uint8_t* src = nullptr;
   uint8_t* dst = nullptr;
@@ -1095,9 +1167,8 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
     src = bin.side ? arr.tmp : arr.recs;
     dst = bin.side ? arr.recs : arr.tmp;
     lines_on = LINES && (reinterpret_cast<uintptr_t>(dst) & 127u) == 0;
-    w = min(P.digit_bits, uint32_t(bin.bits));
-    lob = bin.bits - w;
-    nb = 1u << w;
+    bk = bucketing<KW>(P, bin, cur, b);
+    nb = bk.nb;
     const uint32_t* hrow = whole_bin ? P.L.pair_hist + P.L.pair_d1[b] * kRadix
                                      : P.L.hist[cur] + uint64_t(b) * kRadix;
     const uint32_t h = tid < nb ? hrow[tid] : 0;
@@ -1153,7 +1224,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
         if (valid[j]) {
           uint64_t key[KW];
           key_of<KW>(rec[j], P.kmask, key);
-          dg[j] = digit_of<KW>(key, lob, w);
+          dg[j] = bk.of(key);
 #pragma unroll
           for (int q = 0; q < RW; ++q) s_rec[uint64_t(i) * RW + q] = rec[j][q];
         }
@@ -1162,7 +1233,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
       uint32_t rank[ITEMS];
       uint16_t* wc = s_cnt + wave * kRadix;
       for (int q = lane; q < kRadix; q += kWave) wc[q] = 0;
-      wave_rank<ITEMS>(dg, valid, w, wc, rank);
+      wave_rank<ITEMS>(dg, valid, bk.w, wc, rank);
       lds_barrier();
       block_digit_scan<W>(s_cnt, s_tot, s_off, s_scan);
       if (tid < nb) {
@@ -1227,7 +1298,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
             const uint64_t* r = s_rec + uint64_t(sl) * RW;
             uint64_t key[KW];
             key_of<KW>(r, P.kmask, key);
-            const uint32_t d = digit_of<KW>(key, lob, w);
+            const uint32_t d = bk.of(key);
             const uint64_t at = s_gbase[d] + p;
             if (at < s_lim[d]) {
               // never write outside the bin, whatever the counts say
@@ -1254,7 +1325,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
             const uint64_t* r = s_rec + uint64_t(sl) * RW;
             uint64_t key[KW];
             key_of<KW>(r, P.kmask, key);
-            const uint32_t d = digit_of<KW>(key, lob, w);
+            const uint32_t d = bk.of(key);
             const uint64_t at = s_gbase[d] + p;
             // never write outside the bin, whatever the counts say
             if (at - bin.start < bin.size) store_rec<RW>(dst, at, r, nt);
@@ -1297,7 +1368,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
 // siblings are packed greedily into jobs of at most mid_max records (Sec. 3.3
 // remarks that scanning empty sub-bins one by one costs time).
 template <int KW>
-__global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
+__global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32_t round) {
   __shared__ uint32_t s_cnt[kRadix], s_off[kRadix], s_scan[8];
   __shared__ uint32_t s_js[kRadix], s_jn[kRadix], s_jr[kRadix], s_nj, s_jbase, s_tbase;
   Ctrl* c = P.L.ctrl;
@@ -1307,8 +1378,11 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
   for (uint32_t b = blockIdx.x; b < nbins; b += gridDim.x) {
     __syncthreads();
     const Bin bin = P.L.large[cur][b];
-    const uint32_t w = min(P.digit_bits, uint32_t(bin.bits));
-    const uint32_t lob = bin.bits - w;
+    // an equality split leaves the key bits as they were (buckets: below,
+    // equal to, above the bin's equality key)
+    const bool eqb = (bin.flags & kBinEq) != 0;
+    const uint32_t w = eqb ? 2u : min(P.digit_bits, uint32_t(bin.bits));
+    const uint32_t lob = eqb ? uint32_t(bin.bits) : bin.bits - w;
     const uint32_t nb = 1u << w;
     // with pair counts (second round only) the bin's row is its top digit's
     // row of pair_hist, and any key bit below the bin's digit may differ
@@ -1332,7 +1406,9 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
       if (tid == 0) {
         Bin nbn = bin;
         nbn.bits = uint16_t(tb + 1);
-        push_large(P, nxt, nbn);
+        nbn.flags = uint8_t(bin.flags & kBinRange);
+        const uint64_t none[KW] = {};
+        push_large<KW>(P, nxt, nbn, none);
       }
       continue;
     }
@@ -1347,18 +1423,33 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
       if (tid == 0 && cside == 1) push_copy(P, bin.array, bin.start, bin.size);
       continue;
     }
-    if (tid < nb && h > P.mid_max) {
+    // the equal part of an equality split is finished: all its keys are equal
+    const bool eq_done = eqb && tid == 1;
+    if (eq_done && h > 0 && cside == 1) push_copy(P, bin.array, bin.start + s_off[1], h);
+    if (tid < nb && h > P.mid_max && !eq_done) {
       Bin ch;
       ch.start = bin.start + s_off[tid];
       ch.size = h;
       ch.array = bin.array;
       ch.bits = uint16_t(lob);
       ch.side = cside;
-      ch.flags = 0;
-      push_large(P, nxt, ch);
+      ch.flags = uint8_t((eqb || (bin.flags & kBinRange)) ? kBinRange : 0);
+      // a child that one key dominates is split on that key next round, if
+      // the rounds left leave room for that round and the child's key bits
+      uint64_t eqk[KW] = {};
+      const uint32_t need = (lob + P.digit_bits - 1) / P.digit_bits;
+      if (P.eq_split && round + 2 + need <= P.round_budget) {
+        const ArrayDesc a = P.L.arrays[bin.array];
+        const uint8_t* base = (cside ? a.tmp : a.recs) + uint64_t(ch.start) * P.R;
+        if (dominant_key<KW>(base, h, P.R, P.kmask, eqk)) {
+          ch.flags |= kBinEq;
+          atomicAdd(&c->eq_bins, 1u);
+        }
+      }
+      push_large<KW>(P, nxt, ch, eqk);
     }
     // no child small enough for a sort job (the usual case at the top level)
-    if (!__syncthreads_or(tid < nb && h > 0 && h <= P.mid_max)) continue;
+    if (!__syncthreads_or(tid < nb && h > 0 && h <= P.mid_max && !eq_done)) continue;
     // greedy packing of the small children into jobs, in digit order: every
     // wave runs the same branch-free scalar loop, lane l holding the counts
     // and offsets of digits 4l..4l+3 (read out with readlane, so the loop
@@ -1369,14 +1460,16 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur) {
     // parallel write of the descriptors.
     {
       const uint32_t lane = tid & (kWave - 1);
+      const uint32_t M = P.mid_max;
       int cq[4], oq[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t d = 4 * lane + q;
-        cq[q] = d < nb ? int(s_cnt[d]) : 0;
+        // (the finished equal part of an equality split counts as a large
+        // child: it ends the job before it and joins none)
+        cq[q] = d < nb ? int((eqb && d == 1 && s_cnt[d]) ? M + 1 : s_cnt[d]) : 0;
         oq[q] = d < nb ? int(s_off[d]) : 0;
       }
-      const uint32_t M = P.mid_max;
       // (a lone record in recs is in place)
       const uint32_t lone_moves = __builtin_amdgcn_readfirstlane(uint32_t(cside)) != 0 ? 1u : 0u;
       uint32_t js = 0, jn = 0, nj = 0, nm = 0, nt = 0;
@@ -2866,7 +2959,7 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
     if (r == 0) launch_scatter<RW, KW, 1>(P, cur, s);
     else launch_scatter<RW, KW, 0>(P, cur, s);
     if (r <= 1) prof_mark(slot + 1, 1, s);
-    k_classify<KW><<<P.grid_classify, 256, 0, s>>>(P, cur);
+    k_classify<KW><<<P.grid_classify, 256, 0, s>>>(P, cur, r);
   }
   if (P.inspect) return hipGetLastError();
   prof_mark(kProfMid, 0, s);

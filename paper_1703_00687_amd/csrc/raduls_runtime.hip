@@ -75,7 +75,9 @@ bool use_pair(const Eff& e, uint64_t n, uint32_t K) {
 
 struct Shape {
   uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges, rounds, pair;
-  uint64_t off_ctrl, off_arrays, off_large[2], off_hist[2], off_diff[2], off_tp, off_tb, off_status,
+  uint32_t eq_split;
+  uint64_t off_ctrl, off_arrays, off_large[2], off_hist[2], off_diff[2], off_eqkey[2], off_tp, off_tb,
+      off_status,
       off_tail, off_carry, off_flag, off_mid, off_tiny, off_copy, off_pair_part, off_pair_hist, off_pair_d1,
       bytes;
 };
@@ -91,6 +93,10 @@ Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const
   s.pair = pair ? 1 : 0;
   const uint64_t T = e.mid_max;
   s.rounds = step ? 1 : (8 * K + e.digit_bits - 1) / e.digit_bits;
+  // many records: dominated bins may be split on an equality key, which
+  // takes a round but no key bit
+  s.eq_split = !step && n_total > 64ull * T ? 1u : 0u;
+  if (s.eq_split) s.rounds += kEqRounds;
   const uint64_t large = step ? 1 : n_total / (T + 1) + 1;
   const uint64_t tiles = n_total / e.tile + large + 1;
   const uint64_t mid = step ? 1 : 2 * (n_total / std::max<uint64_t>(T, 1) + 1) + 3ull * s.rounds * large + count + 16;
@@ -113,6 +119,7 @@ Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const
   for (int i = 0; i < 2; ++i) s.off_large[i] = take(uint64_t(s.cap_large) * sizeof(Bin));
   for (int i = 0; i < 2; ++i) s.off_hist[i] = take(uint64_t(s.cap_large) * kRadix * 4);
   for (int i = 0; i < 2; ++i) s.off_diff[i] = take(uint64_t(s.cap_large) * 8 * 8);
+  for (int i = 0; i < 2; ++i) s.off_eqkey[i] = take(s.eq_split ? uint64_t(s.cap_large) * 8 * 8 : 0);
   s.off_tp = take((uint64_t(s.cap_large) + 1) * 4);
   s.off_tb = take(uint64_t(s.cap_tiles) * 4);
   s.off_status = take(status_rows * kRadix * 8);
@@ -140,6 +147,7 @@ Layout make_layout(uint8_t* aux, const Shape& s) {
     L.large[i] = reinterpret_cast<Bin*>(aux + s.off_large[i]);
     L.hist[i] = reinterpret_cast<uint32_t*>(aux + s.off_hist[i]);
     L.diff[i] = reinterpret_cast<uint64_t*>(aux + s.off_diff[i]);
+    L.eqkey[i] = reinterpret_cast<uint64_t*>(aux + s.off_eqkey[i]);
   }
   L.tile_prefix = reinterpret_cast<uint32_t*>(aux + s.off_tp);
   L.tile_bin = reinterpret_cast<uint32_t*>(aux + s.off_tb);
@@ -224,6 +232,8 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
   P.nontemporal = e.nontemporal;
   P.lookback = e.lookback;
   P.rounds = s.rounds;
+  P.round_budget = s.rounds;
+  P.eq_split = s.eq_split;
   P.mode = mode;
   P.count = count;
   const DevInfo d = device_info();
@@ -404,6 +414,7 @@ int raduls_inspect_rounds(void* recs, void* tmp, uint64_t n, uint32_t rec_bytes,
       bins[i].size = host[i].size;
       bins[i].bits = host[i].bits;
       bins[i].side = host[i].side;
+      bins[i].flags = host[i].flags;
     }
   }
   return c.error ? RADULS_E_DEVICE : RADULS_OK;
@@ -510,6 +521,7 @@ int raduls_check(const void* tmp_or_ws, uint64_t n, uint32_t rec_bytes, int ws_o
   stats->moved_records = c.moved_records;
   stats->large_records = c.large_records;
   stats->pair_rounds = c.pair_rounds;
+  stats->eq_bins = c.eq_bins;
   return c.error ? RADULS_E_DEVICE : RADULS_OK;
 }
 

@@ -142,7 +142,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         "         offsetof(raduls_tuning, wave_job_max), offsetof(raduls_tuning, es_job_max),\n"
         "         sizeof(raduls_stats), offsetof(raduls_stats, moved_records),\n"
         "         offsetof(raduls_stats, pair_rounds), sizeof(raduls_array),\n"
-        "         sizeof(raduls_bin), offsetof(raduls_bin, side));\n"
+        "         sizeof(raduls_bin), offsetof(raduls_bin, flags));\n"
         "  return 0;\n}\n")
     exe = tmp_path / "layout"
     inc = os.path.join(ROOT, "include")
@@ -154,5 +154,5 @@ def test_struct_layouts_match_the_header(tmp_path):
             b.raduls_tuning.pair_hist.offset, b.raduls_tuning.wave_job_max.offset,
             b.raduls_tuning.es_job_max.offset, ctypes.sizeof(b.raduls_stats),
             b.raduls_stats.moved_records.offset, b.raduls_stats.pair_rounds.offset,
-            ctypes.sizeof(b.raduls_array), ctypes.sizeof(b.raduls_bin), b.raduls_bin.side.offset]
+            ctypes.sizeof(b.raduls_array), ctypes.sizeof(b.raduls_bin), b.raduls_bin.flags.offset]
     assert got == want

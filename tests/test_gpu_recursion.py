@@ -7,9 +7,11 @@ global rounds and returns the large bins they left.  Each one must be a
 maximal run of the oracle's sorted output whose keys agree on every bit from
 the bin's `bits` up, larger than mid_max, and its records (on the side the
 entry names) must be exactly those of that run in input order (every pass is
-a stable partition; the payload holds the input index).  With uniform keys
-and a fixed digit width no digit is skipped, so the list must also be exactly
-the oracle's bins at level l (oracle.bins_at_level) that exceed mid_max."""
+a stable partition; the payload holds the input index).  A bin that is one
+side of an equality split (a key range inside such a run, flag bit 1) must
+pass the same checks except maximality.  With uniform keys and a fixed digit
+width no digit is skipped, so the list must also be exactly the oracle's
+bins at level l (oracle.bins_at_level) that exceed mid_max."""
 
 import numpy as np
 import pytest
@@ -44,7 +46,7 @@ def check_round(host, key_bytes, idx_word, rounds, exact_level_width=None):
     srt = oracle.sort(host, key_bytes)
     idx = srt.view("<u8")[:, idx_word]
     covered = np.zeros(n, dtype=bool)
-    for start, size, bits, side in bins:
+    for start, size, bits, side, flags in bins:
         assert size > mid_max and start + size <= n and side in (0, 1)
         assert 0 < bits <= 8 * key_bytes
         assert not covered[start:start + size].any(), "bins overlap"
@@ -52,19 +54,21 @@ def check_round(host, key_bytes, idx_word, rounds, exact_level_width=None):
         mk = masked_keys(srt[max(start - 1, 0):start + size + 1], key_bytes, bits)
         body = mk[(1 if start > 0 else 0):][:size]
         assert (body == body[0]).all(), "a bin's records differ above its bits"
-        if start > 0:
-            assert not np.array_equal(mk[0], body[0]), "bin is not maximal (left)"
-        if start + size < n:
-            assert not np.array_equal(mk[-1], body[0]), "bin is not maximal (right)"
+        if not flags & 2:
+            if start > 0:
+                assert not np.array_equal(mk[0], body[0]), "bin is not maximal (left)"
+            if start + size < n:
+                assert not np.array_equal(mk[-1], body[0]), "bin is not maximal (right)"
         expect = srt[start:start + size][np.argsort(idx[start:start + size], kind="stable")]
         assert np.array_equal(sides[side][start:start + size], expect), \
             "a bin's records are not the stable partition"
     if exact_level_width is not None:
         starts, sizes = oracle.bins_at_level(srt, key_bytes, exact_level_width, rounds)
         want = sorted((int(s), int(z)) for s, z in zip(starts, sizes) if z > mid_max)
-        got = sorted((s, z) for s, z, _, _ in bins)
+        got = sorted((s, z) for s, z, _, _, _ in bins)
         assert got == want
-        assert all(bt == 8 * key_bytes - exact_level_width * rounds for _, _, bt, _ in bins)
+        assert all(bt == 8 * key_bytes - exact_level_width * rounds and fl == 0
+                   for _, _, bt, _, fl in bins)
     return bins
 
 
@@ -89,7 +93,7 @@ def test_bins_deep_keys_skip_constant_digits(rounds):
     if rounds == 1:
         # the top 44 key bits are zero for every record: the first round's
         # children already lie below them
-        assert bins and all(bt <= 84 for _, _, bt, _ in bins)
+        assert bins and all(bt <= 84 for _, _, bt, _, _ in bins)
 
 
 def test_bins_small_input_runs_no_round():
@@ -97,3 +101,22 @@ def test_bins_small_input_runs_no_round():
     recs = torch.from_numpy(host.reshape(-1).copy()).cuda()
     tmp = torch.empty(b.raduls_tmp_bytes(1000, 16, 8), dtype=torch.uint8, device="cuda")
     assert b.raduls_inspect_rounds(recs, tmp, 1000, 16, 8, 1) == []
+
+
+def test_equality_splits_of_dominated_bins():
+    """A few keys dominate: bins they fill are split on them (stats count the
+    splits), the bins left after such a round pass the checks above, and the
+    whole sort equals the oracle's."""
+    host = wl.zipf16(1 << 22, seed=45, values=1 << 12)
+    marked = False
+    for rounds in (1, 2, 3):
+        bins = check_round(host, 8, 1, rounds)
+        marked = marked or any(fl & 1 for *_, fl in bins)
+    assert marked, "no bin was marked for a split on a dominant key"
+    n = host.shape[0]
+    recs = torch.from_numpy(host.reshape(-1).copy()).cuda()
+    tmp = torch.empty(b.raduls_tmp_bytes(n, 16, 8), dtype=torch.uint8, device="cuda")
+    b.raduls_sort(recs, tmp, n, 16, 8)
+    st, stats = b.raduls_check(tmp, n, 16, False)
+    assert st == b.OK and stats["eq_bins"] > 0, stats
+    assert np.array_equal(recs.cpu().numpy().reshape(n, 16), oracle.sort(host, 8))
