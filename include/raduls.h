@@ -88,7 +88,11 @@ typedef struct raduls_tuning {
   uint32_t es_job_max;   /* LDS sort jobs of at most this many records skip the counting pass and
                             are finished by one enumeration sort (Sec. 2.2); 1..tiny_max
                             (default 16) */
-  uint32_t reserved[7];
+  uint32_t tile_items;   /* records per thread of a histogram / scatter tile (a tile is 1024
+                            times that); 1..8, clamped to the most the record width's LDS
+                            staging holds, which is also the default (7, 6, 5, 4, 3, 2, 2, 2
+                            for R = 8 .. 64) */
+  uint32_t reserved[6];
 } raduls_tuning;
 
 /* Device-side counters left in the workspace by the last sort that used it. */

@@ -44,7 +44,8 @@ class raduls_tuning(ctypes.Structure):
         ("pair_hist", ctypes.c_uint32),
         ("wave_job_max", ctypes.c_uint32),
         ("es_job_max", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 7),
+        ("tile_items", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 6),
     ]
 
 
@@ -76,7 +77,7 @@ class raduls_array(ctypes.Structure):
 
 
 TUNING_FIELDS = ("digit_bits", "tiny_max", "mid_max", "grid_blocks", "nontemporal", "lookback",
-                 "pair_hist", "wave_job_max", "es_job_max")
+                 "pair_hist", "wave_job_max", "es_job_max", "tile_items")
 
 _lib = None
 

@@ -739,8 +739,8 @@ __global__ void __launch_bounds__(kScatterBlock, TOP == 2 ? 1 : 8) k_hist(Params
     }
     const RADULS_GLOBAL uint64_t* sw = gmem(reinterpret_cast<const uint64_t*>(bl_src));
     const uint32_t k = t - bl_first;
-    const uint32_t tbeg = bl_start + k * TILE;
-    const uint32_t tn = min(TILE, bl_size - k * TILE);
+    const uint32_t tbeg = bl_start + k * P.tile;
+    const uint32_t tn = min(P.tile, bl_size - k * P.tile);
     const uint32_t ipw = (tn + kWave * W - 1) / (kWave * W);
     tn_out = tn;
     // Raw, unconditional loads (lanes past the tile reread its last record,
@@ -989,8 +989,8 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(Params P, uint32_t cu
     }
     block_exclusive_scan256(h, s_binoff, s_scan);
 
-    const uint32_t tbeg = bin.start + k * TILE;
-    const uint32_t tn = min(TILE, bin.size - k * TILE);
+    const uint32_t tbeg = bin.start + k * P.tile;
+    const uint32_t tn = min(P.tile, bin.size - k * P.tile);
     const uint32_t ipw = (tn + kWave * W - 1) / (kWave * W);
     uint64_t rec[ITEMS][RW];
     uint32_t dg[ITEMS], rank[ITEMS];
@@ -1186,8 +1186,8 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
   uint64_t rec[ITEMS][RW];
   auto tile_span = [&](uint32_t t, uint32_t& tbeg, uint32_t& tn, uint32_t& ipw) {
     const uint32_t k = t - bt0;
-    tbeg = bin.start + k * TILE;
-    tn = min(TILE, bin.size - k * TILE);
+    tbeg = bin.start + k * P.tile;
+    tn = min(P.tile, bin.size - k * P.tile);
     ipw = (tn + kWave * W - 1) / (kWave * W);
   };
   auto issue_loads = [&](uint32_t t) {

@@ -53,7 +53,8 @@ Eff effective(const raduls_tuning& t, uint32_t R, uint32_t K) {
   // (wave passes) or than one wave's capacity (workgroup passes), so these
   // bound their number by the LDS list capacities
   e.tiny_max = std::max<uint32_t>(e.tiny_max, (e.mid_max + kMidListCap - 1) / kMidListCap);
-  e.tile = uint32_t(kScatterBlock) * uint32_t(scatter_items(int(rw)));
+  const uint32_t items = uint32_t(scatter_items(int(rw)));
+  e.tile = uint32_t(kScatterBlock) * (t.tile_items ? std::min(t.tile_items, items) : items);
   e.nontemporal = t.nontemporal ? t.nontemporal : 1;
   e.grid_blocks = t.grid_blocks;
   e.lookback = t.lookback ? 1 : 0;
@@ -528,7 +529,7 @@ int raduls_check(const void* tmp_or_ws, uint64_t n, uint32_t rec_bytes, int ws_o
 int raduls_set_tuning(const raduls_tuning* tuning) {
   if (!tuning) return RADULS_E_INVALID;
   if (tuning->digit_bits > 8 || tuning->tiny_max > 256 || tuning->nontemporal > 2 ||
-      tuning->wave_job_max > kTinyJob || tuning->es_job_max > 256)
+      tuning->wave_job_max > kTinyJob || tuning->es_job_max > 256 || tuning->tile_items > 8)
     return RADULS_E_INVALID;
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   g_tuning = *tuning;

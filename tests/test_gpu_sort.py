@@ -54,6 +54,18 @@ def test_tuning_variants(digit_bits, tiny_max, mid_max, r, k):
             _assert_parity(out, inp, k)
 
 
+@pytest.mark.parametrize("tile_items", [1, 2, 3, 5])
+@pytest.mark.parametrize("r,k,lookback", [(16, 8, 0), (32, 16, 1), (8, 8, 0), (24, 13, 0)])
+def test_tile_sizes(tile_items, r, k, lookback):
+    # smaller histogram / scatter tiles than the LDS staging holds (several
+    # tiles per bin, bins that end inside a tile, both prefix schemes)
+    with tuned(tile_items=tile_items, lookback=lookback):
+        for seed, distinct in ((5, None), (6, 40)):
+            inp = _recs(seed + r + tile_items, 300_000, r, k, distinct)
+            out, _ = gpu_sort(inp, k)
+            _assert_parity(out, inp, k)
+
+
 @pytest.mark.parametrize("nontemporal,lookback", [(1, 0), (2, 0), (1, 1), (2, 1)])
 def test_store_policies_and_scans(nontemporal, lookback):
     with tuned(nontemporal=nontemporal, lookback=lookback):
