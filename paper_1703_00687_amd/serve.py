@@ -21,9 +21,10 @@ from __future__ import annotations
 import collections
 import threading
 import time
-from concurrent.futures import Future
 from dataclasses import dataclass, field
 from typing import Any
+
+import numpy as np
 
 
 class Rejected(RuntimeError):
@@ -38,24 +39,61 @@ class BackendError(RuntimeError):
     pass
 
 
-@dataclass
 class Request:
-    recs: Any                     # device tensor [n, R], sorted in place
-    n: int
-    t_arrival: float
-    rid: int
-    future: Future = field(default_factory=Future)
-    t_admit: float = 0.0
-    t_launch: float = 0.0
-    t_done: float = 0.0
-    tmp: Any = None
-    cancelled: bool = False
-    ready: Any = None             # backend token: the input has been written
+    """One queued sort, and its result handle: the subset of
+    concurrent.futures.Future that callers use (result, exception, done).
+    It holds no lock of its own: every request of a server waits on the
+    server's one completion condition, which the scheduler notifies once per
+    completed batch, so a batch of thousands of requests costs one wake-up
+    instead of one per request."""
+
+    __slots__ = ("recs", "n", "t_arrival", "ready", "t_admit", "t_launch", "t_done", "tmp",
+                 "_cv", "_state", "_value")
+    _PENDING, _OK, _ERR = 0, 1, 2
+
+    def __init__(self, recs, n: int, t_arrival: float, cv: threading.Condition,
+                 ready: Any = None):
+        self.recs = recs          # device tensor [n, R], sorted in place
+        self.n = n
+        self.t_arrival = t_arrival
+        self.ready = ready        # backend token: the input has been written
+        self.t_admit = self.t_launch = self.t_done = 0.0
+        self.tmp = None
+        self._cv = cv
+        self._state = Request._PENDING
+        self._value = None
+
+    def done(self) -> bool:
+        return self._state != Request._PENDING
+
+    def _wait(self, timeout):
+        if self._state == Request._PENDING:
+            with self._cv:
+                if not self._cv.wait_for(self.done, timeout):
+                    raise TimeoutError("request not completed in time")
+
+    def result(self, timeout: float | None = None):
+        self._wait(timeout)
+        if self._state == Request._ERR:
+            raise self._value
+        return self._value
+
+    def exception(self, timeout: float | None = None):
+        self._wait(timeout)
+        return self._value if self._state == Request._ERR else None
+
+    # scheduler side: set, then notify the condition (once for many requests)
+    def _resolve(self, value) -> None:
+        self._value = value
+        self._state = Request._OK
+
+    def _fail(self, exc: BaseException) -> None:
+        self._value = exc
+        self._state = Request._ERR
 
 
 @dataclass
 class Stats:
-    submitted: int = 0
     completed: int = 0
     rejected: int = 0
     cancelled: int = 0
@@ -65,6 +103,7 @@ class Stats:
     latencies: list = field(default_factory=list)
     t_first: float = 0.0
     t_last: float = 0.0
+    launch_host_s: float = 0.0    # host time spent preparing and enqueuing batches
 
     def summary(self) -> dict:
         lat = sorted(self.latencies)
@@ -83,6 +122,8 @@ class Stats:
             "max_ms": None if not lat else lat[-1] * 1e3,
             "records_per_s": self.records / span if self.completed else 0.0,
             "span_s": span,
+            "mean_batch": self.completed / self.batches if self.batches else 0.0,
+            "launch_host_s": self.launch_host_s,
         }
 
 
@@ -148,12 +189,13 @@ class GpuBackend:
             self._capture()
 
     def producer_event(self, recs) -> Any:
-        """An event on the submitting thread's current stream: the sort of
-        `recs` waits for it, so work that stream queued to write the input
-        (not yet finished at submission) comes first."""
+        """(stream, event) recorded on the submitting thread's current
+        stream: the sort of `recs` waits for it, so work that stream queued to
+        write the input (not yet finished at submission) comes first."""
+        s = self.torch.cuda.current_stream(recs.device)
         ev = self.torch.cuda.Event()
-        ev.record(self.torch.cuda.current_stream(recs.device))
-        return ev
+        ev.record(s)
+        return (s.cuda_stream, ev)
 
     def _capture(self):
         torch = self.torch
@@ -170,18 +212,21 @@ class GpuBackend:
         torch.cuda.synchronize()
 
     def prepare(self, stream_idx: int, reqs: list) -> bool:
-        """Carve the batch's scratch out of the arena; False if it does not fit
-        yet (the server retries after a batch completes)."""
-        step = [-(-(r.n * self.rec_bytes) // 16) * 16 for r in reqs]
-        total = sum(step)
+        """Carve the batch's scratch out of the arena (one 16-byte aligned
+        slice per request, in order); False if it does not fit yet (the
+        server retries after a batch completes)."""
+        k = len(reqs)
+        ns = np.fromiter((r.n for r in reqs), dtype=np.int64, count=k)
+        step = (ns * self.rec_bytes + 15) // 16 * 16
+        total = int(step.sum())
         off = self.arena.alloc(total)
         if off is None:
             return False
         self.chunks[stream_idx] = (off, total)
-        base = self.arena_buf.data_ptr() + off
-        for r, sz in zip(reqs, step):
-            r.tmp = base
-            base += sz
+        h = self.batches[stream_idx].host_desc.numpy()
+        h[k:] = 0
+        h[:k, 1] = self.arena_buf.data_ptr() + off + np.cumsum(step) - step
+        h[:k, 2] = ns
         return True
 
     def launch(self, stream_idx: int, reqs: list) -> Any:
@@ -189,20 +234,23 @@ class GpuBackend:
         s = self.streams[stream_idx]
         bt = self.batches[stream_idx]
         hd = bt.host_desc
-        h = hd.numpy()
-        h[:] = 0
-        for i, r in enumerate(reqs):
-            h[i, 0] = r.recs.data_ptr()
-            h[i, 1] = r.tmp
-            h[i, 2] = r.n
+        k = len(reqs)
+        hd.numpy()[:k, 0] = np.fromiter((r.recs.data_ptr() for r in reqs), dtype=np.int64,
+                                        count=k)
+        # the producers' writes of the inputs come first: events on one
+        # stream complete in order, so the last one per producing stream
+        # (requests are in arrival order) covers the others.  (The server
+        # keeps every request, and with it its tensor, until the batch has
+        # completed, so the caching allocator cannot hand the memory to other
+        # work meanwhile.)
+        last = {}
+        for r in reqs:
+            if r.ready is not None:
+                last[r.ready[0]] = r.ready[1]
         ev = torch.cuda.Event()
         with torch.cuda.stream(s):
-            for r in reqs:
-                if r.ready is not None:
-                    s.wait_event(r.ready)  # the producer's writes of the input come first
-                # the caching allocator must not hand the input's memory to
-                # another stream's work before this sort is done with it
-                r.recs.record_stream(s)
+            for e in last.values():
+                s.wait_event(e)
             bt.desc.copy_(hd, non_blocking=True)
             if self.graphs[stream_idx] is not None:
                 self.graphs[stream_idx].replay()
@@ -223,14 +271,19 @@ class GpuBackend:
         token.synchronize()
         st, stats = self.batches[stream_idx].check(self.streams[stream_idx])
         err = None if st == self.b.OK else f"device error {stats}"
-        for r in reqs:
-            r.tmp = None
         self.release(stream_idx)
         return [err] * len(reqs)
 
 
 class Server:
-    """Admission by scratch budget and slots, continuous batching over streams."""
+    """Admission by scratch budget and slots, continuous batching over streams.
+
+    Clients append to a lock-free deque (submit / submit_many take no lock
+    the scheduler holds); the scheduler thread moves what has arrived into
+    its pending queue under its own lock, admits in arrival order, launches,
+    and resolves a completed batch's tickets together."""
+
+    SUBMIT_CHUNK = 256   # requests submit_many queues at a time
 
     def __init__(self, backend, rec_bytes: int, budget_bytes: int, max_slots: int,
                  max_batch: int | None = None, poll_s: float = 2e-5):
@@ -249,12 +302,15 @@ class Server:
         self.slots = max_slots
         self.max_batch = max_batch or backend.max_batch
         self.poll_s = poll_s
+        # clients append without a lock; the scheduler, cancel and stop take
+        # requests out only under `lock`
         self.pending: collections.deque = collections.deque()
         self.admitted: list = []
         self.inflight: dict = {}          # stream -> (token, reqs)
         self.lock = threading.Condition()
+        self.done_cv = threading.Condition(threading.Lock())  # tickets wait here
         self.stats = Stats()
-        self._rid = 0
+        self._sleeping = False
         self._stop = False
         self._thread = None
 
@@ -262,41 +318,84 @@ class Server:
     def need(self, n: int) -> int:
         return n * self.rec_bytes
 
-    def submit(self, recs, t_arrival: float | None = None) -> Future:
-        n = int(recs.shape[0])
-        with self.lock:
-            req = Request(recs=recs, n=n, t_arrival=time.perf_counter() if t_arrival is None
-                          else t_arrival, rid=self._rid)
-            self._rid += 1
-            self.stats.submitted += 1
-            if self.need(n) > self.budget:
-                self.stats.rejected += 1
-                req.future.set_exception(Rejected(f"request of {n} records exceeds the budget"))
-                return req.future
-            if self.stats.t_first == 0.0:
-                self.stats.t_first = req.t_arrival
+    def _ready_token(self, recs, ready):
+        if ready is True:
             mark = getattr(self.backend, "producer_event", None)
-            if mark is not None:
-                req.ready = mark(recs)
-            self.pending.append(req)
-            self.lock.notify_all()
-        return req.future
+            return mark(recs) if mark is not None else None
+        return None if ready is False else ready
 
-    def cancel(self, fut: Future) -> bool:
+    def _reject(self, req: Request) -> None:
+        with self.lock:
+            self.stats.rejected += 1
+        req._fail(Rejected(f"request of {req.n} records exceeds the budget"))
+        self._notify_done()
+
+    def _wake(self) -> None:
+        if self._sleeping:
+            with self.lock:
+                self.lock.notify_all()
+
+    def submit(self, recs, t_arrival: float | None = None, ready: Any = True) -> Request:
+        """Queue `recs` (an [n, R] device tensor) for sorting in place; the
+        returned request is its result handle.  ready=True (default): the
+        sort waits for the work the calling thread's current stream has
+        queued so far (the backend records an event there); ready=False: the
+        caller guarantees the input is already written (e.g. after a
+        synchronize); otherwise a backend token to wait for."""
+        n = int(recs.shape[0])
+        req = Request(recs, n, time.perf_counter() if t_arrival is None else t_arrival,
+                      self.done_cv)
+        if n * self.rec_bytes > self.budget:
+            self._reject(req)
+            return req
+        req.ready = self._ready_token(recs, ready)
+        self.pending.append(req)   # deque appends are atomic: no lock
+        self._wake()
+        return req
+
+    def submit_many(self, arrays, t_arrival: float | None = None, ready: Any = True) -> list:
+        """submit() for several arrays at once, in order: one readiness token
+        covers them all (they come from the same stream).  Requests are handed
+        to the scheduler in chunks, so the first batch can launch while later
+        requests are still being queued."""
+        if not len(arrays):
+            return []
+        token = self._ready_token(arrays[0], ready)
+        t = time.perf_counter() if t_arrival is None else t_arrival
+        cap, R, cv = self.budget, self.rec_bytes, self.done_cv
+        out = []
+        for c in range(0, len(arrays), self.SUBMIT_CHUNK):
+            reqs = [Request(a, int(a.shape[0]), t, cv, token)
+                    for a in arrays[c:c + self.SUBMIT_CHUNK]]
+            ok = [r for r in reqs if r.n * R <= cap]
+            if len(ok) != len(reqs):
+                for r in reqs:
+                    if r.n * R > cap:
+                        self._reject(r)
+            self.pending.extend(ok)
+            self._wake()
+            out += reqs
+        return out
+
+    def _notify_done(self) -> None:
+        with self.done_cv:
+            self.done_cv.notify_all()
+
+    def cancel(self, fut: Request) -> bool:
         """Cancel a request that has not been launched yet."""
         with self.lock:
             for q, reserved in ((self.pending, False), (self.admitted, True)):
-                for r in list(q):
-                    if r.future is fut:
-                        q.remove(r)
-                        if reserved:  # admitted requests hold budget and a slot
-                            self.free += self.need(r.n)
-                            self.slots += 1
-                        r.tmp = None
-                        self.stats.cancelled += 1
-                        fut.set_exception(Cancelled("cancelled before launch"))
-                        self.lock.notify_all()
-                        return True
+                if fut in q:     # identity: requests define no equality
+                    q.remove(fut)
+                    if reserved:  # admitted requests hold budget and a slot
+                        self.free += self.need(fut.n)
+                        self.slots += 1
+                    fut.tmp = None
+                    self.stats.cancelled += 1
+                    fut._fail(Cancelled("cancelled before launch"))
+                    self._notify_done()
+                    self.lock.notify_all()
+                    return True
         return False
 
     # ------------------------------------------------------------ scheduler
@@ -308,10 +407,10 @@ class Server:
     def stop(self, drain: bool = True) -> dict:
         with self.lock:
             if not drain:
-                for r in list(self.pending):
-                    r.future.set_exception(Cancelled("server stopped"))
+                while self.pending:
+                    self.pending.popleft()._fail(Cancelled("server stopped"))
                     self.stats.cancelled += 1
-                self.pending.clear()
+                self._notify_done()
             self._stop = True
             self.lock.notify_all()
         if self._thread is not None:
@@ -324,51 +423,69 @@ class Server:
                 return s
         return None
 
+    def _complete(self, s, tok, reqs) -> None:
+        try:
+            errs = self.backend.finish(s, tok, reqs)
+        except Exception as e:  # backend failure: fail the batch, keep serving
+            errs = [f"backend failure: {e}"] * len(reqs)
+        now = time.perf_counter()
+        R = self.rec_bytes
+        with self.lock:
+            del self.inflight[s]
+            st = self.stats
+            freed = 0
+            lat = st.latencies
+            for r, err in zip(reqs, errs):
+                freed += r.n * R
+                r.t_done = now
+                if err:
+                    st.failed += 1
+                    r._fail(BackendError(err))
+                else:
+                    st.completed += 1
+                    st.records += r.n
+                    lat.append(now - r.t_arrival)
+                    r._resolve(r.recs)
+            if st.completed:
+                st.t_last = now
+            self.free += freed
+            self.slots += len(reqs)
+            self.lock.notify_all()
+        self._notify_done()
+
     def step(self) -> bool:
         """One scheduling pass; returns True if it did any work."""
         worked = False
-        # completions
         for s, (tok, reqs) in list(self.inflight.items()):
             if self.backend.done(tok):
-                try:
-                    errs = self.backend.finish(s, tok, reqs)
-                except Exception as e:  # backend failure: fail the batch, keep serving
-                    errs = [f"backend failure: {e}"] * len(reqs)
-                now = time.perf_counter()
-                with self.lock:
-                    del self.inflight[s]
-                    for r, err in zip(reqs, errs):
-                        self.free += self.need(r.n)
-                        self.slots += 1
-                        r.t_done = now
-                        if err:
-                            self.stats.failed += 1
-                            r.future.set_exception(BackendError(err))
-                        else:
-                            self.stats.completed += 1
-                            self.stats.records += r.n
-                            self.stats.latencies.append(now - r.t_arrival)
-                            self.stats.t_last = now
-                            r.future.set_result(r.recs)
-                    self.lock.notify_all()
+                self._complete(s, tok, reqs)
                 worked = True
         # admission, in arrival order (no overtaking)
         with self.lock:
             s_idx = self._idle_stream()
-            while self.pending and self.slots > 0 and len(self.admitted) < self.max_batch:
-                r = self.pending[0]
-                if self.need(r.n) > self.free:
+            pend, adm, R = self.pending, self.admitted, self.rec_bytes
+            room = min(self.slots, self.max_batch - len(adm))
+            took = 0
+            while pend and took < room:
+                nb = pend[0].n * R
+                if nb > self.free:
                     break
-                self.pending.popleft()
-                self.free -= self.need(r.n)
-                self.slots -= 1
-                r.t_admit = time.perf_counter()
-                self.admitted.append(r)
+                self.free -= nb
+                adm.append(pend.popleft())
+                took += 1
+            if took:
+                self.slots -= took
+                now = time.perf_counter()
+                if not self.stats.t_first:  # admission is in arrival order
+                    self.stats.t_first = adm[-took].t_arrival
+                for r in adm[-took:]:
+                    r.t_admit = now
                 worked = True
-            if s_idx is None or not self.admitted:
+            if s_idx is None or not adm:
                 return worked
-            batch, self.admitted = self.admitted, []
+            batch, self.admitted = adm, []
         # launch on the idle stream
+        t_host = time.perf_counter()
         try:
             if not self.backend.prepare(s_idx, batch):
                 with self.lock:  # scratch fragmented: retry after a completion
@@ -384,7 +501,8 @@ class Server:
                     self.slots += 1
                     r.tmp = None
                     self.stats.failed += 1
-                    r.future.set_exception(BackendError(f"launch failed: {e}"))
+                    r._fail(BackendError(f"launch failed: {e}"))
+            self._notify_done()
             return True
         now = time.perf_counter()
         for r in batch:
@@ -392,16 +510,23 @@ class Server:
         with self.lock:
             self.inflight[s_idx] = (tok, batch)
             self.stats.batches += 1
+            self.stats.launch_host_s += now - t_host
         return True
 
     def _run(self):
         while True:
-            worked = self.step()
+            if self.step():
+                continue
             with self.lock:
-                if self._stop and not self.pending and not self.admitted and not self.inflight:
+                idle = not (self.pending or self.admitted or self.inflight)
+                if self._stop and idle:
                     return
-                if not worked:
-                    if not self.inflight and not self.pending and not self._stop:
+                if idle:
+                    # a client that appends after this check sees _sleeping
+                    # set and notifies; the timeout only bounds a lost race
+                    self._sleeping = True
+                    if not self.pending:
                         self.lock.wait(timeout=0.01)
-            if not worked:
-                time.sleep(self.poll_s)
+                    self._sleeping = False
+                    continue
+            time.sleep(self.poll_s)

@@ -210,3 +210,31 @@ def test_budget_above_backend_capacity_is_refused():
     with pytest.raises(ValueError):
         serve.Server(be, rec_bytes=16, budget_bytes=1001, max_slots=4)
     serve.Server(be, rec_bytes=16, budget_bytes=1000, max_slots=4)  # at the capacity: fine
+
+
+def test_submit_many_keeps_order_and_rejects_only_oversize():
+    be = FakeBackend(n_streams=2, max_batch=4, delay_s=0.001)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=16 * 5000, max_slots=8).start()
+    arrays = _arrays(12, seed=21)
+    big = wl.random_records(np.random.default_rng(22), 6000, 16, 8)  # above the budget
+    batch = arrays[:6] + [big] + arrays[6:]
+    expect = [oracle.sort(a, 8) for a in batch]
+    futs = srv.submit_many(batch)
+    with pytest.raises(serve.Rejected):
+        futs[6].result(timeout=5)
+    for i, f in enumerate(futs):
+        if i != 6:
+            assert np.array_equal(f.result(timeout=30), expect[i])
+    s = srv.stop()
+    assert s["requests"] == 12 and s["rejected"] == 1
+    assert srv.free == srv.budget and srv.slots == srv.max_slots
+
+
+def test_ticket_times_out_while_pending():
+    be = FakeBackend(n_streams=1, max_batch=1, delay_s=0.2)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 20, max_slots=1).start()
+    f = srv.submit(_arrays(1, seed=23)[0])
+    with pytest.raises(TimeoutError):
+        f.result(timeout=0.01)
+    assert f.result(timeout=10) is not None and f.done()
+    srv.stop()
