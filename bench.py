@@ -201,6 +201,31 @@ def cpu_baseline(name: str, log2n: int, par_log2n: int) -> dict:
 MOVE_PASSES = ["top_scatter", "round2_scatter", "lds_sort"]
 
 
+def plain_ms(src, n, R, K, reps):
+    """Median of `reps` plain sorts of fresh copies of src (HIP events on the
+    current stream around the call only)."""
+    import torch
+    from paper_1703_00687_amd import binding as b
+    c = torch.empty_like(src)
+    tmp = torch.empty(b.raduls_tmp_bytes(n, R, K), dtype=torch.uint8, device=src.device)
+    times = []
+    for i in range(reps + 1):
+        c.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.raduls_sort(c, tmp, n, R, K)
+        e1.record()
+        e1.synchronize()
+        if i:
+            times.append(e0.elapsed_time(e1))
+    st, stats = b.raduls_check(tmp, n, R, False)
+    if st != b.OK:
+        raise RuntimeError(f"device error: {stats}")
+    del c, tmp
+    torch.cuda.empty_cache()
+    return sorted(times)[len(times) // 2]
+
+
 def time_sorts(src, n, R, K, steps, warm, verify, roof=None):
     """Sort `steps` resident copies of src (after `warm` untimed sorts), first
     with the library's profile events around every kernel class (the phase
@@ -387,6 +412,26 @@ def bench_batch(args) -> dict:
         if rep:
             times.append(t)
     t_batched = sorted(times)[len(times) // 2]
+    # the same call captured once in a HIP graph and replayed (how a serving
+    # loop issues it)
+    gs = torch.cuda.Stream()
+    with torch.cuda.stream(gs):
+        bt.launch(stream=gs)  # (kernel attributes are set outside the capture)
+    gs.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gs):
+        bt.launch(stream=gs)
+    gtimes = []
+    for rep in range(1 + args.batch_reps):
+        fill_batch(recs, starts, sizes)
+        t = ev_time(graph.replay)
+        st, stats = bt.check()
+        if st != b.OK:
+            raise RuntimeError(f"batched sort (graph): device error {stats}")
+        if rep:
+            gtimes.append(t)
+    t_graph = sorted(gtimes)[len(gtimes) // 2]
+    del graph
     rng = np.random.default_rng(0)
     for j in rng.choice(count, size=min(48, count), replace=False):
         a, n = int(starts[j]), int(sizes[j])
@@ -421,6 +466,7 @@ def bench_batch(args) -> dict:
                     "uint64 key uniform, uint64 payload = index",
         "arrays": count, "records": total,
         "batched_ms": round(t_batched * 1e3, 3), "batched_records_per_s": total / t_batched,
+        "batched_graph_ms": round(t_graph * 1e3, 3), "batched_graph_records_per_s": total / t_graph,
         "plain_ms": round(t_plain * 1e3, 3), "plain_records_per_s": total / t_plain,
         "batched_vs_plain": t_plain / t_batched,
     }
@@ -429,44 +475,64 @@ def bench_batch(args) -> dict:
         budget = min(args.serve_budget_gib << 30, total * R)
         be = serve.GpuBackend(R, K, n_streams=3, max_batch=2048, max_records=budget // R)
         views = [recs[int(starts[j]):int(starts[j]) + int(sizes[j])] for j in range(nreq)]
-        served_records = int(sizes[:nreq].sum())
         import gc
-        for mode, rho in (("closed", None), ("poisson", args.serve_load)):
+
+        def serve_run(rate, many=True):
+            """Serve the first nreq arrays: all at t = 0 (rate None; in one
+            submit_many call, or one submit per array if not `many`) or as a
+            Poisson stream of `rate` requests per second from an open-loop
+            client that submits every request whose arrival time has come,
+            one submit each."""
             fill_batch(recs, starts, sizes)
-            torch.cuda.synchronize()
+            torch.cuda.synchronize()  # (so the requests are submitted with ready=False)
             # Python's cyclic collector would stop both the client and the
             # server thread for up to ~0.15 s at a time while tens of
             # thousands of requests are alive; a latency-sensitive client
             # turns it off while it serves
             gc.collect()
             gc.disable()
-            srv = serve.Server(be, R, budget, max_slots=4096).start()
+            srv = serve.Server(be, R, budget, max_slots=be.n_streams * be.max_batch).start()
             futs = []
             t0 = time.perf_counter()
-            if rho is None:
+            if rate is None and many:
+                futs = srv.submit_many(views, ready=False)
+            elif rate is None:
                 for v in views:
-                    futs.append(srv.submit(v))
+                    futs.append(srv.submit(v, ready=False))
             else:
-                rate = rho * (total / t_plain) / (served_records / nreq)  # requests per second
-                gaps = np.random.default_rng(7).exponential(1.0 / rate, size=nreq)
-                t_next = t0
-                for v, g in zip(views, gaps):
-                    t_next += g
-                    wait = t_next - time.perf_counter()
-                    if wait > 0:
-                        time.sleep(wait)  # releases the GIL to the scheduler thread
-                    futs.append(srv.submit(v, t_arrival=t_next))
+                sched = t0 + np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, size=nreq))
+                i = 0
+                while i < nreq:
+                    now = time.perf_counter()
+                    while i < nreq and sched[i] <= now:
+                        futs.append(srv.submit(views[i], t_arrival=float(sched[i]), ready=False))
+                        i += 1
+                    if i < nreq:
+                        wait = sched[i] - time.perf_counter()
+                        if wait > 0:
+                            time.sleep(wait)  # releases the GIL to the scheduler thread
             for f in futs:
                 f.result(timeout=600)
             summ = srv.stop()
             gc.enable()
             summ["wall_s"] = time.perf_counter() - t0
-            if rho is not None:
-                summ["arrival_rate_req_s"] = rate
-                summ["load_vs_plain"] = rho
-            log(f"[serve] {mode}: {summ}")
-            out["served_" + mode] = {k: (round(v, 4) if isinstance(v, float) else v)
-                                     for k, v in summ.items()}
+            return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+
+        closed = serve_run(None)
+        log(f"[serve] closed: {closed}")
+        out["served_closed"] = closed
+        closed1 = serve_run(None, many=False)
+        log(f"[serve] closed, one submit per request: {closed1}")
+        out["served_closed_per_request"] = closed1
+        cap_rate = closed["requests"] / closed["span_s"]  # requests per second the server sustains
+        loads = []
+        for rho in args.serve_loads:
+            s = serve_run(rho * cap_rate)
+            s["load_vs_closed"] = rho
+            s["arrival_rate_req_s"] = round(rho * cap_rate, 1)
+            log(f"[serve] load {rho}: {s}")
+            loads.append(s)
+        out["served_load"] = loads
         rng = np.random.default_rng(1)
         for j in rng.choice(nreq, size=min(32, nreq), replace=False):
             a, n = int(starts[j]), int(sizes[j])
@@ -586,13 +652,17 @@ def main() -> int:
     ap.add_argument("--cpu-par-log2", type=int, default=None,
                     help="all-cores oracle sample, 2^k records (default: the whole input up to 2^28)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", choices=["cache", "defaults"], default="cache",
+                    help="cache: the autotuner's entry for this workload and shape, if any "
+                         "(the library defaults are timed beside it); defaults: none")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--batch-count", type=int, default=65536)
     ap.add_argument("--batch-log2max", type=int, default=20)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-requests", type=int, default=65536)
-    ap.add_argument("--serve-load", type=float, default=0.9,
-                    help="Poisson arrival rate as a fraction of the plain per-call throughput")
+    ap.add_argument("--serve-loads", type=float, nargs="*", default=[0.25, 0.5, 0.75, 0.9],
+                    help="Poisson arrival rates as fractions of the rate the server sustains "
+                         "with every request present at once")
     ap.add_argument("--serve-budget-gib", type=int, default=32)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched / served comparison (run only with uniform16)")
@@ -622,8 +692,27 @@ def main() -> int:
     src = wl.make_torch(name, n, device=dev)
     torch.cuda.synchronize()
     pass_bytes = 2 * n * R
+    from paper_1703_00687_amd import autotune
+    from paper_1703_00687_amd import binding as b
+    defaults = b.raduls_get_tuning()
+    tune_key, tune_entry = (None, None)
+    if args.tuning == "cache":
+        tune_key, tune_entry = autotune.apply(R, K, n, name)
+    log(f"[bench] tuning: {tune_key or 'library defaults'}"
+        + (f" {tune_entry['tuning']}" if tune_entry else ""))
     ms_per_step, roof, roof_ms, phases, stats, verified = time_sorts(
         src, n, R, K, steps, warm, not args.no_verify)
+    tuning = {"source": tune_key or "library defaults"}
+    if tune_entry is not None:
+        # the same plain timing with the tuned setting and with the defaults
+        tuned_ms = plain_ms(src, n, R, K, max(steps, 3))
+        b.raduls_set_tuning(**defaults)
+        default_ms = plain_ms(src, n, R, K, max(steps, 3))
+        tuning.update({"knobs": tune_entry["tuning"], "changed": tune_entry.get("changed"),
+                       "tuned_ms": round(tuned_ms, 4), "default_ms": round(default_ms, 4),
+                       "tuned_beats_defaults": tuned_ms < default_ms})
+        log(f"[bench] tuned {tuned_ms:.3f} ms, library defaults {default_ms:.3f} ms")
+    b.raduls_set_tuning(**defaults)  # the other legs run the library defaults
     achieved = pass_bytes / (roof_ms * 1e-3) / 1e9
     traffic = load_traffic(name, n, R, roof)
     rw, kw = R // 8, (K + 7) // 8
@@ -704,6 +793,7 @@ def main() -> int:
         "device_copy_gbs": round(copy_gbs, 1),
         "stats": stats,
         "verified": verified,
+        "tuning": tuning,
         "batched": batched,
     }
     if sweep is not None:

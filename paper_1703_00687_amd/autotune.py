@@ -23,16 +23,21 @@ DEFAULT_CACHE = os.environ.get(
 
 SPACE = {
     "digit_bits": [8, 7, 6],
-    "tiny_max": [16, 32, 64, 128],
+    "tile_items": [0, 5, 4, 3, 2],      # records per thread of a scatter tile (0: the most)
+    "tiny_max": [64, 32, 16, 128],
     "mid_frac": [1.0, 0.75, 0.5],       # mid_max as a fraction of the LDS capacity
+    "wave_job_max": [0, 128, 64, 1],    # largest wave-network job (0: the most, 1: none)
     "nontemporal": [1, 2],
     "lookback": [0, 1],
     "pair_hist": [1, 2],
 }
 
 
-def shape_key(arch: str, rec_bytes: int, key_bytes: int, n: int) -> str:
-    return f"{arch}/R{rec_bytes}/K{key_bytes}/n2^{max(0, int(round(math.log2(max(n, 1)))))}"
+def shape_key(arch: str, rec_bytes: int, key_bytes: int, n: int, workload: str | None = None) -> str:
+    """Cache key of a call shape; `workload` names the key distribution the
+    entry was tuned on (inputs of one shape can want different settings)."""
+    k = f"{arch}/R{rec_bytes}/K{key_bytes}/n2^{max(0, int(round(math.log2(max(n, 1)))))}"
+    return f"{k}/{workload}" if workload else k
 
 
 def _arch() -> str:
@@ -49,22 +54,37 @@ def load_cache(path: str = DEFAULT_CACHE) -> dict:
         return {}
 
 
-def apply(rec_bytes: int, key_bytes: int, n: int, path: str = DEFAULT_CACHE) -> dict | None:
-    """Set the process-global tuning from the cache entry for this shape (the
-    nearest record count with the same R and K); returns it, or None."""
-    cache = load_cache(path)
-    prefix = f"{_arch()}/R{rec_bytes}/K{key_bytes}/n2^"
-    best, dist = None, None
+def lookup(cache: dict, arch: str, rec_bytes: int, key_bytes: int, n: int,
+           workload: str | None = None):
+    """(key, entry) of the cache entry for this shape, or (None, None): the
+    same arch, R and K; an entry tuned on `workload` first, then one with no
+    workload named; among those the nearest record count.  Entries tuned on
+    another distribution are not used."""
+    prefix = f"{arch}/R{rec_bytes}/K{key_bytes}/n2^"
     want = math.log2(max(n, 1))
+    best = None
     for k, v in cache.items():
-        if k.startswith(prefix):
-            d = abs(int(k[len(prefix):]) - want)
-            if dist is None or d < dist:
-                best, dist = v, d
-    if best is None:
-        return None
-    b.raduls_set_tuning(**best["tuning"])
-    return best
+        if not k.startswith(prefix):
+            continue
+        rest = k[len(prefix):].split("/", 1)
+        wl_name = rest[1] if len(rest) > 1 else None
+        if wl_name is not None and wl_name != workload:
+            continue
+        score = (wl_name is None, abs(int(rest[0]) - want))
+        if best is None or score < best[0]:
+            best = (score, k, v)
+    return (None, None) if best is None else (best[1], best[2])
+
+
+def apply(rec_bytes: int, key_bytes: int, n: int, workload: str | None = None,
+          path: str = DEFAULT_CACHE):
+    """Set the process-global tuning from the cache entry for this shape
+    (see lookup); returns (key, entry), or (None, None) with the tuning
+    left as it was."""
+    key, entry = lookup(load_cache(path), _arch(), rec_bytes, key_bytes, n, workload)
+    if entry is not None:
+        b.raduls_set_tuning(**entry["tuning"])
+    return key, entry
 
 
 def _time_sort(src, copies, tmp, n, R, K, reps):
@@ -119,8 +139,8 @@ def _looks_sorted(out, src, key_bytes: int) -> bool:
     return bool(le.all())
 
 
-def tune(src, key_bytes: int, reps: int = 3, space: dict | None = None, budget_s: float = 300.0,
-         path: str | None = DEFAULT_CACHE, log=print) -> dict:
+def tune(src, key_bytes: int, reps: int = 5, space: dict | None = None, budget_s: float = 300.0,
+         path: str | None = DEFAULT_CACHE, log=print, workload: str | None = None) -> dict:
     """Search the space for the [n, R] uint8 device tensor `src` (left
     unchanged).  Coordinate descent from the defaults: one knob at a time over
     its values, keeping the best, repeated while it improves and time lasts."""
@@ -136,7 +156,8 @@ def tune(src, key_bytes: int, reps: int = 3, space: dict | None = None, budget_s
         return {"digit_bits": c["digit_bits"], "tiny_max": c["tiny_max"],
                 "mid_max": max(64, int(cap * c["mid_frac"]) // 64 * 64),
                 "nontemporal": c["nontemporal"], "lookback": c["lookback"],
-                "pair_hist": c.get("pair_hist", 1), "grid_blocks": 0}
+                "pair_hist": c.get("pair_hist", 1), "grid_blocks": 0,
+                "tile_items": c.get("tile_items", 0), "wave_job_max": c.get("wave_job_max", 0)}
 
     def measure(c):
         t = cand_to_tuning(c)
@@ -150,6 +171,7 @@ def tune(src, key_bytes: int, reps: int = 3, space: dict | None = None, budget_s
 
     cur = {k: v[0] for k, v in space.items()}
     best_ms = measure(cur)
+    default_ms = best_ms  # the first value of every knob is its default
     log(f"[autotune] start {cur} {best_ms:.3f} ms")
     improved = True
     while improved and time.perf_counter() - t_start < budget_s:
@@ -164,7 +186,9 @@ def tune(src, key_bytes: int, reps: int = 3, space: dict | None = None, budget_s
                 if ms < best_ms * 0.99:
                     best_ms, cur, improved = ms, c, True
     best = {"tuning": cand_to_tuning(cur), "ms": best_ms, "n": n,
-            "records_per_s": n / (best_ms * 1e-3)}
+            "records_per_s": n / (best_ms * 1e-3), "default_ms": default_ms,
+            "changed": {k: v for k, v in cur.items() if v != space[k][0]},
+            "workload": workload}
     # the winner must sort: no device error, keys non-decreasing and the
     # record words' sum and xor unchanged
     b.raduls_set_tuning(**best["tuning"])
@@ -178,7 +202,7 @@ def tune(src, key_bytes: int, reps: int = 3, space: dict | None = None, budget_s
         raise RuntimeError(f"autotune: the winning setting {best['tuning']} did not sort ({stats})")
     if path:
         cache = load_cache(path)
-        cache[shape_key(_arch(), R, key_bytes, n)] = best
+        cache[shape_key(_arch(), R, key_bytes, n, workload)] = best
         with open(path, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     b.raduls_set_tuning(**prev)
@@ -189,11 +213,18 @@ if __name__ == "__main__":
     import argparse
     import torch
     from . import workloads as wl
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="uniform16")
-    ap.add_argument("--log2n", type=int, default=26)
+    ap = argparse.ArgumentParser(description="tune the sort for workloads at their full sizes")
+    ap.add_argument("--workloads", nargs="+", default=["uniform16", "zipf16", "deep32"])
+    ap.add_argument("--log2n", type=int, default=None, help="records = 2^k (default: the workload's)")
     ap.add_argument("--budget-s", type=float, default=240)
     args = ap.parse_args()
-    host, k = wl.make(args.workload, 1 << args.log2n)
-    src = torch.from_numpy(host).cuda()
-    print(json.dumps(tune(src, k, budget_s=args.budget_s)))
+    for name in args.workloads:
+        spec = wl.WORKLOADS[name]
+        n = spec["n"] if args.log2n is None else 1 << args.log2n
+        src = wl.make_torch(name, n, device=torch.device("cuda:0"))
+        torch.cuda.synchronize()
+        best = tune(src, spec["key_bytes"], budget_s=args.budget_s, workload=name,
+                    log=lambda m: print(m, flush=True))
+        print(json.dumps({name: best}), flush=True)
+        del src
+        torch.cuda.empty_cache()

@@ -11,6 +11,24 @@ from paper_1703_00687_amd import workloads as wl
 def test_shape_key():
     assert at.shape_key("gfx950", 16, 8, 1 << 28) == "gfx950/R16/K8/n2^28"
     assert at.shape_key("gfx950", 32, 16, 3) == "gfx950/R32/K16/n2^2"
+    assert at.shape_key("gfx950", 16, 8, 1 << 28, "zipf16") == "gfx950/R16/K8/n2^28/zipf16"
+
+
+def test_lookup_prefers_the_workload_then_the_nearest_size():
+    cache = {"gfx950/R16/K8/n2^28/uniform16": {"tuning": {"tiny_max": 1}},
+             "gfx950/R16/K8/n2^28/zipf16": {"tuning": {"tiny_max": 2}},
+             "gfx950/R16/K8/n2^24": {"tuning": {"tiny_max": 3}},
+             "gfx950/R32/K16/n2^27/deep32": {"tuning": {"tiny_max": 4}},
+             "gfx942/R16/K8/n2^28/zipf16": {"tuning": {"tiny_max": 5}}}
+    k, e = at.lookup(cache, "gfx950", 16, 8, 1 << 27, "zipf16")
+    assert k == "gfx950/R16/K8/n2^28/zipf16" and e["tuning"]["tiny_max"] == 2
+    # no entry for this distribution: the one tuned on none, never another's
+    k, e = at.lookup(cache, "gfx950", 16, 8, 1 << 28, "keys16")
+    assert k == "gfx950/R16/K8/n2^24"
+    k, e = at.lookup(cache, "gfx950", 32, 16, 1 << 27, "uniform32")
+    assert k is None and e is None
+    k, e = at.lookup(cache, "gfx950", 32, 16, 1 << 20, "deep32")
+    assert k == "gfx950/R32/K16/n2^27/deep32"
 
 
 @pytest.mark.parametrize("r,k", [(16, 8), (32, 16), (16, 5)])
