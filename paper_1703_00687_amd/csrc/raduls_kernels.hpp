@@ -1362,6 +1362,35 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
 
 // ------------------------------------------------------------ round: classify
 
+constexpr uint32_t kNoChild = 0xFFFFu;
+
+// Highest set bit below position i of a 256-bit mask held as four words, or -1.
+__device__ __forceinline__ int mask_prev256(const uint64_t* m, uint32_t i) {
+  int w = int(i >> 6);
+  uint64_t x = m[w] & ((1ull << (i & 63u)) - 1ull);
+  while (!x) {
+    if (--w < 0) return -1;
+    x = m[w];
+  }
+  return (w << 6) + 63 - __clzll(x);
+}
+
+// Lowest set bit above position i of a 256-bit mask, or n if there is none
+// below n.
+__device__ __forceinline__ uint32_t mask_next256(const uint64_t* m, uint32_t i, uint32_t n) {
+  const uint32_t q = i + 1;
+  if (q >= 256u) return n;
+  uint32_t w = q >> 6;
+  uint64_t x = m[w] & (~0ull << (q & 63u));
+  while (!x) {
+    if (++w >= 4u) return n;
+    x = m[w];
+  }
+  const uint32_t r = (w << 6) + uint32_t(__builtin_ctzll(x));
+  return r < n ? r : n;
+}
+
+
 // Decide what happens to each large bin after the round (Sec. 3.1-3.3): all
 // keys equal -> finished; digit constant -> same bin, next differing digit;
 // otherwise its children become next-round large bins or LDS jobs.  Small
@@ -1370,7 +1399,9 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
 template <int KW>
 __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32_t round) {
   __shared__ uint32_t s_cnt[kRadix], s_off[kRadix], s_scan[8];
-  __shared__ uint32_t s_js[kRadix], s_jn[kRadix], s_jr[kRadix], s_nj, s_jbase, s_tbase;
+  __shared__ uint32_t s_px[kRadix + 1], s_jmp[kRadix], s_st[kRadix], s_wt[4], s_wm[4];
+  __shared__ uint32_t s_jbase, s_tbase;
+  __shared__ uint64_t s_bm[4], s_sm[4];
   Ctrl* c = P.L.ctrl;
   const uint32_t nbins = min(c->large_count[cur], P.L.cap_large);
   const uint32_t nxt = cur ^ 1;
@@ -1450,86 +1481,98 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32
     }
     // no child small enough for a sort job (the usual case at the top level)
     if (!__syncthreads_or(tid < nb && h > 0 && h <= P.mid_max && !eq_done)) continue;
-    // greedy packing of the small children into jobs, in digit order: every
-    // wave runs the same branch-free scalar loop, lane l holding the counts
-    // and offsets of digits 4l..4l+3 (read out with readlane, so the loop
-    // waits on no memory; with branches it took ~0.2 us per digit).  Thread
-    // 0 writes the job being built to entry nj of the job table; nj advances
-    // when a job is complete, so the entry is rewritten until then.  Then one reservation in each job
-    // list (jobs of at most tiny_job records go to the tiny-job list) and a
-    // parallel write of the descriptors.
+    // Greedy packing of the small children into jobs, in digit order: a job
+    // closes before a child that would take it past mid_max records and at
+    // every child too large for a job (the finished equal part of an
+    // equality split counts as one).  The scan is sequential by nature (a
+    // loop over the digits took ~35 us per bin); it is computed in parallel
+    // instead.  Every small child finds by binary search over the prefix
+    // sums of the small children where a job starting at it would end and
+    // which child would start the next job; the job starts -- the children
+    // reached by those jumps from the first small child after each large
+    // one -- are marked by pointer doubling (eight steps cover 256
+    // children).  The jobs are the same as the loop's.
     {
-      const uint32_t lane = tid & (kWave - 1);
       const uint32_t M = P.mid_max;
-      int cq[4], oq[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t d = 4 * lane + q;
-        // (the finished equal part of an equality split counts as a large
-        // child: it ends the job before it and joins none)
-        cq[q] = d < nb ? int((eqb && d == 1 && s_cnt[d]) ? M + 1 : s_cnt[d]) : 0;
-        oq[q] = d < nb ? int(s_off[d]) : 0;
+      const uint32_t lane = tid & (kWave - 1), wave = tid >> 6;
+      const uint32_t cd = tid < nb ? ((eqb && tid == 1 && s_cnt[1]) ? M + 1 : s_cnt[tid]) : 0u;
+      const bool big = cd > M;
+      const bool small = cd != 0 && !big;
+      const uint64_t bmask = __ballot(big), smask = __ballot(small);
+      if (lane == 0) {
+        s_bm[wave] = bmask;
+        s_sm[wave] = smask;
+      }
+      // s_px[i]: records of the small children before child i (s_px[256]: all)
+      block_exclusive_scan256(small ? cd : 0u, s_px, s_scan);
+      if (tid == kRadix - 1) s_px[kRadix] = s_px[tid] + (small ? cd : 0u);
+      lds_barrier();
+      uint32_t jn = 0, nxt_start = kNoChild;
+      bool root = false;
+      if (small) {
+        const uint32_t i = tid;
+        const uint32_t nbig = mask_next256(s_bm, i, nb);  // first large child after i, or nb
+        const int pbig = mask_prev256(s_bm, i), psmall = mask_prev256(s_sm, i);
+        root = psmall < 0 || psmall < pbig;
+        // first m in [i+2, nb] with s_px[m] > s_px[i] + M: child m-1 would
+        // take a job starting at i past M (child i alone never does)
+        const uint64_t lim = uint64_t(s_px[i]) + M;
+        uint32_t lo = i + 2, hi = nb + 1;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (uint64_t(s_px[mid]) > lim) hi = mid;
+          else lo = mid + 1;
+        }
+        const uint32_t k = lo <= nb ? lo - 1 : nb;  // next job's first child, or nb
+        const uint32_t end = k < nbig ? k : nbig;
+        jn = s_px[end] - s_px[i];
+        nxt_start = k < nbig ? k : kNoChild;
+      }
+      s_jmp[tid] = nxt_start;
+      s_st[tid] = root ? 1u : 0u;
+      bool more = __syncthreads_or(nxt_start != kNoChild);
+      while (more) {  // at most eight rounds: chains are shorter than 256
+        const uint32_t j = s_jmp[tid];
+        const uint32_t st = s_st[tid];
+        const uint32_t jj = j != kNoChild ? s_jmp[j] : kNoChild;
+        lds_barrier();
+        if (st && j != kNoChild) s_st[j] = 1u;
+        s_jmp[tid] = jj;
+        more = __syncthreads_or(jj != kNoChild);
       }
       // (a lone record in recs is in place)
-      const uint32_t lone_moves = __builtin_amdgcn_readfirstlane(uint32_t(cside)) != 0 ? 1u : 0u;
-      uint32_t js = 0, jn = 0, nj = 0, nm = 0, nt = 0;
-      // (every write lands below kRadix: a job is complete only once a later
-      // child or the final call closes it, and its entry is written before
-      // nj advances past it)
-      // (flags as 0/1 integers combined with bitwise operators, so that the
-      // compiler selects instead of branching)
-      auto add = [&](uint32_t cd, uint32_t od) {
-        const uint32_t big = cd > M ? 1u : 0u;
-        const uint32_t small = (cd != 0 ? 1u : 0u) & (big ^ 1u);
-        const uint32_t cut = big | (small & (jn + cd > M ? 1u : 0u));  // the job ends before this child
-        const uint32_t done = cut & (jn > 0 ? 1u : 0u) & ((jn > 1 ? 1u : 0u) | lone_moves);
-        const uint32_t tj = jn <= P.tiny_job ? 1u : 0u;
-        if (tid == 0) {  // (one lane: many lanes writing one LDS word serialize)
-          s_js[nj] = js;
-          s_jn[nj] = jn;
-          s_jr[nj] = tj ? (0x80000000u | nt) : nm;
-        }
-        nt += done & tj;
-        nm += done & (tj ^ 1u);
-        nj += done;
-        jn = cut ? 0u : jn;
-        js = (small & (jn == 0 ? 1u : 0u)) ? od : js;
-        jn += small ? cd : 0u;
-      };
-      const uint32_t nl = (nb + 3) / 4;
-      // the LDS reads and scalar loads above complete here, so that the
-      // compiler's wait for them is not placed at the head of the loop (where
-      // it would wait for the loop's own LDS writes on every iteration)
-      __builtin_amdgcn_s_waitcnt(0xC07F);  // gfx9 encoding: lgkmcnt(0) only
-      for (uint32_t l = 0; l < nl; ++l) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          add(uint32_t(__builtin_amdgcn_readlane(cq[q], int(l))),
-              uint32_t(__builtin_amdgcn_readlane(oq[q], int(l))));
+      const bool emit = small && s_st[tid] && (jn > 1 || cside != 0);
+      const bool tj = jn <= P.tiny_job;
+      const uint64_t tball = __ballot(emit && tj), mball = __ballot(emit && !tj);
+      if (lane == 0) {
+        s_wt[wave] = uint32_t(__popcll(tball));
+        s_wm[wave] = uint32_t(__popcll(mball));
       }
-      add(M + 1, 0);  // closes the last job
+      lds_barrier();
       if (tid == 0) {
-        s_nj = nj;
-        s_jbase = nm ? atomicAdd(&c->mid_count, nm) : 0u;
+        const uint32_t nt = s_wt[0] + s_wt[1] + s_wt[2] + s_wt[3];
+        const uint32_t nm = s_wm[0] + s_wm[1] + s_wm[2] + s_wm[3];
         s_tbase = nt ? atomicAdd(&c->tiny_count, nt) : 0u;
+        s_jbase = nm ? atomicAdd(&c->mid_count, nm) : 0u;
       }
-    }
-    __syncthreads();
-    if (tid < s_nj) {
-      const uint32_t r = s_jr[tid];
-      const bool tiny = (r >> 31) != 0;
-      const uint32_t i = (tiny ? s_tbase : s_jbase) + (r & 0x7FFFFFFFu);
-      if (i < P.L.cap_mid) {
-        const ArrayDesc a = P.L.arrays[bin.array];
-        const uint64_t st = uint64_t(bin.start) + s_js[tid];
-        MidJob j;
-        j.src = (cside ? a.tmp : a.recs) + st * P.R;
-        j.dst = a.recs + st * P.R;
-        j.size = s_jn[tid];
-        j.pad[0] = j.pad[1] = j.pad[2] = 0;
-        (tiny ? P.L.tiny : P.L.mid)[i] = j;
-      } else {
-        atomicOr(&c->error, kErrCapacity);
+      lds_barrier();
+      if (emit) {
+        uint32_t before = 0;
+        for (uint32_t w = 0; w < wave; ++w) before += tj ? s_wt[w] : s_wm[w];
+        const uint64_t mine = tj ? tball : mball;
+        const uint32_t i = (tj ? s_tbase : s_jbase) + before + uint32_t(__popcll(mine & lanemask_lt()));
+        if (i < P.L.cap_mid) {
+          const ArrayDesc a = P.L.arrays[bin.array];
+          const uint64_t st = uint64_t(bin.start) + s_off[tid];
+          MidJob j;
+          j.src = (cside ? a.tmp : a.recs) + st * P.R;
+          j.dst = a.recs + st * P.R;
+          j.size = jn;
+          j.pad[0] = j.pad[1] = j.pad[2] = 0;
+          (tj ? P.L.tiny : P.L.mid)[i] = j;
+        } else {
+          atomicOr(&c->error, kErrCapacity);
+        }
       }
     }
   }
