@@ -52,7 +52,10 @@ typedef enum raduls_status {
   RADULS_E_UNSUPPORTED = -4, /* R not a multiple of 8 in [8, 64], or n >= 2^32 */
   RADULS_E_HIP = -5,         /* a HIP runtime call or kernel launch failed */
   RADULS_E_DEVICE = -6,      /* raduls_check(): the device recorded an error */
-  RADULS_E_SCRATCH = -7      /* raduls_sort_static: n needs more than the static workspace */
+  RADULS_E_SCRATCH = -7,     /* raduls_sort_static: n needs more than the static workspace */
+  RADULS_E_BUSY = -8,        /* server: the ring slot of the next request is still in use */
+  RADULS_E_STOPPED = -9,     /* server: its kernel has left (stopped or idle too long) */
+  RADULS_E_TIMEOUT = -10     /* server: raduls_server_wait gave up */
 } raduls_status;
 
 /* Tuning knobs (process-global; set them before enqueuing sorts, never while
@@ -243,6 +246,55 @@ int raduls_set_profile_events(hipEvent_t *events, uint32_t count);
 /* Largest mid_max (records) the LDS sorter supports for records of R bytes
  * with K key bytes (0 for an unsupported shape). */
 uint32_t raduls_mid_capacity(uint32_t rec_bytes, uint32_t key_bytes);
+
+/* ---- Resident server: small arrays sorted without a launch per request.
+ *
+ * Paper: Sec. 3.2 sorts a small bin with one thread in the processor's cache
+ * and Sec. 3.3 tiny bins in registers; a request of at most
+ * raduls_server_max_records records is that case as a whole: one workgroup
+ * sorts it in LDS.  raduls_server_create launches `workgroups` workgroups
+ * of the LDS sorter (0: an eighth of the CUs) that stay resident on a stream
+ * of the server's own and take requests from a submission ring of `slots`
+ * entries in host-pinned memory: the host writes a request and publishes it;
+ * the first free workgroup claims it, sorts it in place (stable, the same
+ * result as raduls_sort) and publishes its completion.  The workgroups
+ * occupy their CUs while the server lives; the other CUs stay free for other
+ * work.
+ *
+ * Ownership and contracts:
+ *   - create allocates the ring (pinned host memory), a small device state
+ *     and the stream; destroy frees them.  No other server call allocates.
+ *   - submit: `recs` is a device pointer to n <= max_records records of the
+ *     server's R and K, written and visible on the device before the call
+ *     (e.g. its producer's stream synchronized); the caller keeps it alive
+ *     and does not touch it until the request completes.  It returns at once
+ *     with a ticket (0, 1, 2, ... in submission order).  RADULS_E_BUSY: the
+ *     ring slot the request needs still holds an uncompleted request from
+ *     `slots` submissions ago (retry after a completion);
+ *     RADULS_E_UNSUPPORTED: n > max_records; RADULS_E_STOPPED: the kernel
+ *     has left.  One submitter at a time is safe (calls are serialized).
+ *   - poll returns 1 once the request's sorted records are visible to the
+ *     host and to work enqueued afterwards (*status: 0, or the device's
+ *     error bits), 0 while pending, RADULS_E_STOPPED if the kernel left
+ *     without completing it.  Poll a ticket before `slots` later submissions
+ *     reuse its slot, or its status reads 0.  wait polls until done or
+ *     `timeout_ms` (then RADULS_E_TIMEOUT).
+ *   - Every wait of the kernel is bounded: a workgroup leaves when destroy
+ *     sets the ring's stop word, or after `idle_ms` (0: 10 s; at most 10
+ *     minutes) without a request; a server whose kernel has left serves no
+ *     more requests (info: running 0, reason 1 stopped / 2 idle).
+ *   - destroy stops the kernel (requests being sorted finish; queued ones
+ *     are not started), waits for it to leave and frees everything. */
+typedef struct raduls_server raduls_server;
+int raduls_server_max_records(uint32_t rec_bytes, uint32_t key_bytes, uint64_t *out_records);
+int raduls_server_create(uint32_t rec_bytes, uint32_t key_bytes, uint32_t slots,
+                         uint32_t workgroups, uint32_t idle_ms, raduls_server **out);
+int raduls_server_submit(raduls_server *srv, void *recs, uint64_t n, uint64_t *ticket);
+int raduls_server_poll(raduls_server *srv, uint64_t ticket, uint32_t *status);
+int raduls_server_wait(raduls_server *srv, uint64_t ticket, uint32_t timeout_ms, uint32_t *status);
+int raduls_server_info(raduls_server *srv, uint64_t *max_records, uint32_t *workgroups,
+                       uint32_t *running, uint32_t *reason);
+int raduls_server_destroy(raduls_server *srv);
 
 const char *raduls_strerror(int status);
 

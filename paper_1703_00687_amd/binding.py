@@ -25,6 +25,9 @@ E_UNSUPPORTED = -4
 E_HIP = -5
 E_DEVICE = -6
 E_SCRATCH = -7
+E_BUSY = -8
+E_STOPPED = -9
+E_TIMEOUT = -10
 
 
 class RadulsError(RuntimeError):
@@ -109,6 +112,14 @@ def load() -> ctypes.CDLL:
         "raduls_inspect_rounds": (i32, [vp, vp, u64, u32, u32, u32, ctypes.POINTER(raduls_bin), u32,
                                         ctypes.POINTER(ctypes.c_uint32), vp]),
         "raduls_set_profile_events": (i32, [ctypes.POINTER(ctypes.c_void_p), u32]),
+        "raduls_server_max_records": (i32, [u32, u32, u64p]),
+        "raduls_server_create": (i32, [u32, u32, u32, u32, u32, ctypes.POINTER(vp)]),
+        "raduls_server_submit": (i32, [vp, vp, u64, u64p]),
+        "raduls_server_poll": (i32, [vp, u64, ctypes.POINTER(ctypes.c_uint32)]),
+        "raduls_server_wait": (i32, [vp, u64, u32, ctypes.POINTER(ctypes.c_uint32)]),
+        "raduls_server_info": (i32, [vp, u64p, ctypes.POINTER(ctypes.c_uint32),
+                                     ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
+        "raduls_server_destroy": (i32, [vp]),
         "raduls_strerror": (ctypes.c_char_p, [i32]),
     }
     for name, (res, args) in sig.items():
@@ -126,6 +137,8 @@ def exported_symbols() -> list[str]:
         "raduls_set_tuning", "raduls_get_tuning", "raduls_mid_capacity", "raduls_strerror",
         "raduls_inspect_rounds", "raduls_sort_static",
         "raduls_set_profile_events",
+        "raduls_server_max_records", "raduls_server_create", "raduls_server_submit",
+        "raduls_server_poll", "raduls_server_wait", "raduls_server_info", "raduls_server_destroy",
     ]
 
 
@@ -274,6 +287,82 @@ def raduls_inspect_rounds(recs, tmp, n: int, rec_bytes: int, key_bytes: int, rou
            "raduls_inspect_rounds")
     k = min(int(cnt.value), cap)
     return [(arr[i].start, arr[i].size, arr[i].bits, arr[i].side, arr[i].flags) for i in range(k)]
+
+
+def raduls_server_max_records(rec_bytes: int, key_bytes: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check(load().raduls_server_max_records(rec_bytes, key_bytes, ctypes.byref(out)),
+           "raduls_server_max_records")
+    return int(out.value)
+
+
+class ResidentServer:
+    """The resident server of raduls.h: `workgroups` workgroups of the LDS
+    sorter stay on the device and sort submitted arrays of at most
+    ``max_records`` records in place, with no launch per request.  Use as a
+    context manager (or call ``close``); ``submit`` returns a ticket that
+    ``poll`` / ``wait`` take."""
+
+    def __init__(self, rec_bytes: int, key_bytes: int, slots: int = 4096, workgroups: int = 0,
+                 idle_ms: int = 0):
+        self.rec_bytes, self.key_bytes = rec_bytes, key_bytes
+        h = ctypes.c_void_p()
+        _check(load().raduls_server_create(rec_bytes, key_bytes, slots, workgroups, idle_ms,
+                                           ctypes.byref(h)), "raduls_server_create")
+        self._h = h
+        self.max_records, self.workgroups, _, _ = self.info()
+
+    def info(self) -> tuple[int, int, bool, int]:
+        """(max_records, workgroups, running, reason: 0, 1 stopped, 2 idle)."""
+        m, w, r, why = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(load().raduls_server_info(self._h, ctypes.byref(m), ctypes.byref(w), ctypes.byref(r),
+                                         ctypes.byref(why)), "raduls_server_info")
+        return int(m.value), int(w.value), bool(r.value), int(why.value)
+
+    def submit_status(self, recs, n: int | None = None) -> tuple[int, int]:
+        """(status, ticket): the raw result of raduls_server_submit."""
+        if n is None:
+            n = int(recs.shape[0])
+        t = ctypes.c_uint64(0)
+        st = load().raduls_server_submit(self._h, _ptr(recs) if n else None, n, ctypes.byref(t))
+        return st, int(t.value)
+
+    def submit(self, recs, n: int | None = None) -> int:
+        st, t = self.submit_status(recs, n)
+        _check(st, "raduls_server_submit")
+        return t
+
+    def poll(self, ticket: int) -> tuple[int, int]:
+        """(1 done / 0 pending / negative status, device error bits)."""
+        s = ctypes.c_uint32(0)
+        r = load().raduls_server_poll(self._h, ticket, ctypes.byref(s))
+        return int(r), int(s.value)
+
+    def wait(self, ticket: int, timeout_ms: int = 10000) -> int:
+        """Wait for the request; returns its device error bits (0: sorted)."""
+        s = ctypes.c_uint32(0)
+        r = load().raduls_server_wait(self._h, ticket, timeout_ms, ctypes.byref(s))
+        if r < 0:
+            raise RadulsError(r, "raduls_server_wait")
+        return int(s.value)
+
+    def close(self) -> None:
+        if self._h:
+            h, self._h = self._h, None
+            _check(load().raduls_server_destroy(h), "raduls_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def raduls_strerror(status: int) -> str:

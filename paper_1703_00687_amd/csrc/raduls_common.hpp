@@ -192,6 +192,43 @@ struct Ctrl {
   unsigned long long batch_total;
 };
 
+// ---- resident server: requests of at most mid_max records, each sorted in
+// place by one workgroup of a kernel that stays resident until stopped.
+// The submission ring lives in host-pinned memory: the host fills a slot and
+// then publishes it by writing its sequence word; the device writes the
+// slot's completion word once the request is sorted and visible.
+constexpr uint32_t kServeMaxSlots = 1u << 20;
+constexpr uint32_t kServeMaxIdleMs = 600000;     // 10 minutes
+constexpr uint32_t kServeDefaultIdleMs = 10000;  // idle_ms = 0
+
+struct ServeSlot {
+  uint64_t seq;     // host: ticket + 1 once recs and n are written
+  uint64_t recs;    // device address of the request's [n, R] records
+  uint64_t n;       // records (<= mid_max)
+  uint64_t done;    // device: ticket + 1 once the sorted records are visible
+  uint32_t status;  // device: error bits of the request (0: sorted)
+  uint32_t pad[7];
+};
+static_assert(sizeof(ServeSlot) == 64, "one slot per 64-byte line");
+
+struct ServeRing {
+  uint64_t stop;      // host: non-zero asks every workgroup to exit
+  uint64_t pad0[7];
+  uint32_t reason;    // device: why the last workgroup to leave left (1 stop, 2 idle)
+  uint32_t pad1[15];
+  ServeSlot slot[1];  // [slots] (allocated past the struct's end)
+};
+
+// Device-memory state of a server: the dispatch lock (one workgroup at a
+// time reads the ring), the next ticket to hand out, and per workgroup the
+// error bits of the request it is sorting.
+struct ServeState {
+  uint32_t lock;
+  uint32_t pad;
+  uint64_t next;
+  uint64_t pad1[6];
+};
+
 // Device pointers into the auxiliary workspace.
 struct Layout {
   Ctrl* ctrl;
@@ -250,6 +287,12 @@ struct Params {
   // launch shapes
   uint32_t grid_hist, grid_scatter, grid_classify, grid_mid, grid_copy, grid_tiny;
   uint32_t mid_lds_bytes, scatter_lds_bytes;
+  // resident server
+  ServeRing* ring;          // device address of the host-pinned ring
+  ServeState* serve;        // device memory
+  Ctrl* serve_ctrl;         // [workgroups] error bits of each workgroup's request
+  uint32_t serve_slots;
+  uint64_t serve_idle;      // ticks of the 100 MHz constant clock a workgroup waits idle
 };
 
 __host__ __device__ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }

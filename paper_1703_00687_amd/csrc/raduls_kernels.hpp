@@ -2189,6 +2189,80 @@ __device__ __forceinline__ void mid_wave_sort_bucket(const MidLds& L, uint32_t s
   if (lane < cn) L.perm[st + rk] = uint16_t(sv);
 }
 
+// ------------------------------------------------------------ resident server
+
+// Claim the next request of a resident server (all threads call; the result
+// is uniform).  Thread 0 waits for a published ring slot: it takes the
+// dispatch lock (one workgroup at a time reads the host ring), reads the slot
+// of the next ticket with an acquire at system scope (which also makes the
+// request's input, written before it was submitted, visible here), advances
+// the ticket and drops the lock.  It gives up when the host sets the stop
+// word or after P.serve_idle ticks of the 100 MHz clock without a request;
+// every wait of the server is bounded that way.  Returns false to exit.
+__device__ __forceinline__ bool serve_claim(const Params& P, MidJob& job, uint64_t& ticket) {
+  __shared__ uint64_t s_t, s_recs, s_n;
+  __shared__ uint32_t s_got;
+  if (threadIdx.x == 0) {
+    uint32_t got = 0;
+    const uint64_t t0 = wall_clock64();
+    uint32_t spins = 0;
+    for (;;) {
+      if (__hip_atomic_load(&P.ring->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+        __hip_atomic_store(&P.ring->reason, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        break;
+      }
+      if (__hip_atomic_load(&P.serve->lock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+        uint32_t expect = 0u;
+        if (__hip_atomic_compare_exchange_strong(&P.serve->lock, &expect, 1u, __ATOMIC_ACQUIRE,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          const uint64_t t = __hip_atomic_load(&P.serve->next, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+          ServeSlot* sl = &P.ring->slot[t % P.serve_slots];
+          if (__hip_atomic_load(&sl->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == t + 1) {
+            s_recs = __hip_atomic_load(&sl->recs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            s_n = __hip_atomic_load(&sl->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            s_t = t;
+            __hip_atomic_store(&P.serve->next, t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            got = 1;
+          }
+          __hip_atomic_store(&P.serve->lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          if (got) break;
+        }
+      }
+      if (wall_clock64() - t0 > P.serve_idle) {
+        __hip_atomic_store(&P.ring->reason, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        break;
+      }
+      // short naps while requests are coming, longer ones when idle
+      if (++spins < 256) __builtin_amdgcn_s_sleep(2);
+      else __builtin_amdgcn_s_sleep(60);
+    }
+    s_got = got;
+  }
+  __syncthreads();
+  if (!s_got) return false;
+  ticket = s_t;
+  job.src = job.dst = reinterpret_cast<uint8_t*>(s_recs);
+  job.size = uint32_t(s_n);
+  job.pad[0] = job.pad[1] = job.pad[2] = 0;
+  return true;
+}
+
+// Publish a server request's completion (all threads call, after the job's
+// stores): every thread's stores are made visible at system scope, then
+// thread 0 writes the slot's status (the workgroup's error bits, cleared for
+// the next request) and, with a release, its completion word.
+__device__ __forceinline__ void serve_complete(const Params& P, Ctrl* c, uint64_t ticket) {
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ServeSlot* sl = &P.ring->slot[ticket % P.serve_slots];
+    const uint32_t err = atomicExch(&c->error, 0u);
+    __hip_atomic_store(&sl->status, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&sl->done, ticket + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // Sorts jobs of at most mid_max records entirely in LDS (the small-bin case of
 // Sec. 3.2, with LDS in the role of the cache).  A job's records are read from
 // HBM once and kept in LDS in input order; every pass permutes a 16-bit slot
@@ -2210,7 +2284,11 @@ __device__ __forceinline__ void mid_wave_sort_bucket(const MidLds& L, uint32_t s
 // records of job i+1 travel into registers (they are loaded before job i's
 // stores are issued, so waiting for them never waits for those stores), the
 // descriptor of job i+2 is on its way and the claim for job i+3 is made.
-template <int RW, int KW>
+//
+// SERVE = 1 is the resident server: no job list and no pipelining; each
+// workgroup claims one request at a time from the submission ring (waiting
+// for it, bounded), sorts it in place and publishes its completion.
+template <int RW, int KW, int SERVE = 0>
 __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
   constexpr int W = kMidWaves;
   constexpr int WI = mid_wave_items(RW);
@@ -2259,19 +2337,24 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
   L.scan = s_scan;
   L.diff = s_diff;
 
-  Ctrl* c = P.L.ctrl;
-  const uint32_t njobs = min(c->mid_count, P.L.cap_mid);
+  Ctrl* c = SERVE ? P.serve_ctrl + blockIdx.x : P.L.ctrl;
+  const uint32_t njobs = SERVE ? 0u : min(c->mid_count, P.L.cap_mid);
   const uint32_t tiny = P.tiny_max;
   const uint32_t wave_cap = kWave * WI;
   const uint32_t G = gridDim.x;
-  if (blockIdx.x >= njobs) return;
-
-  MidJob job = P.L.mid[blockIdx.x];  // job i
+  MidJob job{};  // job i
+  uint64_t ticket = 0;  // (server) the request being sorted
+  if constexpr (SERVE) {
+    if (!serve_claim(P, job, ticket)) return;
+  } else {
+    if (blockIdx.x >= njobs) return;
+    job = P.L.mid[blockIdx.x];
+  }
   uint64_t kr[ITEMS][RW] = {}, key0[KW];
   mid_fetch<RW, KW, ITEMS>(job.src, job.size <= T ? job.size : 0u, threadIdx.x, kr, key0);
   if (threadIdx.x == 0) {
-    s_next = G + atomicAdd(&c->mid_claim, 1u);
-    s_next2 = G + atomicAdd(&c->mid_claim, 1u);
+    s_next = SERVE ? 0u : G + atomicAdd(&c->mid_claim, 1u);
+    s_next2 = SERVE ? 0u : G + atomicAdd(&c->mid_claim, 1u);
     s_hb[0] = 0;
     s_hb[1] = 0;
     s_flag[0] = 0;
@@ -2660,6 +2743,13 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
       if (bad) atomicOr(&c->error, kErrBounds);
     }
     lds_barrier();  // the records are rewritten by the next job
+    if constexpr (SERVE) {
+      serve_complete(P, c, ticket);
+      if (!serve_claim(P, job, ticket)) break;
+      mid_fetch<RW, KW, ITEMS>(job.src, job.size <= T ? job.size : 0u, threadIdx.x, kr, key0);
+      __builtin_amdgcn_s_waitcnt(0);
+      continue;
+    }
     if (!have1) break;
     job = nxt;
     nxt = nxt2;
@@ -3019,6 +3109,37 @@ hipError_t run_rw(const Params& P, uint32_t kw, hipStream_t s) {
 #define RADULS_KW_CASE(N) \
   case N:                 \
     if constexpr (N <= RW) return run_sequence<RW, N>(P, s); \
+    break;
+    RADULS_KW_CASE(1)
+    RADULS_KW_CASE(2)
+    RADULS_KW_CASE(3)
+    RADULS_KW_CASE(4)
+    RADULS_KW_CASE(5)
+    RADULS_KW_CASE(6)
+    RADULS_KW_CASE(7)
+    RADULS_KW_CASE(8)
+#undef RADULS_KW_CASE
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+// The resident server's launch: `wgs` workgroups of the LDS sorter in server
+// mode, which stay until the ring's stop word is set or they idle out.
+template <int RW, int KW>
+hipError_t serve_launch(const Params& P, uint32_t wgs, hipStream_t s) {
+  set_lds_limit<k_mid<RW, KW, 1>>(P.mid_lds_bytes);
+  k_mid<RW, KW, 1><<<wgs, kMidBlock, P.mid_lds_bytes, s>>>(P);
+  return hipGetLastError();
+}
+
+template <int RW>
+hipError_t serve_rw(const Params& P, uint32_t kw, uint32_t wgs, hipStream_t s) {
+  switch (kw) {
+#define RADULS_KW_CASE(N) \
+  case N:                 \
+    if constexpr (N <= RW) return serve_launch<RW, N>(P, wgs, s); \
     break;
     RADULS_KW_CASE(1)
     RADULS_KW_CASE(2)

@@ -2,6 +2,9 @@
 // layout, tuning, launch shapes.  Never allocates, frees or synchronizes in
 // the sort calls.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <thread>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -24,6 +27,14 @@ hipError_t run_rw5(const Params&, uint32_t, hipStream_t);
 hipError_t run_rw6(const Params&, uint32_t, hipStream_t);
 hipError_t run_rw7(const Params&, uint32_t, hipStream_t);
 hipError_t run_rw8(const Params&, uint32_t, hipStream_t);
+hipError_t serve_rw1(const Params&, uint32_t, uint32_t, hipStream_t);
+hipError_t serve_rw2(const Params&, uint32_t, uint32_t, hipStream_t);
+hipError_t serve_rw3(const Params&, uint32_t, uint32_t, hipStream_t);
+hipError_t serve_rw4(const Params&, uint32_t, uint32_t, hipStream_t);
+hipError_t serve_rw5(const Params&, uint32_t, uint32_t, hipStream_t);
+hipError_t serve_rw6(const Params&, uint32_t, uint32_t, hipStream_t);
+hipError_t serve_rw7(const Params&, uint32_t, uint32_t, hipStream_t);
+hipError_t serve_rw8(const Params&, uint32_t, uint32_t, hipStream_t);
 
 namespace {
 
@@ -300,6 +311,56 @@ int static_scratch(void** out) {
   return RADULS_OK;
 }
 
+hipError_t serve_launch_rw(const Params& P, uint32_t R, uint32_t K, uint32_t wgs, hipStream_t s) {
+  const uint32_t kw = (K + 7) / 8;
+  switch (R / 8) {
+    case 1: return serve_rw1(P, kw, wgs, s);
+    case 2: return serve_rw2(P, kw, wgs, s);
+    case 3: return serve_rw3(P, kw, wgs, s);
+    case 4: return serve_rw4(P, kw, wgs, s);
+    case 5: return serve_rw5(P, kw, wgs, s);
+    case 6: return serve_rw6(P, kw, wgs, s);
+    case 7: return serve_rw7(P, kw, wgs, s);
+    case 8: return serve_rw8(P, kw, wgs, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+}  // namespace raduls
+
+// A resident server: its ring (host-pinned), device state, own stream and
+// the kernel running there.
+struct raduls_server {
+  uint32_t R = 0, K = 0, slots = 0, wgs = 0;
+  uint64_t cap = 0;                          // records per request
+  raduls::ServeRing* ring = nullptr;         // host address
+  void* dmem = nullptr;                      // ServeState + Ctrl[wgs]
+  hipStream_t stream = nullptr;
+  std::atomic<uint64_t> next{0};             // next ticket
+  std::atomic<bool> exited{false};           // the kernel has left
+  std::mutex mu;                             // submitters
+};
+
+namespace raduls {
+namespace {
+
+bool server_running(raduls_server* s) {
+  if (s->exited.load(std::memory_order_acquire)) return false;
+  const hipError_t q = hipStreamQuery(s->stream);
+  if (q == hipErrorNotReady) return true;
+  if (q != hipSuccess) (void)hipGetLastError();
+  s->exited.store(true, std::memory_order_release);
+  return false;
+}
+
+void server_free(raduls_server* s) {
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->dmem) (void)hipFree(s->dmem);
+  if (s->ring) (void)hipHostFree(s->ring);
+  delete s;
+}
+
 }  // namespace
 }  // namespace raduls
 
@@ -556,6 +617,141 @@ uint32_t raduls_mid_capacity(uint32_t rec_bytes, uint32_t key_bytes) {
   return mid_capacity(rec_bytes / 8, (key_bytes + 7) / 8);
 }
 
+int raduls_server_max_records(uint32_t rec_bytes, uint32_t key_bytes, uint64_t* out_records) {
+  int st = check_shape(rec_bytes, key_bytes);
+  if (st) return st;
+  if (!out_records) return RADULS_E_INVALID;
+  *out_records = effective(current_tuning(), rec_bytes, key_bytes).mid_max;
+  return RADULS_OK;
+}
+
+int raduls_server_create(uint32_t rec_bytes, uint32_t key_bytes, uint32_t slots,
+                         uint32_t workgroups, uint32_t idle_ms, raduls_server** out) {
+  int st = check_shape(rec_bytes, key_bytes);
+  if (st) return st;
+  if (!out || slots == 0 || slots > kServeMaxSlots || idle_ms > kServeMaxIdleMs)
+    return RADULS_E_INVALID;
+  *out = nullptr;
+  const uint32_t cus = uint32_t(device_info().cus);
+  const uint32_t wgs = std::min(workgroups ? workgroups : std::max(1u, cus / 8), cus);
+  const Eff e = effective(current_tuning(), rec_bytes, key_bytes);
+  raduls_server* s = new raduls_server;
+  s->R = rec_bytes;
+  s->K = key_bytes;
+  s->slots = slots;
+  s->wgs = wgs;
+  s->cap = e.mid_max;
+  const size_t ring_bytes = sizeof(ServeRing) + size_t(slots - 1) * sizeof(ServeSlot);
+  const size_t dev_bytes = sizeof(ServeState) + size_t(wgs) * sizeof(Ctrl);
+  void* dring = nullptr;
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->ring), ring_bytes,
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer(&dring, s->ring, 0) != hipSuccess ||
+      hipMalloc(&s->dmem, dev_bytes) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    server_free(s);
+    return RADULS_E_HIP;
+  }
+  std::memset(s->ring, 0, ring_bytes);
+  if (hipMemsetAsync(s->dmem, 0, dev_bytes, s->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    server_free(s);
+    return RADULS_E_HIP;
+  }
+  Params P{};
+  P.R = rec_bytes;
+  P.K = key_bytes;
+  const uint32_t top = key_bytes - 8 * ((key_bytes - 1) / 8);
+  P.kmask = top == 8 ? ~0ull : ((1ull << (8 * top)) - 1);
+  P.tiny_job = e.wave_job;
+  P.es_job = e.es_job;
+  P.tiny_max = e.tiny_max;
+  P.mid_max = e.mid_max;
+  P.mid_lds_bytes = mid_dynamic_lds(mid_capacity(rec_bytes / 8, (key_bytes + 7) / 8),
+                                    int(rec_bytes / 8));
+  P.ring = static_cast<ServeRing*>(dring);
+  P.serve = static_cast<ServeState*>(s->dmem);
+  P.serve_ctrl = reinterpret_cast<Ctrl*>(static_cast<uint8_t*>(s->dmem) + sizeof(ServeState));
+  P.serve_slots = slots;
+  P.serve_idle = uint64_t(idle_ms ? idle_ms : kServeDefaultIdleMs) * 100000ull;  // 100 MHz ticks
+  if (serve_launch_rw(P, rec_bytes, key_bytes, wgs, s->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(s->stream);
+    server_free(s);
+    return RADULS_E_HIP;
+  }
+  *out = s;
+  return RADULS_OK;
+}
+
+int raduls_server_submit(raduls_server* s, void* recs, uint64_t n, uint64_t* ticket) {
+  if (!s || !ticket || (n && !recs)) return RADULS_E_INVALID;
+  if (n > s->cap) return RADULS_E_UNSUPPORTED;
+  if (recs && misaligned(recs)) return RADULS_E_ALIGN;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (!server_running(s)) return RADULS_E_STOPPED;
+  const uint64_t t = s->next.load(std::memory_order_relaxed);
+  ServeSlot& sl = s->ring->slot[t % s->slots];
+  // the slot's previous request must have completed
+  if (t >= s->slots && __atomic_load_n(&sl.done, __ATOMIC_ACQUIRE) != t - s->slots + 1)
+    return RADULS_E_BUSY;
+  sl.recs = reinterpret_cast<uint64_t>(recs);
+  sl.n = n;
+  sl.status = 0;
+  __atomic_store_n(&sl.seq, t + 1, __ATOMIC_RELEASE);  // publish
+  s->next.store(t + 1, std::memory_order_release);
+  *ticket = t;
+  return RADULS_OK;
+}
+
+int raduls_server_poll(raduls_server* s, uint64_t ticket, uint32_t* status) {
+  if (!s || ticket >= s->next.load(std::memory_order_acquire)) return RADULS_E_INVALID;
+  const ServeSlot& sl = s->ring->slot[ticket % s->slots];
+  const uint64_t d = __atomic_load_n(&sl.done, __ATOMIC_ACQUIRE);
+  if (d >= ticket + 1) {  // (larger: the slot has served a later request since)
+    if (status) *status = d == ticket + 1 ? __atomic_load_n(&sl.status, __ATOMIC_RELAXED) : 0u;
+    return 1;
+  }
+  if (!server_running(s)) {
+    // the kernel may have completed the request just before leaving
+    if (__atomic_load_n(&sl.done, __ATOMIC_ACQUIRE) >= ticket + 1) return raduls_server_poll(s, ticket, status);
+    return RADULS_E_STOPPED;
+  }
+  return 0;
+}
+
+int raduls_server_wait(raduls_server* s, uint64_t ticket, uint32_t timeout_ms, uint32_t* status) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t k = 0;; ++k) {
+    const int r = raduls_server_poll(s, ticket, status);
+    if (r != 0) return r;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(timeout_ms))
+      return RADULS_E_TIMEOUT;
+    if (k > 64) std::this_thread::yield();
+  }
+}
+
+int raduls_server_info(raduls_server* s, uint64_t* max_records, uint32_t* workgroups,
+                       uint32_t* running, uint32_t* reason) {
+  if (!s) return RADULS_E_INVALID;
+  if (max_records) *max_records = s->cap;
+  if (workgroups) *workgroups = s->wgs;
+  if (running) *running = server_running(s) ? 1u : 0u;
+  if (reason) *reason = __atomic_load_n(&s->ring->reason, __ATOMIC_ACQUIRE);
+  return RADULS_OK;
+}
+
+int raduls_server_destroy(raduls_server* s) {
+  if (!s) return RADULS_E_INVALID;
+  __atomic_store_n(&s->ring->stop, 1ull, __ATOMIC_RELEASE);
+  // every wait of the kernel checks the stop word, so it leaves after the
+  // requests it is sorting
+  const hipError_t e = hipStreamSynchronize(s->stream);
+  server_free(s);
+  return e == hipSuccess ? RADULS_OK : RADULS_E_HIP;
+}
+
 const char* raduls_strerror(int status) {
   switch (status) {
     case RADULS_OK: return "ok";
@@ -566,6 +762,9 @@ const char* raduls_strerror(int status) {
     case RADULS_E_HIP: return "HIP runtime error";
     case RADULS_E_DEVICE: return "device reported an error";
     case RADULS_E_SCRATCH: return "the static workspace is too small for this many records";
+    case RADULS_E_BUSY: return "the server's ring slot for the next request is still in use";
+    case RADULS_E_STOPPED: return "the resident server has stopped";
+    case RADULS_E_TIMEOUT: return "the request did not complete in time";
     default: return "unknown status";
   }
 }

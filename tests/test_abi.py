@@ -119,7 +119,7 @@ def test_tuning_roundtrip_and_rejects():
 
 def test_strerror():
     for st in (b.OK, b.E_INVALID, b.E_ALIGN, b.E_TMP_SMALL, b.E_UNSUPPORTED, b.E_HIP, b.E_DEVICE,
-               b.E_SCRATCH):
+               b.E_SCRATCH, b.E_BUSY, b.E_STOPPED, b.E_TIMEOUT):
         assert b.strerror(st) and b.strerror(st) != "unknown status"
 
 
@@ -156,3 +156,33 @@ def test_struct_layouts_match_the_header(tmp_path):
             b.raduls_stats.moved_records.offset, b.raduls_stats.pair_rounds.offset,
             ctypes.sizeof(b.raduls_array), ctypes.sizeof(b.raduls_bin), b.raduls_bin.flags.offset]
     assert got == want
+
+
+def test_server_argument_errors_on_host():
+    """Resident-server calls that fail before touching the device."""
+    import ctypes
+    lib = b.load()
+    h = ctypes.c_void_p()
+    assert lib.raduls_server_create(12, 8, 64, 1, 100, ctypes.byref(h)) == b.E_UNSUPPORTED
+    assert lib.raduls_server_create(16, 17, 64, 1, 100, ctypes.byref(h)) == b.E_INVALID
+    assert lib.raduls_server_create(16, 8, 0, 1, 100, ctypes.byref(h)) == b.E_INVALID
+    assert lib.raduls_server_create(16, 8, (1 << 20) + 1, 1, 100, ctypes.byref(h)) == b.E_INVALID
+    assert lib.raduls_server_create(16, 8, 64, 1, 600001, ctypes.byref(h)) == b.E_INVALID
+    assert lib.raduls_server_create(16, 8, 64, 1, 100, None) == b.E_INVALID
+    t = ctypes.c_uint64()
+    st = ctypes.c_uint32()
+    assert lib.raduls_server_submit(None, None, 0, ctypes.byref(t)) == b.E_INVALID
+    assert lib.raduls_server_poll(None, 0, ctypes.byref(st)) == b.E_INVALID
+    assert lib.raduls_server_wait(None, 0, 1, ctypes.byref(st)) == b.E_INVALID
+    assert lib.raduls_server_info(None, None, None, None, None) == b.E_INVALID
+    assert lib.raduls_server_destroy(None) == b.E_INVALID
+
+
+def test_server_max_records_is_the_lds_capacity():
+    for r, k in ((8, 8), (16, 8), (32, 16), (64, 64)):
+        assert b.raduls_server_max_records(r, k) == b.raduls_mid_capacity(r, k)
+    prev = b.raduls_set_tuning(mid_max=1000)
+    try:
+        assert b.raduls_server_max_records(16, 8) == 1000
+    finally:
+        b.raduls_set_tuning(**prev)

@@ -1,0 +1,149 @@
+"""The resident server (raduls_server_* in raduls.h): requests sorted by
+workgroups that stay on the device, checked against the oracle alone and,
+in a mix with plain calls running meanwhile, against the plain call's bytes;
+and its host-side contracts (oversize, alignment, busy slots, the idle limit,
+stop)."""
+
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1703_00687_amd import binding as b
+from paper_1703_00687_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+IDLE_MS = 30000  # every test's server leaves by itself within this if a test breaks
+
+
+def _device(h: np.ndarray) -> torch.Tensor:
+    t = torch.empty(h.shape, dtype=torch.uint8, device=DEV)
+    if h.size:
+        t.copy_(torch.from_numpy(h))
+    return t
+
+
+@pytest.mark.parametrize("r,k", [(16, 8), (8, 8), (32, 16), (16, 16), (24, 5)])
+def test_server_alone_matches_oracle(r, k):
+    cap = b.raduls_server_max_records(r, k)
+    sizes = [n for n in (0, 1, 2, 3, 17, 64, 65, 255, 256, 257, 1000, 3000) if n < cap]
+    sizes += [cap - 1, cap]
+    rng = np.random.default_rng(r * 100 + k)
+    hosts = [wl.random_records(rng, n, r, k, distinct_keys=max(1, n // 3)) for n in sizes]
+    devs = [_device(h) for h in hosts]
+    torch.cuda.synchronize()  # inputs written before they are submitted
+    with b.ResidentServer(r, k, slots=64, workgroups=4, idle_ms=IDLE_MS) as srv:
+        assert srv.max_records == cap
+        tickets = [srv.submit(d) for d in devs]
+        assert tickets == list(range(len(sizes)))
+        for t in tickets:
+            assert srv.wait(t) == 0
+        for h, d in zip(hosts, devs):
+            got = d.cpu().numpy()
+            assert np.array_equal(got, oracle.sort(h, k)), (r, k, h.shape)
+        _, _, running, _ = srv.info()
+        assert running
+
+
+def test_server_in_mix_matches_plain_calls():
+    """Requests of random sizes through a ring of 32 slots (so slots are
+    reused many times) while plain raduls_sort calls run on the default
+    stream; every served array equals the plain call's output on a copy."""
+    r, k = 16, 8
+    cap = b.raduls_server_max_records(r, k)
+    rng = np.random.default_rng(5)
+    count = 400
+    sizes = rng.integers(0, cap + 1, size=count)
+    sizes[:8] = [0, 1, 2, cap, cap, 64, 65, 256]
+    hosts = [wl.random_records(rng, int(n), r, k, distinct_keys=max(1, int(n) // 2)) for n in sizes]
+    served = [_device(h) for h in hosts]
+    plain = [d.clone() for d in served]
+    # plain calls on other arrays keep the rest of the GPU busy meanwhile
+    other = _device(wl.random_records(rng, 1 << 20, r, k))
+    tmp_other = torch.empty(b.raduls_tmp_bytes(1 << 20, r, k), dtype=torch.uint8, device=DEV)
+    torch.cuda.synchronize()
+    with b.ResidentServer(r, k, slots=32, workgroups=8, idle_ms=IDLE_MS) as srv:
+        tickets = []
+        for i, d in enumerate(served):
+            if i % 50 == 0:
+                b.raduls_sort(other, tmp_other, 1 << 20, r, k)
+            while True:
+                st, t = srv.submit_status(d)
+                if st == b.OK:
+                    tickets.append(t)
+                    break
+                assert st == b.E_BUSY, b.strerror(st)
+                # the slot's previous request is still being sorted
+                assert srv.wait(tickets[-32]) == 0
+        for t in tickets:
+            assert srv.wait(t) == 0
+    torch.cuda.synchronize()
+    for d, n in zip(plain, sizes):
+        if n > 1:
+            tmp = torch.empty(b.raduls_tmp_bytes(int(n), r, k), dtype=torch.uint8, device=DEV)
+            b.raduls_sort(d, tmp, int(n), r, k)
+    torch.cuda.synchronize()
+    for i, (s, p) in enumerate(zip(served, plain)):
+        assert torch.equal(s, p), (i, int(sizes[i]))
+    # and a sample against the oracle
+    for i in rng.choice(count, size=12, replace=False):
+        assert np.array_equal(served[i].cpu().numpy(), oracle.sort(hosts[i], k))
+
+
+def test_server_rejects_oversize_and_misaligned():
+    r, k = 16, 8
+    cap = b.raduls_server_max_records(r, k)
+    buf = torch.zeros((cap + 2) * r + 64, dtype=torch.uint8, device=DEV)
+    with b.ResidentServer(r, k, slots=8, workgroups=1, idle_ms=IDLE_MS) as srv:
+        assert srv.submit_status(buf, cap + 1)[0] == b.E_UNSUPPORTED
+        assert srv.submit_status(buf.data_ptr() + 8, 10)[0] == b.E_ALIGN
+        assert srv.submit_status(None, 5)[0] == b.E_INVALID
+        # nothing was queued by the refused calls: the next ticket is 0
+        t = srv.submit(buf, 3)
+        assert t == 0 and srv.wait(t) == 0
+
+
+def test_server_busy_slot_then_free():
+    r, k = 16, 8
+    h = wl.random_records(np.random.default_rng(9), 3000, r, k)
+    d = _device(h)
+    e = _device(h)
+    torch.cuda.synchronize()
+    with b.ResidentServer(r, k, slots=1, workgroups=1, idle_ms=IDLE_MS) as srv:
+        t0 = srv.submit(d)
+        st, t1 = srv.submit_status(e)
+        # the one slot is free again only once request 0 has completed
+        assert st in (b.OK, b.E_BUSY)
+        assert srv.wait(t0) == 0
+        if st == b.E_BUSY:
+            t1 = srv.submit(e)
+        assert t1 == 1 and srv.wait(t1) == 0
+    expect = oracle.sort(h, k)
+    assert np.array_equal(d.cpu().numpy(), expect) and np.array_equal(e.cpu().numpy(), expect)
+
+
+def test_server_idle_limit_ends_the_kernel():
+    r, k = 16, 8
+    srv = b.ResidentServer(r, k, slots=8, workgroups=2, idle_ms=50)
+    try:
+        deadline = time.time() + 20
+        while srv.info()[2] and time.time() < deadline:
+            time.sleep(0.05)
+        _, _, running, reason = srv.info()
+        assert not running and reason == 2
+        buf = torch.zeros(64 * r, dtype=torch.uint8, device=DEV)
+        assert srv.submit_status(buf, 64)[0] == b.E_STOPPED
+    finally:
+        srv.close()
+
+
+def test_server_stop_is_prompt():
+    r, k = 8, 8
+    srv = b.ResidentServer(r, k, slots=8, workgroups=16, idle_ms=IDLE_MS)
+    time.sleep(0.05)
+    t = time.perf_counter()
+    srv.close()
+    assert time.perf_counter() - t < 2.0
