@@ -544,6 +544,124 @@ def bench_batch(args) -> dict:
     return out
 
 
+def bench_resident(args) -> dict:
+    """Small arrays (1 to the LDS capacity records, log-uniform sizes, uniform
+    keys, 16 B records) sorted by the resident server, against the two ways
+    of sorting them without it: one plain call per array and one batched
+    call over all of them.  Latency: one request at a time (submit, then
+    wait on the host; plain: the call, then a synchronize of its stream).
+    Throughput: every array submitted at once (submit_many) and waited for,
+    against the batched call."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1703_00687_amd import binding as b
+    from paper_1703_00687_amd import workloads as wl
+
+    R, K = 16, 8
+    cap = b.raduls_server_max_records(R, K)
+    count = args.resident_count
+    rng = np.random.default_rng(11)
+    sizes = np.exp(rng.uniform(0.0, np.log(cap), size=count)).astype(np.int64).clip(1, cap)
+    starts = np.zeros(count, dtype=np.int64)
+    starts[1:] = np.cumsum(sizes)[:-1]
+    total = int(sizes.sum())
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    src = wl.sweep_records_torch(total, R, K, device=dev)
+    recs = torch.empty_like(src)
+    ptrs = (recs.data_ptr() + starts * R).astype(np.uint64)
+    log(f"[resident] {count} arrays of 1..{cap} records (log-uniform), {total} records")
+
+    def refill():
+        recs.copy_(src)
+        stream.synchronize()  # (a device-wide synchronize would wait for the server)
+
+    sample = np.linspace(0, count - 1, num=min(512, count)).astype(np.int64)
+    # one plain call per array, each waited for
+    tmp = torch.empty(b.raduls_tmp_bytes(cap, R, K), dtype=torch.uint8, device=dev)
+    refill()
+    lat_plain = []
+    for j in sample:
+        a, n = int(starts[j]), int(sizes[j])
+        t0 = time.perf_counter()
+        b.raduls_sort(recs[a:a + n], tmp, n, R, K)
+        stream.synchronize()
+        lat_plain.append(time.perf_counter() - t0)
+    # one batched call over every array
+    bt = b.Batch(count, total, R, K, device=dev)
+    btmp = torch.empty_like(src)
+    h = bt.host_desc.numpy()
+    h[:, 0] = ptrs.astype(np.int64)
+    h[:, 1] = btmp.data_ptr() + starts * R
+    h[:, 2] = sizes
+    bt.desc.copy_(bt.host_desc)
+    bms = []
+    for rep in range(4):
+        refill()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        bt.launch()
+        e1.record()
+        e1.synchronize()
+        if rep:
+            bms.append(e0.elapsed_time(e1))
+    st, stats = bt.check()
+    if st != b.OK:
+        raise RuntimeError(f"batched small arrays: device error {stats}")
+    batched_ms = sorted(bms)[len(bms) // 2]
+    del bt, btmp
+
+    def pct(v, p):
+        v = sorted(v)
+        return v[min(len(v) - 1, int(round(p / 100 * (len(v) - 1))))] * 1e6
+
+    out = {"workload": f"{count} arrays of 16 B records, sizes log-uniform in [1, {cap}], "
+                       "uint64 keys uniform",
+           "arrays": count, "records": total, "max_records": cap,
+           "plain_latency_us": {"p50": round(pct(lat_plain, 50), 1), "p99": round(pct(lat_plain, 99), 1)},
+           "batched_ms": round(batched_ms, 4),
+           "batched_records_per_s": total / (batched_ms * 1e-3),
+           "servers": []}
+    for wgs in args.resident_wgs:
+        with b.ResidentServer(R, K, slots=max(count, 1024), workgroups=wgs, idle_ms=60000) as srv:
+            refill()
+            lat = []
+            for j in sample:
+                t0 = time.perf_counter()
+                t = srv.submit(int(ptrs[j]), int(sizes[j]))
+                if srv.wait(t) != 0:
+                    raise RuntimeError("resident server: device error")
+                lat.append(time.perf_counter() - t0)
+            runs = []
+            for rep in range(3):
+                refill()
+                t0 = time.perf_counter()
+                first, acc = srv.submit_many(ptrs, sizes)
+                if acc != count:
+                    raise RuntimeError(f"resident server accepted {acc} of {count}")
+                if srv.wait_range(first, count) != 0:
+                    raise RuntimeError("resident server: device error")
+                runs.append(time.perf_counter() - t0)
+            wall = sorted(runs)[len(runs) // 2]
+            # the last run's output against the oracle, for a sample of arrays
+            for j in sample[:: max(1, len(sample) // 24)]:
+                a, n = int(starts[j]), int(sizes[j])
+                if not np.array_equal(recs[a:a + n].cpu().numpy(),
+                                      oracle.sort(src[a:a + n].cpu().numpy(), K)):
+                    raise RuntimeError(f"resident server: array {j} differs from the oracle")
+            r = {"workgroups": srv.workgroups,
+                 "latency_us": {"p50": round(pct(lat, 50), 1), "p99": round(pct(lat, 99), 1)},
+                 "closed_ms": round(wall * 1e3, 3),
+                 "closed_records_per_s": total / wall, "closed_requests_per_s": count / wall,
+                 "verified": True}
+            log(f"[resident] {r}")
+            out["servers"].append(r)
+    log(f"[resident] plain latency {out['plain_latency_us']}, batched {batched_ms:.3f} ms")
+    del recs, src, tmp
+    return out
+
+
 TINY_SIZES = [2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 1024, 4096]
 # The small-array sorters compared per record layout (the GPU counterpart of
 # the paper's comparison of tiny-bin sorters by record layout, Sec. 4.1):
@@ -666,6 +784,11 @@ def main() -> int:
     ap.add_argument("--serve-budget-gib", type=int, default=32)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched / served comparison (run only with uniform16)")
+    ap.add_argument("--no-resident", action="store_true",
+                    help="skip the resident-server comparison (run only with uniform16)")
+    ap.add_argument("--resident-count", type=int, default=16384)
+    ap.add_argument("--resident-wgs", type=int, nargs="+", default=[32, 64, 128],
+                    help="workgroups of the resident server, one run each")
     ap.add_argument("--rec-sweep", action="store_true",
                     help="also sort records of 8-64 B with 8/16 B keys (2^--sweep-log2 each)")
     ap.add_argument("--sweep-log2", type=int, default=28)
@@ -754,6 +877,9 @@ def main() -> int:
     batched = None
     if not args.no_batch and name == "uniform16":
         batched = bench_batch(args)
+    resident = None
+    if not args.no_resident and name == "uniform16":
+        resident = bench_resident(args)
     sweep = None
     if args.rec_sweep:
         sweep = rec_sweep(args.sweep_log2, not args.no_verify)
@@ -795,6 +921,7 @@ def main() -> int:
         "verified": verified,
         "tuning": tuning,
         "batched": batched,
+        "resident": resident,
     }
     if sweep is not None:
         line["rec_sweep"] = sweep

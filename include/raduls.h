@@ -290,8 +290,20 @@ int raduls_server_max_records(uint32_t rec_bytes, uint32_t key_bytes, uint64_t *
 int raduls_server_create(uint32_t rec_bytes, uint32_t key_bytes, uint32_t slots,
                          uint32_t workgroups, uint32_t idle_ms, raduls_server **out);
 int raduls_server_submit(raduls_server *srv, void *recs, uint64_t n, uint64_t *ticket);
+/* submit_many: requests recs[i] of n[i] records, i < count, in order, with
+ * tickets *first_ticket, *first_ticket + 1, ...; stops early (without error)
+ * at the first request whose ring slot is still in use and reports in
+ * *accepted how many were submitted.  Arguments are checked for all of them
+ * before any is submitted. */
+int raduls_server_submit_many(raduls_server *srv, void *const *recs, const uint64_t *n,
+                              uint32_t count, uint64_t *first_ticket, uint32_t *accepted);
 int raduls_server_poll(raduls_server *srv, uint64_t ticket, uint32_t *status);
 int raduls_server_wait(raduls_server *srv, uint64_t ticket, uint32_t timeout_ms, uint32_t *status);
+/* wait_range: waits for tickets [first, first + count) (all submitted);
+ * *status_or is the OR of their status words.  RADULS_OK, RADULS_E_TIMEOUT,
+ * RADULS_E_STOPPED or RADULS_E_INVALID. */
+int raduls_server_wait_range(raduls_server *srv, uint64_t first, uint64_t count,
+                             uint32_t timeout_ms, uint32_t *status_or);
 int raduls_server_info(raduls_server *srv, uint64_t *max_records, uint32_t *workgroups,
                        uint32_t *running, uint32_t *reason);
 int raduls_server_destroy(raduls_server *srv);

@@ -115,8 +115,11 @@ def load() -> ctypes.CDLL:
         "raduls_server_max_records": (i32, [u32, u32, u64p]),
         "raduls_server_create": (i32, [u32, u32, u32, u32, u32, ctypes.POINTER(vp)]),
         "raduls_server_submit": (i32, [vp, vp, u64, u64p]),
+        "raduls_server_submit_many": (i32, [vp, ctypes.POINTER(vp), u64p, u32, u64p,
+                                            ctypes.POINTER(ctypes.c_uint32)]),
         "raduls_server_poll": (i32, [vp, u64, ctypes.POINTER(ctypes.c_uint32)]),
         "raduls_server_wait": (i32, [vp, u64, u32, ctypes.POINTER(ctypes.c_uint32)]),
+        "raduls_server_wait_range": (i32, [vp, u64, u64, u32, ctypes.POINTER(ctypes.c_uint32)]),
         "raduls_server_info": (i32, [vp, u64p, ctypes.POINTER(ctypes.c_uint32),
                                      ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
         "raduls_server_destroy": (i32, [vp]),
@@ -138,7 +141,7 @@ def exported_symbols() -> list[str]:
         "raduls_inspect_rounds", "raduls_sort_static",
         "raduls_set_profile_events",
         "raduls_server_max_records", "raduls_server_create", "raduls_server_submit",
-        "raduls_server_poll", "raduls_server_wait", "raduls_server_info", "raduls_server_destroy",
+        "raduls_server_submit_many", "raduls_server_poll", "raduls_server_wait_range", "raduls_server_wait", "raduls_server_info", "raduls_server_destroy",
     ]
 
 
@@ -332,6 +335,22 @@ class ResidentServer:
         _check(st, "raduls_server_submit")
         return t
 
+    def submit_many(self, ptrs, ns) -> tuple[int, int]:
+        """Submit arrays by device address and record count (sequences or
+        numpy arrays); returns (first ticket, how many were accepted: fewer
+        than given when the ring's slots ran out)."""
+        import numpy as np
+        p = np.ascontiguousarray(ptrs, dtype=np.uint64)
+        n = np.ascontiguousarray(ns, dtype=np.uint64)
+        if p.shape != n.shape:
+            raise ValueError("one record count per array")
+        first, acc = ctypes.c_uint64(0), ctypes.c_uint32(0)
+        _check(load().raduls_server_submit_many(
+            self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_void_p)),
+            n.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), p.size, ctypes.byref(first),
+            ctypes.byref(acc)), "raduls_server_submit_many")
+        return int(first.value), int(acc.value)
+
     def poll(self, ticket: int) -> tuple[int, int]:
         """(1 done / 0 pending / negative status, device error bits)."""
         s = ctypes.c_uint32(0)
@@ -344,6 +363,14 @@ class ResidentServer:
         r = load().raduls_server_wait(self._h, ticket, timeout_ms, ctypes.byref(s))
         if r < 0:
             raise RadulsError(r, "raduls_server_wait")
+        return int(s.value)
+
+    def wait_range(self, first: int, count: int, timeout_ms: int = 10000) -> int:
+        """Wait for tickets [first, first + count); returns the OR of their
+        device error bits (0: all sorted)."""
+        s = ctypes.c_uint32(0)
+        _check(load().raduls_server_wait_range(self._h, first, count, timeout_ms, ctypes.byref(s)),
+               "raduls_server_wait_range")
         return int(s.value)
 
     def close(self) -> None:

@@ -200,6 +200,7 @@ struct Ctrl {
 constexpr uint32_t kServeMaxSlots = 1u << 20;
 constexpr uint32_t kServeMaxIdleMs = 600000;     // 10 minutes
 constexpr uint32_t kServeDefaultIdleMs = 10000;  // idle_ms = 0
+constexpr uint32_t kServeChunk = 8;              // most requests a workgroup claims at once
 
 struct ServeSlot {
   uint64_t seq;     // host: ticket + 1 once recs and n are written
@@ -219,14 +220,20 @@ struct ServeRing {
   ServeSlot slot[1];  // [slots] (allocated past the struct's end)
 };
 
-// Device-memory state of a server: the dispatch lock (one workgroup at a
-// time reads the ring), the next ticket to hand out, and per workgroup the
-// error bits of the request it is sorting.
+// Device-memory state of a server.  Requests move from the host ring into a
+// device queue (entry t % slots for ticket t) in batches of up to one wave's
+// worth, read in parallel by the wave that holds the dispatch lock; `tail`
+// counts the requests queued, `head` the ones claimed by workgroups.
 struct ServeState {
   uint32_t lock;
   uint32_t pad;
-  uint64_t next;
-  uint64_t pad1[6];
+  uint64_t head;
+  uint64_t tail;
+  uint64_t pad1[5];
+};
+struct ServeJob {
+  uint64_t recs;
+  uint64_t n;
 };
 
 // Device pointers into the auxiliary workspace.
@@ -291,6 +298,7 @@ struct Params {
   ServeRing* ring;          // device address of the host-pinned ring
   ServeState* serve;        // device memory
   Ctrl* serve_ctrl;         // [workgroups] error bits of each workgroup's request
+  ServeJob* serve_queue;    // [serve_slots] requests moved from the ring
   uint32_t serve_slots;
   uint64_t serve_idle;      // ticks of the 100 MHz constant clock a workgroup waits idle
 };

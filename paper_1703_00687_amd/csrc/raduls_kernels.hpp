@@ -2191,75 +2191,178 @@ __device__ __forceinline__ void mid_wave_sort_bucket(const MidLds& L, uint32_t s
 
 // ------------------------------------------------------------ resident server
 
-// Claim the next request of a resident server (all threads call; the result
-// is uniform).  Thread 0 waits for a published ring slot: it takes the
-// dispatch lock (one workgroup at a time reads the host ring), reads the slot
-// of the next ticket with an acquire at system scope (which also makes the
-// request's input, written before it was submitted, visible here), advances
-// the ticket and drops the lock.  It gives up when the host sets the stop
-// word or after P.serve_idle ticks of the 100 MHz clock without a request;
-// every wait of the server is bounded that way.  Returns false to exit.
-__device__ __forceinline__ bool serve_claim(const Params& P, MidJob& job, uint64_t& ticket) {
-  __shared__ uint64_t s_t, s_recs, s_n;
+// A workgroup's claimed run of tickets [first, first + count); idx of them
+// taken so far.
+struct ServeCursor {
+  uint64_t first, count, idx;
+};
+
+// Claim a run of queued requests of a resident server (all threads call; the
+// result is uniform).  Wave 0 does the waiting: it claims the oldest queued
+// requests (a compare-and-swap on the device queue's head; an eighth of the
+// queue, 1..kServeChunk of them, so that a long queue is taken in runs and a
+// short one a request at a time); when none is queued it takes the dispatch
+// lock and moves newly published requests from the host ring into the device
+// queue -- each lane reads one slot with an acquire at system scope, the
+// published run from the oldest on is copied, and the queue's tail advances
+// past it with a release.  The claimant also acquires at system scope, so
+// that the requests' inputs (written before they were submitted) are visible
+// to it.  It gives up when the host sets the stop word or after P.serve_idle
+// ticks of the 100 MHz clock without a request; every wait of the server is
+// bounded that way.  Returns false to exit.
+__device__ __forceinline__ bool serve_claim(const Params& P, ServeCursor& cur) {
+  __shared__ uint64_t s_first, s_count;
   __shared__ uint32_t s_got;
-  if (threadIdx.x == 0) {
-    uint32_t got = 0;
+  if (threadIdx.x < kWave) {
+    const uint32_t lane = threadIdx.x;
+    ServeState* S = P.serve;
+    const uint32_t width = min(uint32_t(kWave), P.serve_slots);  // distinct ring slots per read
     const uint64_t t0 = wall_clock64();
-    uint32_t spins = 0;
+    uint32_t got = 0, spins = 0, lost = 0;
     for (;;) {
-      if (__hip_atomic_load(&P.ring->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
-        __hip_atomic_store(&P.ring->reason, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        break;
-      }
-      if (__hip_atomic_load(&P.serve->lock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
-        uint32_t expect = 0u;
-        if (__hip_atomic_compare_exchange_strong(&P.serve->lock, &expect, 1u, __ATOMIC_ACQUIRE,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          const uint64_t t = __hip_atomic_load(&P.serve->next, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-          ServeSlot* sl = &P.ring->slot[t % P.serve_slots];
-          if (__hip_atomic_load(&sl->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == t + 1) {
-            s_recs = __hip_atomic_load(&sl->recs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            s_n = __hip_atomic_load(&sl->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            s_t = t;
-            __hip_atomic_store(&P.serve->next, t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            got = 1;
+      uint32_t won = 0, queued = 0;
+      if (lane == 0) {
+        const uint64_t h = __hip_atomic_load(&S->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t = __hip_atomic_load(&S->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        queued = h < t ? 1u : 0u;
+        if (queued) {
+          const uint64_t take = min(max((t - h) / 8u, uint64_t(1)), uint64_t(kServeChunk));
+          uint64_t expect = h;
+          won = __hip_atomic_compare_exchange_strong(&S->head, &expect, h + take, __ATOMIC_ACQ_REL,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    ? 1u
+                    : 0u;
+          if (won) {
+            // (an acquire at system scope here too: the wave that read the
+            // ring may run on another XCD, whose caches are not this one's)
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+            s_first = h;
+            s_count = take;
           }
-          __hip_atomic_store(&P.serve->lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-          if (got) break;
         }
       }
-      if (wall_clock64() - t0 > P.serve_idle) {
-        __hip_atomic_store(&P.ring->reason, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      if (__builtin_amdgcn_readfirstlane(won)) {
+        got = 1;
         break;
       }
+      if (__builtin_amdgcn_readfirstlane(queued)) {
+        // another workgroup took them: retry after a pause that grows with
+        // the claims lost in a row (staggered by workgroup), so that many
+        // workgroups do not keep hammering the head
+        lost = min(lost + 1u, 6u);
+        for (uint32_t k = (blockIdx.x & 3u) + (1u << lost); k > 0; --k) __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      lost = 0;
+      // nothing queued: move published requests from the ring, if the lock is free
+      uint32_t locked = 0;
+      if (lane == 0 &&
+          __hip_atomic_load(&S->lock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+        uint32_t expect = 0u;
+        locked = __hip_atomic_compare_exchange_strong(&S->lock, &expect, 1u, __ATOMIC_ACQUIRE,
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     ? 1u
+                     : 0u;
+      }
+      if (__builtin_amdgcn_readfirstlane(locked)) {
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);  // (every lane, after lane 0's acquire)
+        const uint64_t base = __hip_atomic_load(&S->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t tk = base + lane;
+        bool pub = false;
+        uint64_t recs = 0, n = 0;
+        if (lane < width) {
+          ServeSlot* sl = &P.ring->slot[tk % P.serve_slots];
+          pub = __hip_atomic_load(&sl->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == tk + 1;
+          if (pub) {
+            recs = __hip_atomic_load(&sl->recs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            n = __hip_atomic_load(&sl->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          }
+        }
+        // the published run from the oldest slot on
+        const uint64_t missing = __ballot(!pub);
+        const uint32_t cnt = missing ? uint32_t(__builtin_ctzll(missing)) : uint32_t(kWave);
+        if (lane < cnt) {
+          ServeJob q;
+          q.recs = recs;
+          q.n = n;
+          P.serve_queue[tk % P.serve_slots] = q;
+        }
+        __threadfence();  // the queue entries before the tail
+        if (lane == 0) {
+          if (cnt) __hip_atomic_store(&S->tail, base + cnt, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&S->lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (cnt) {
+          spins = 0;
+          continue;  // claim some of them
+        }
+      }
+      uint32_t quit = 0;
+      if (lane == 0) {
+        if (__hip_atomic_load(&P.ring->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+          __hip_atomic_store(&P.ring->reason, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          quit = 1;
+        } else if (wall_clock64() - t0 > P.serve_idle) {
+          __hip_atomic_store(&P.ring->reason, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          quit = 1;
+        }
+      }
+      if (__builtin_amdgcn_readfirstlane(quit)) break;
       // short naps while requests are coming, longer ones when idle
       if (++spins < 256) __builtin_amdgcn_s_sleep(2);
       else __builtin_amdgcn_s_sleep(60);
     }
-    s_got = got;
+    if (lane == 0) s_got = got;
   }
   __syncthreads();
   if (!s_got) return false;
-  ticket = s_t;
+  cur.first = s_first;
+  cur.count = s_count;
+  cur.idx = 0;
+  return true;
+}
+
+// The next request of a resident server: the next of the workgroup's
+// claimed run, or the first of a new run (all threads call).
+__device__ __forceinline__ bool serve_next(const Params& P, ServeCursor& cur, MidJob& job,
+                                           uint64_t& ticket) {
+  __shared__ uint64_t s_recs, s_n;
+  if (cur.idx >= cur.count && !serve_claim(P, cur)) return false;
+  ticket = cur.first + cur.idx;
+  ++cur.idx;
+  if (threadIdx.x == 0) {
+    const ServeJob* q = P.serve_queue + ticket % P.serve_slots;
+    s_recs = __hip_atomic_load(&q->recs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_n = __hip_atomic_load(&q->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
   job.src = job.dst = reinterpret_cast<uint8_t*>(s_recs);
   job.size = uint32_t(s_n);
   job.pad[0] = job.pad[1] = job.pad[2] = 0;
   return true;
 }
 
-// Publish a server request's completion (all threads call, after the job's
-// stores): every thread's stores are made visible at system scope, then
-// thread 0 writes the slot's status (the workgroup's error bits, cleared for
-// the next request) and, with a release, its completion word.
-__device__ __forceinline__ void serve_complete(const Params& P, Ctrl* c, uint64_t ticket) {
-  __threadfence_system();
-  __syncthreads();
+// A server request's stores are done (all threads call): thread 0 writes the
+// request's status (the workgroup's error bits, cleared for the next one).
+// At the end of the workgroup's run every thread waits until its stores have
+// reached the device cache, and after a barrier wave 0 publishes the run's
+// completion words with release stores at system scope, whose write-back
+// of the cache then covers every thread's records: one write-back per run
+// instead of one per wave.
+__device__ __forceinline__ void serve_complete(const Params& P, Ctrl* c, uint64_t ticket,
+                                               const ServeCursor& cur) {
   if (threadIdx.x == 0) {
-    ServeSlot* sl = &P.ring->slot[ticket % P.serve_slots];
     const uint32_t err = atomicExch(&c->error, 0u);
-    __hip_atomic_store(&sl->status, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&sl->done, ticket + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&P.ring->slot[ticket % P.serve_slots].status, err, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  if (cur.idx < cur.count) return;
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
+  __syncthreads();
+  if (threadIdx.x < cur.count) {
+    const uint64_t t = cur.first + threadIdx.x;
+    __hip_atomic_store(&P.ring->slot[t % P.serve_slots].done, t + 1, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -2344,8 +2447,9 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
   const uint32_t G = gridDim.x;
   MidJob job{};  // job i
   uint64_t ticket = 0;  // (server) the request being sorted
+  ServeCursor scur{0, 0, 0};
   if constexpr (SERVE) {
-    if (!serve_claim(P, job, ticket)) return;
+    if (!serve_next(P, scur, job, ticket)) return;
   } else {
     if (blockIdx.x >= njobs) return;
     job = P.L.mid[blockIdx.x];
@@ -2744,8 +2848,8 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
     }
     lds_barrier();  // the records are rewritten by the next job
     if constexpr (SERVE) {
-      serve_complete(P, c, ticket);
-      if (!serve_claim(P, job, ticket)) break;
+      serve_complete(P, c, ticket, scur);
+      if (!serve_next(P, scur, job, ticket)) break;
       mid_fetch<RW, KW, ITEMS>(job.src, job.size <= T ? job.size : 0u, threadIdx.x, kr, key0);
       __builtin_amdgcn_s_waitcnt(0);
       continue;

@@ -642,7 +642,8 @@ int raduls_server_create(uint32_t rec_bytes, uint32_t key_bytes, uint32_t slots,
   s->wgs = wgs;
   s->cap = e.mid_max;
   const size_t ring_bytes = sizeof(ServeRing) + size_t(slots - 1) * sizeof(ServeSlot);
-  const size_t dev_bytes = sizeof(ServeState) + size_t(wgs) * sizeof(Ctrl);
+  const size_t dev_bytes =
+      sizeof(ServeState) + size_t(wgs) * sizeof(Ctrl) + size_t(slots) * sizeof(ServeJob);
   void* dring = nullptr;
   if (hipHostMalloc(reinterpret_cast<void**>(&s->ring), ring_bytes,
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
@@ -673,6 +674,7 @@ int raduls_server_create(uint32_t rec_bytes, uint32_t key_bytes, uint32_t slots,
   P.ring = static_cast<ServeRing*>(dring);
   P.serve = static_cast<ServeState*>(s->dmem);
   P.serve_ctrl = reinterpret_cast<Ctrl*>(static_cast<uint8_t*>(s->dmem) + sizeof(ServeState));
+  P.serve_queue = reinterpret_cast<ServeJob*>(P.serve_ctrl + wgs);
   P.serve_slots = slots;
   P.serve_idle = uint64_t(idle_ms ? idle_ms : kServeDefaultIdleMs) * 100000ull;  // 100 MHz ticks
   if (serve_launch_rw(P, rec_bytes, key_bytes, wgs, s->stream) != hipSuccess) {
@@ -705,6 +707,34 @@ int raduls_server_submit(raduls_server* s, void* recs, uint64_t n, uint64_t* tic
   return RADULS_OK;
 }
 
+int raduls_server_submit_many(raduls_server* s, void* const* recs, const uint64_t* n,
+                              uint32_t count, uint64_t* first_ticket, uint32_t* accepted) {
+  if (!s || !first_ticket || !accepted || (count && (!recs || !n))) return RADULS_E_INVALID;
+  *accepted = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    if (n[i] > s->cap) return RADULS_E_UNSUPPORTED;
+    if ((n[i] && !recs[i])) return RADULS_E_INVALID;
+    if (recs[i] && misaligned(recs[i])) return RADULS_E_ALIGN;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (!server_running(s)) return RADULS_E_STOPPED;
+  const uint64_t t0 = s->next.load(std::memory_order_relaxed);
+  *first_ticket = t0;
+  uint32_t i = 0;
+  for (; i < count; ++i) {
+    const uint64_t t = t0 + i;
+    ServeSlot& sl = s->ring->slot[t % s->slots];
+    if (t >= s->slots && __atomic_load_n(&sl.done, __ATOMIC_ACQUIRE) != t - s->slots + 1) break;
+    sl.recs = reinterpret_cast<uint64_t>(recs[i]);
+    sl.n = n[i];
+    sl.status = 0;
+    __atomic_store_n(&sl.seq, t + 1, __ATOMIC_RELEASE);
+  }
+  s->next.store(t0 + i, std::memory_order_release);
+  *accepted = i;
+  return RADULS_OK;
+}
+
 int raduls_server_poll(raduls_server* s, uint64_t ticket, uint32_t* status) {
   if (!s || ticket >= s->next.load(std::memory_order_acquire)) return RADULS_E_INVALID;
   const ServeSlot& sl = s->ring->slot[ticket % s->slots];
@@ -730,6 +760,30 @@ int raduls_server_wait(raduls_server* s, uint64_t ticket, uint32_t timeout_ms, u
       return RADULS_E_TIMEOUT;
     if (k > 64) std::this_thread::yield();
   }
+}
+
+int raduls_server_wait_range(raduls_server* s, uint64_t first, uint64_t count,
+                             uint32_t timeout_ms, uint32_t* status_or) {
+  if (!s) return RADULS_E_INVALID;
+  if (count && first + count > s->next.load(std::memory_order_acquire)) return RADULS_E_INVALID;
+  const auto t0 = std::chrono::steady_clock::now();
+  uint32_t acc = 0;
+  for (uint64_t t = first; t < first + count; ++t) {
+    for (uint32_t k = 0;; ++k) {
+      uint32_t st = 0;
+      const int r = raduls_server_poll(s, t, &st);
+      if (r < 0) return r;
+      if (r == 1) {
+        acc |= st;
+        break;
+      }
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(timeout_ms))
+        return RADULS_E_TIMEOUT;
+      if (k > 64) std::this_thread::yield();
+    }
+  }
+  if (status_or) *status_or = acc;
+  return RADULS_OK;
 }
 
 int raduls_server_info(raduls_server* s, uint64_t* max_records, uint32_t* workgroups,

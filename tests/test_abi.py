@@ -172,8 +172,12 @@ def test_server_argument_errors_on_host():
     t = ctypes.c_uint64()
     st = ctypes.c_uint32()
     assert lib.raduls_server_submit(None, None, 0, ctypes.byref(t)) == b.E_INVALID
+    acc = ctypes.c_uint32()
+    assert lib.raduls_server_submit_many(None, None, None, 0, ctypes.byref(t),
+                                         ctypes.byref(acc)) == b.E_INVALID
     assert lib.raduls_server_poll(None, 0, ctypes.byref(st)) == b.E_INVALID
     assert lib.raduls_server_wait(None, 0, 1, ctypes.byref(st)) == b.E_INVALID
+    assert lib.raduls_server_wait_range(None, 0, 1, 1, ctypes.byref(st)) == b.E_INVALID
     assert lib.raduls_server_info(None, None, None, None, None) == b.E_INVALID
     assert lib.raduls_server_destroy(None) == b.E_INVALID
 

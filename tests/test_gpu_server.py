@@ -147,3 +147,30 @@ def test_server_stop_is_prompt():
     t = time.perf_counter()
     srv.close()
     assert time.perf_counter() - t < 2.0
+
+
+def test_server_submit_many_stops_at_a_busy_slot():
+    r, k = 16, 8
+    cap = b.raduls_server_max_records(r, k)
+    rng = np.random.default_rng(13)
+    sizes = [int(x) for x in rng.integers(0, cap + 1, size=40)]
+    hosts = [wl.random_records(rng, n, r, k, distinct_keys=max(1, n // 4)) for n in sizes]
+    devs = [_device(h) for h in hosts]
+    torch.cuda.synchronize()
+    ptrs = [d.data_ptr() if n else 0 for d, n in zip(devs, sizes)]
+    with b.ResidentServer(r, k, slots=16, workgroups=2, idle_ms=IDLE_MS) as srv:
+        # one oversize request: nothing is submitted
+        with pytest.raises(b.RadulsError):
+            srv.submit_many(ptrs[:3] + [ptrs[3]], sizes[:3] + [cap + 1])
+        done = 0
+        while done < len(sizes):
+            first, acc = srv.submit_many(ptrs[done:], sizes[done:])
+            assert first == done and acc <= 16
+            if acc == 0:  # every slot in use: free the oldest
+                assert srv.wait(done - 16) == 0
+            done += acc
+        assert srv.wait_range(0, len(sizes)) == 0
+        with pytest.raises(b.RadulsError):
+            srv.wait_range(0, len(sizes) + 1)  # a ticket not submitted yet
+    for h, d in zip(hosts, devs):
+        assert np.array_equal(d.cpu().numpy(), oracle.sort(h, k))
