@@ -229,7 +229,7 @@ int oracle_msd_sort(const uint8_t* in, uint8_t* out, uint64_t n, uint32_t R, uin
   int st = validate(n, R, K);
   if (st != ST_OK) return st;
   if (width == 0 || width > 16) return ST_INVALID;
-  std::memcpy(out, in, n * R);
+  if (n) std::memcpy(out, in, n * R);  // (memcpy with a null pointer is undefined even for 0 bytes)
   std::vector<uint8_t> buf(n * R + 1);
   msd_rec(out, buf.data(), n, R, K, 8 * K, width, tiny_max);
   return ST_OK;
