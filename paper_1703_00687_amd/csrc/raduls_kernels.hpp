@@ -3199,11 +3199,16 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
     k_classify<KW><<<P.grid_classify, 256, 0, s>>>(P, cur, r);
   }
   if (P.inspect) return hipGetLastError();
+  // a single array of at most mid_max records (no rounds) is one job, which
+  // the seed put on the tiny list or the LDS list by its size; nothing can
+  // end in tmp.  Only that job's sorter is launched.
+  const bool one_job = P.mode == kModeSort && P.rounds == 0;
   prof_mark(kProfMid, 0, s);
-  k_tiny<RW, KW><<<P.grid_tiny, kMidBlock, 0, s>>>(P);
-  k_mid<RW, KW><<<P.grid_mid, kMidBlock, P.mid_lds_bytes, s>>>(P);
+  if (!one_job || P.n <= P.tiny_job) k_tiny<RW, KW><<<P.grid_tiny, kMidBlock, 0, s>>>(P);
+  if (!one_job || P.n > P.tiny_job)
+    k_mid<RW, KW><<<P.grid_mid, kMidBlock, P.mid_lds_bytes, s>>>(P);
   prof_mark(kProfMid, 1, s);
-  k_copy<RW><<<P.grid_copy, 256, 0, s>>>(P);
+  if (!one_job) k_copy<RW><<<P.grid_copy, 256, 0, s>>>(P);
   return hipGetLastError();
 }
 

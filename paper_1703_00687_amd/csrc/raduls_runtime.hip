@@ -106,8 +106,10 @@ Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const
   const uint64_t T = e.mid_max;
   s.rounds = step ? 1 : (8 * K + e.digit_bits - 1) / e.digit_bits;
   // many records: dominated bins may be split on an equality key, which
-  // takes a round but no key bit
-  s.eq_split = !step && n_total > 64ull * T ? 1u : 0u;
+  // takes a round but no key bit.  Below 256 * mid_max records the top
+  // level alone leaves bins of about mid_max records, and a heavy key's run
+  // is cheap to isolate by digits, so those sorts launch no rounds for it.
+  s.eq_split = !step && n_total > 256ull * T ? 1u : 0u;
   if (s.eq_split) s.rounds += kEqRounds;
   const uint64_t large = step ? 1 : n_total / (T + 1) + 1;
   const uint64_t tiles = n_total / e.tile + large + 1;
