@@ -1894,8 +1894,11 @@ __device__ __forceinline__ void mid_wg_pass(const Params& P, MidLds& L, uint32_t
     for (int j = 0; j < ITEMS; ++j) {
       if (valid[j]) {
         const uint32_t wd = src[j] >> 5;
-        L.perm[s + pre[wd] + uint32_t(__popc(bits[wd] & ((1u << (src[j] & 31u)) - 1u)))] =
-            uint16_t(src[j]);
+        const uint32_t at =
+            s + pre[wd] + uint32_t(__popc(bits[wd] & ((1u << (src[j] & 31u)) - 1u)));
+        L.perm[at] = uint16_t(src[j]);
+        // the range is final: the windows' enumeration sort skips it
+        atomicAnd(&L.bmb[at >> 5], ~(1u << (at & 31u)));
       }
     }
     lds_barrier();
@@ -1984,7 +1987,12 @@ __device__ __forceinline__ void mid_wave_pass(const Params& P, MidLds& L, uint32
       for (uint32_t q = 0; q < 3; ++q)
         place += q < (wd & 3u) ? uint32_t(__popc(wc[(wd & ~3u) + q])) : 0u;
       place += uint32_t(__popc(wc[wd] & ((1u << (src[j] & 31u)) - 1u)));
-      if (valid[j]) L.perm[s + place] = uint16_t(src[j]);
+      if (valid[j]) {
+        const uint32_t at = s + place;
+        L.perm[at] = uint16_t(src[j]);
+        // the range is final: the windows' enumeration sort skips it
+        atomicAnd(&L.bmb[at >> 5], ~(1u << (at & 31u)));
+      }
     }
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_wave_barrier();
