@@ -155,7 +155,10 @@ int raduls_sort_static(void *recs, void *tmp, uint64_t n, uint32_t rec_bytes, ui
  * at the same offsets.  flags bit 0: the next round splits the bin on one key
  * that dominates it (keys below, equal to, above it); bit 1: the bin is one
  * side of such a split, a key range inside a run of records sharing the bits
- * from `bits` up rather than the whole run. */
+ * from `bits` up rather than the whole run; bits 2-5: when non-zero, the
+ * width of the digit the next round splits the bin on (narrower than the
+ * tuning's digit width: the bin is split into children of about one LDS job
+ * each). */
 typedef struct raduls_bin {
   uint32_t start;
   uint32_t size;

@@ -144,6 +144,12 @@ struct ArrayDesc {  // same layout as raduls_array
 // records that share all key bits above `bits`, not the whole run.
 constexpr uint8_t kBinEq = 1;
 constexpr uint8_t kBinRange = 2;
+// Bits 2-5: the width of the digit the next round splits the bin on, when
+// narrower than digit_bits (0: digit_bits).  A bin a little larger than an
+// LDS job is split on just enough bits that its children fit one job each,
+// instead of on a full digit into children that must be packed many to a job.
+constexpr uint32_t kBinWidthShift = 2;
+constexpr uint8_t kBinWidthMask = 0x3C;
 // Extra rounds that a sort of many records allows for equality splits (a
 // split consumes a round but no key bit), and the samples that decide one.
 constexpr uint32_t kEqRounds = 2;

@@ -160,6 +160,12 @@ __device__ __forceinline__ int top_bit(const uint64_t (&d)[KW]) {
 // [lob, lob + w) of the key (Sec. 1), or, for a bin marked for an equality
 // split (kBinEq), into 0: keys below its equality key, 1: that key, 2: keys
 // above it (the key bits stay to be sorted in both ranges).
+// The digit width a large bin is split on (its own narrower width, if set).
+__device__ __forceinline__ uint32_t bin_width(const Params& P, const Bin& bin) {
+  const uint32_t bw = (uint32_t(bin.flags) & kBinWidthMask) >> kBinWidthShift;
+  return bw ? bw : P.digit_bits;
+}
+
 template <int KW>
 struct Bucketing {
   uint32_t lob, w, nb;
@@ -177,7 +183,7 @@ __device__ __forceinline__ Bucketing<KW> bucketing(const Params& P, const Bin& b
                                                    uint32_t b) {
   Bucketing<KW> d;
   d.eq = (bin.flags & kBinEq) != 0;
-  d.w = d.eq ? 2u : min(P.digit_bits, uint32_t(bin.bits));
+  d.w = d.eq ? 2u : min(bin_width(P, bin), uint32_t(bin.bits));
   d.lob = d.eq ? uint32_t(bin.bits) : uint32_t(bin.bits) - d.w;
   d.nb = 1u << d.w;
 #pragma unroll
@@ -1412,7 +1418,7 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32
     // an equality split leaves the key bits as they were (buckets: below,
     // equal to, above the bin's equality key)
     const bool eqb = (bin.flags & kBinEq) != 0;
-    const uint32_t w = eqb ? 2u : min(P.digit_bits, uint32_t(bin.bits));
+    const uint32_t w = eqb ? 2u : min(bin_width(P, bin), uint32_t(bin.bits));
     const uint32_t lob = eqb ? uint32_t(bin.bits) : bin.bits - w;
     const uint32_t nb = 1u << w;
     // with pair counts (second round only) the bin's row is its top digit's
@@ -1437,7 +1443,7 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32
       if (tid == 0) {
         Bin nbn = bin;
         nbn.bits = uint16_t(tb + 1);
-        nbn.flags = uint8_t(bin.flags & kBinRange);
+        nbn.flags = uint8_t(bin.flags & (kBinRange | kBinWidthMask));
         const uint64_t none[KW] = {};
         push_large<KW>(P, nxt, nbn, none);
       }
@@ -1476,6 +1482,21 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32
           ch.flags |= kBinEq;
           atomicAdd(&c->eq_bins, 1u);
         }
+      }
+      // a child of 1.6 to 230 jobs' worth of records is split next round on
+      // the fewest bits that leave children of at most 0.9 mid_max each
+      // (about one job each, all its bits in the job's first pass), when
+      // that is fewer than a digit and the rounds left still cover the key
+      // bits below; not where the second round takes the top level's pair
+      // counts (they are per full digit)
+      const uint32_t target = P.mid_max - P.mid_max / 10u;
+      if (!(ch.flags & kBinEq) && !(P.pair && round == 0) &&
+          uint64_t(h) * 5u >= uint64_t(P.mid_max) * 8u && h <= 256u * target) {
+        uint32_t wn = 1;
+        while (wn < 8u && (h >> wn) > target) ++wn;
+        const uint32_t need_n = (lob - min(wn, lob) + P.digit_bits - 1) / P.digit_bits;
+        if (wn < min(P.digit_bits, lob) && round + 2 + need_n <= P.round_budget)
+          ch.flags |= uint8_t(wn << kBinWidthShift);
       }
       push_large<KW>(P, nxt, ch, eqk);
     }
