@@ -10,7 +10,7 @@ adds pure-Python helpers used by the pins.
 
 Record model: a record is R bytes, its key is bytes [0, K) read as an unsigned
 little-endian integer (the paper's 8 B key + 8 B data records, Sec. 4.2; byte
-order is this build's reading since the paper does not state one).
+order is a reading of ours, since the paper does not state one).
 """
 
 from __future__ import annotations
