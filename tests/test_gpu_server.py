@@ -174,3 +174,32 @@ def test_server_submit_many_stops_at_a_busy_slot():
             srv.wait_range(0, len(sizes) + 1)  # a ticket not submitted yet
     for h, d in zip(hosts, devs):
         assert np.array_equal(d.cpu().numpy(), oracle.sort(h, k))
+
+
+def test_two_servers_side_by_side():
+    """Two servers of different record layouts at once, each with its own
+    ring, queue and stream, while a plain sort runs on the default stream."""
+    rng = np.random.default_rng(17)
+    a_h = [wl.random_records(rng, int(n), 16, 8, distinct_keys=max(1, int(n) // 5))
+           for n in rng.integers(0, 5121, size=40)]
+    b_h = [wl.random_records(rng, int(n), 32, 16, distinct_keys=max(1, int(n) // 5))
+           for n in rng.integers(0, b.raduls_server_max_records(32, 16) + 1, size=40)]
+    a_d = [_device(h) for h in a_h]
+    b_d = [_device(h) for h in b_h]
+    big = _device(wl.random_records(rng, 1 << 20, 16, 8))
+    big_h = big.cpu().numpy()
+    tmp = torch.empty(b.raduls_tmp_bytes(1 << 20, 16, 8), dtype=torch.uint8, device=DEV)
+    torch.cuda.synchronize()
+    with b.ResidentServer(16, 8, slots=64, workgroups=4, idle_ms=IDLE_MS) as sa, \
+            b.ResidentServer(32, 16, slots=64, workgroups=4, idle_ms=IDLE_MS) as sb:
+        b.raduls_sort(big, tmp, 1 << 20, 16, 8)
+        ta = [sa.submit(d) for d in a_d]
+        tb = [sb.submit(d) for d in b_d]
+        assert sa.wait_range(ta[0], len(ta)) == 0
+        assert sb.wait_range(tb[0], len(tb)) == 0
+        torch.cuda.current_stream().synchronize()
+    for h, d in zip(a_h, a_d):
+        assert np.array_equal(d.cpu().numpy(), oracle.sort(h, 8))
+    for h, d in zip(b_h, b_d):
+        assert np.array_equal(d.cpu().numpy(), oracle.sort(h, 16))
+    assert np.array_equal(big.cpu().numpy(), oracle.sort(big_h, 8))
