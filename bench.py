@@ -477,14 +477,19 @@ def bench_batch(args) -> dict:
         views = [recs[int(starts[j]):int(starts[j]) + int(sizes[j])] for j in range(nreq)]
         import gc
 
+        small_cap = b.raduls_server_max_records(R, K)
+
         def serve_run(rate, many=True):
             """Serve the first nreq arrays: all at t = 0 (rate None; in one
             submit_many call, or one submit per array if not `many`) or as a
             Poisson stream of `rate` requests per second from an open-loop
             client that submits every request whose arrival time has come,
-            one submit each."""
+            one submit each.  Latencies are also reported apart for the
+            requests of at most one LDS job (small_cap records) and the
+            others."""
             fill_batch(recs, starts, sizes)
-            torch.cuda.synchronize()  # (so the requests are submitted with ready=False)
+            # (so the requests are submitted with ready=False)
+            torch.cuda.current_stream().synchronize()
             # Python's cyclic collector would stop both the client and the
             # server thread for up to ~0.15 s at a time while tens of
             # thousands of requests are alive; a latency-sensitive client
@@ -516,6 +521,12 @@ def bench_batch(args) -> dict:
             summ = srv.stop()
             gc.enable()
             summ["wall_s"] = time.perf_counter() - t0
+            for name, sel in (("small", lambda n: n <= small_cap), ("large", lambda n: n > small_cap)):
+                lat = sorted((f.t_done - f.t_arrival) * 1e3 for f in futs if sel(f.n))
+                if lat:
+                    summ[f"{name}_requests"] = len(lat)
+                    summ[f"{name}_p50_ms"] = lat[len(lat) // 2]
+                    summ[f"{name}_p99_ms"] = lat[min(len(lat) - 1, int(0.99 * (len(lat) - 1) + 0.5))]
             return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
 
         closed = serve_run(None)

@@ -275,23 +275,37 @@ uint32_t raduls_mid_capacity(uint32_t rec_bytes, uint32_t key_bytes);
  *     ring slot the request needs still holds an uncompleted request from
  *     `slots` submissions ago (retry after a completion);
  *     RADULS_E_UNSUPPORTED: n > max_records; RADULS_E_STOPPED: the kernel
- *     has left.  One submitter at a time is safe (calls are serialized).
+ *     could not be relaunched (destroyed, or the launch failed).  Calls
+ *     are serialized.
  *   - poll returns 1 once the request's sorted records are visible to the
  *     host and to work enqueued afterwards (*status: 0, or the device's
- *     error bits), 0 while pending, RADULS_E_STOPPED if the kernel left
- *     without completing it.  Poll a ticket before `slots` later submissions
+ *     error bits), 0 while pending, RADULS_E_STOPPED if the kernel was
+ *     stopped (or could not be relaunched) before completing it.  Poll a ticket before `slots` later submissions
  *     reuse its slot, or its status reads 0.  wait polls until done or
  *     `timeout_ms` (then RADULS_E_TIMEOUT).
  *   - Every wait of the kernel is bounded: a workgroup leaves when destroy
  *     sets the ring's stop word, or after `idle_ms` (0: 10 s; at most 10
- *     minutes) without a request; a server whose kernel has left serves no
- *     more requests (info: running 0, reason 1 stopped / 2 idle).
+ *     minutes) without a request, or, with `lease_ms` > 0 (at most 10
+ *     minutes), before its next claim once it has run that long, requests
+ *     queued or not.  A kernel that left idle or by its lease is relaunched
+ *     (same stream, ring and state) by the next submit, or by a poll /
+ *     completed / wait that finds requests pending: requests queued when it
+ *     left progress only while the host makes such calls.  Only destroy's
+ *     stop is final (info: running, reason 1 stopped / 2 idle / 3 lease).
+ *   - The kernel holds its stream's hardware queue while it runs.  When a
+ *     process has more streams than the device's hardware queues (HIP maps
+ *     streams onto a few queues per device; a PyTorch program that creates
+ *     one stream of its pool has dozens), streams share queues, and work on
+ *     a stream that shares the server's queue waits until the kernel leaves.
+ *     Such programs set a short lease (and idle time), which bounds that
+ *     wait.  A device-wide synchronize also waits for the kernel.
  *   - destroy stops the kernel (requests being sorted finish; queued ones
  *     are not started), waits for it to leave and frees everything. */
 typedef struct raduls_server raduls_server;
 int raduls_server_max_records(uint32_t rec_bytes, uint32_t key_bytes, uint64_t *out_records);
 int raduls_server_create(uint32_t rec_bytes, uint32_t key_bytes, uint32_t slots,
-                         uint32_t workgroups, uint32_t idle_ms, raduls_server **out);
+                         uint32_t workgroups, uint32_t idle_ms, uint32_t lease_ms,
+                         raduls_server **out);
 int raduls_server_submit(raduls_server *srv, void *recs, uint64_t n, uint64_t *ticket);
 /* submit_many: requests recs[i] of n[i] records, i < count, in order, with
  * tickets *first_ticket, *first_ticket + 1, ...; stops early (without error)
@@ -307,6 +321,14 @@ int raduls_server_wait(raduls_server *srv, uint64_t ticket, uint32_t timeout_ms,
  * RADULS_E_STOPPED or RADULS_E_INVALID. */
 int raduls_server_wait_range(raduls_server *srv, uint64_t first, uint64_t count,
                              uint32_t timeout_ms, uint32_t *status_or);
+/* completed: *through = the number of leading tickets that have all
+ * completed (every ticket below it is done), advanced from where the last
+ * call left it; *status_or = the OR of the status words of the tickets this
+ * call newly found done (so that a caller polling many requests needs one
+ * call, and `poll` only to find which of them failed).  RADULS_E_STOPPED if
+ * tickets are pending and the kernel was stopped or could not be
+ * relaunched. */
+int raduls_server_completed(raduls_server *srv, uint64_t *through, uint32_t *status_or);
 int raduls_server_info(raduls_server *srv, uint64_t *max_records, uint32_t *workgroups,
                        uint32_t *running, uint32_t *reason);
 int raduls_server_destroy(raduls_server *srv);

@@ -113,13 +113,14 @@ def load() -> ctypes.CDLL:
                                         ctypes.POINTER(ctypes.c_uint32), vp]),
         "raduls_set_profile_events": (i32, [ctypes.POINTER(ctypes.c_void_p), u32]),
         "raduls_server_max_records": (i32, [u32, u32, u64p]),
-        "raduls_server_create": (i32, [u32, u32, u32, u32, u32, ctypes.POINTER(vp)]),
+        "raduls_server_create": (i32, [u32, u32, u32, u32, u32, u32, ctypes.POINTER(vp)]),
         "raduls_server_submit": (i32, [vp, vp, u64, u64p]),
         "raduls_server_submit_many": (i32, [vp, ctypes.POINTER(vp), u64p, u32, u64p,
                                             ctypes.POINTER(ctypes.c_uint32)]),
         "raduls_server_poll": (i32, [vp, u64, ctypes.POINTER(ctypes.c_uint32)]),
         "raduls_server_wait": (i32, [vp, u64, u32, ctypes.POINTER(ctypes.c_uint32)]),
         "raduls_server_wait_range": (i32, [vp, u64, u64, u32, ctypes.POINTER(ctypes.c_uint32)]),
+        "raduls_server_completed": (i32, [vp, u64p, ctypes.POINTER(ctypes.c_uint32)]),
         "raduls_server_info": (i32, [vp, u64p, ctypes.POINTER(ctypes.c_uint32),
                                      ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
         "raduls_server_destroy": (i32, [vp]),
@@ -141,7 +142,8 @@ def exported_symbols() -> list[str]:
         "raduls_inspect_rounds", "raduls_sort_static",
         "raduls_set_profile_events",
         "raduls_server_max_records", "raduls_server_create", "raduls_server_submit",
-        "raduls_server_submit_many", "raduls_server_poll", "raduls_server_wait_range", "raduls_server_wait", "raduls_server_info", "raduls_server_destroy",
+        "raduls_server_submit_many", "raduls_server_poll", "raduls_server_wait_range",
+        "raduls_server_completed", "raduls_server_wait", "raduls_server_info", "raduls_server_destroy",
     ]
 
 
@@ -307,16 +309,16 @@ class ResidentServer:
     ``poll`` / ``wait`` take."""
 
     def __init__(self, rec_bytes: int, key_bytes: int, slots: int = 4096, workgroups: int = 0,
-                 idle_ms: int = 0):
+                 idle_ms: int = 0, lease_ms: int = 0):
         self.rec_bytes, self.key_bytes = rec_bytes, key_bytes
         h = ctypes.c_void_p()
         _check(load().raduls_server_create(rec_bytes, key_bytes, slots, workgroups, idle_ms,
-                                           ctypes.byref(h)), "raduls_server_create")
+                                           lease_ms, ctypes.byref(h)), "raduls_server_create")
         self._h = h
         self.max_records, self.workgroups, _, _ = self.info()
 
     def info(self) -> tuple[int, int, bool, int]:
-        """(max_records, workgroups, running, reason: 0, 1 stopped, 2 idle)."""
+        """(max_records, workgroups, running, reason: 0, 1 stopped, 2 idle, 3 lease)."""
         m, w, r, why = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
         _check(load().raduls_server_info(self._h, ctypes.byref(m), ctypes.byref(w), ctypes.byref(r),
                                          ctypes.byref(why)), "raduls_server_info")
@@ -364,6 +366,15 @@ class ResidentServer:
         if r < 0:
             raise RadulsError(r, "raduls_server_wait")
         return int(s.value)
+
+    def completed(self) -> tuple[int, int]:
+        """(tickets below this have all completed, OR of the status words of
+        those newly found done); raises if requests are pending and the
+        kernel was stopped or could not be relaunched."""
+        t, s = ctypes.c_uint64(0), ctypes.c_uint32(0)
+        _check(load().raduls_server_completed(self._h, ctypes.byref(t), ctypes.byref(s)),
+               "raduls_server_completed")
+        return int(t.value), int(s.value)
 
     def wait_range(self, first: int, count: int, timeout_ms: int = 10000) -> int:
         """Wait for tickets [first, first + count); returns the OR of their

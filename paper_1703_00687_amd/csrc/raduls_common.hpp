@@ -206,6 +206,7 @@ struct Ctrl {
 constexpr uint32_t kServeMaxSlots = 1u << 20;
 constexpr uint32_t kServeMaxIdleMs = 600000;     // 10 minutes
 constexpr uint32_t kServeDefaultIdleMs = 10000;  // idle_ms = 0
+constexpr uint32_t kServeMaxLeaseMs = 600000;    // 10 minutes
 constexpr uint32_t kServeChunk = 8;              // most requests a workgroup claims at once
 
 struct ServeSlot {
@@ -221,7 +222,7 @@ static_assert(sizeof(ServeSlot) == 64, "one slot per 64-byte line");
 struct ServeRing {
   uint64_t stop;      // host: non-zero asks every workgroup to exit
   uint64_t pad0[7];
-  uint32_t reason;    // device: why the last workgroup to leave left (1 stop, 2 idle)
+  uint32_t reason;    // device: why the last workgroup to leave left (1 stop, 2 idle, 3 lease)
   uint32_t pad1[15];
   ServeSlot slot[1];  // [slots] (allocated past the struct's end)
 };
@@ -307,6 +308,7 @@ struct Params {
   ServeJob* serve_queue;    // [serve_slots] requests moved from the ring
   uint32_t serve_slots;
   uint64_t serve_idle;      // ticks of the 100 MHz constant clock a workgroup waits idle
+  uint64_t serve_lease;     // ticks a workgroup serves before it leaves (0: no limit)
 };
 
 __host__ __device__ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }

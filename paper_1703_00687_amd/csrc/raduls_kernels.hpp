@@ -2224,6 +2224,7 @@ __device__ __forceinline__ void mid_wave_sort_bucket(const MidLds& L, uint32_t s
 // taken so far.
 struct ServeCursor {
   uint64_t first, count, idx;
+  uint64_t start;  // the 100 MHz clock when the workgroup started
 };
 
 // Claim a run of queued requests of a resident server (all threads call; the
@@ -2238,7 +2239,11 @@ struct ServeCursor {
 // that the requests' inputs (written before they were submitted) are visible
 // to it.  It gives up when the host sets the stop word or after P.serve_idle
 // ticks of the 100 MHz clock without a request; every wait of the server is
-// bounded that way.  Returns false to exit.
+// bounded that way.  With a lease (P.serve_lease ticks, non-zero) it also
+// gives up before claiming once the workgroup has run that long, queued
+// requests or not: the host relaunches the kernel for them, and work queued
+// behind the kernel on a shared hardware queue runs in between.  Returns
+// false to exit.
 __device__ __forceinline__ bool serve_claim(const Params& P, ServeCursor& cur) {
   __shared__ uint64_t s_first, s_count;
   __shared__ uint32_t s_got;
@@ -2249,7 +2254,12 @@ __device__ __forceinline__ bool serve_claim(const Params& P, ServeCursor& cur) {
     const uint64_t t0 = wall_clock64();
     uint32_t got = 0, spins = 0, lost = 0;
     for (;;) {
-      uint32_t won = 0, queued = 0;
+      uint32_t won = 0, queued = 0, expired = 0;
+      if (lane == 0 && P.serve_lease && wall_clock64() - cur.start > P.serve_lease) {
+        __hip_atomic_store(&P.ring->reason, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        expired = 1;
+      }
+      if (__builtin_amdgcn_readfirstlane(expired)) break;
       if (lane == 0) {
         const uint64_t h = __hip_atomic_load(&S->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t t = __hip_atomic_load(&S->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -2476,7 +2486,7 @@ __global__ void __launch_bounds__(kMidBlock) k_mid(Params P) {
   const uint32_t G = gridDim.x;
   MidJob job{};  // job i
   uint64_t ticket = 0;  // (server) the request being sorted
-  ServeCursor scur{0, 0, 0};
+  ServeCursor scur{0, 0, 0, SERVE ? wall_clock64() : 0ull};
   if constexpr (SERVE) {
     if (!serve_next(P, scur, job, ticket)) return;
   } else {

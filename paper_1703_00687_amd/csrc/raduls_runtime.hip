@@ -340,8 +340,11 @@ struct raduls_server {
   void* dmem = nullptr;                      // ServeState + Ctrl[wgs]
   hipStream_t stream = nullptr;
   std::atomic<uint64_t> next{0};             // next ticket
+  uint64_t through = 0;                      // tickets below it have all completed (under mu_done)
+  std::mutex mu_done;
   std::atomic<bool> exited{false};           // the kernel has left
-  std::mutex mu;                             // submitters
+  std::mutex mu;                             // submitters, relaunches
+  raduls::Params P{};                        // the kernel's launch parameters
 };
 
 namespace raduls {
@@ -354,6 +357,22 @@ bool server_running(raduls_server* s) {
   if (q != hipSuccess) (void)hipGetLastError();
   s->exited.store(true, std::memory_order_release);
   return false;
+}
+
+// The server's kernel, relaunched (same stream, same ring and device state)
+// if it left idle or at the end of its lease: requests still in the device
+// queue, or published after its last look at the ring, are then picked up.  False if the host stopped it or the launch
+// failed.  The caller holds s->mu.
+bool server_ensure(raduls_server* s) {
+  if (server_running(s)) return true;
+  if (__atomic_load_n(&s->ring->stop, __ATOMIC_ACQUIRE)) return false;
+  __atomic_store_n(&s->ring->reason, 0u, __ATOMIC_RELEASE);
+  if (serve_launch_rw(s->P, s->R, s->K, s->wgs, s->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  s->exited.store(false, std::memory_order_release);
+  return true;
 }
 
 void server_free(raduls_server* s) {
@@ -628,10 +647,12 @@ int raduls_server_max_records(uint32_t rec_bytes, uint32_t key_bytes, uint64_t* 
 }
 
 int raduls_server_create(uint32_t rec_bytes, uint32_t key_bytes, uint32_t slots,
-                         uint32_t workgroups, uint32_t idle_ms, raduls_server** out) {
+                         uint32_t workgroups, uint32_t idle_ms, uint32_t lease_ms,
+                         raduls_server** out) {
   int st = check_shape(rec_bytes, key_bytes);
   if (st) return st;
-  if (!out || slots == 0 || slots > kServeMaxSlots || idle_ms > kServeMaxIdleMs)
+  if (!out || slots == 0 || slots > kServeMaxSlots || idle_ms > kServeMaxIdleMs ||
+      lease_ms > kServeMaxLeaseMs)
     return RADULS_E_INVALID;
   *out = nullptr;
   const uint32_t cus = uint32_t(device_info().cus);
@@ -679,6 +700,8 @@ int raduls_server_create(uint32_t rec_bytes, uint32_t key_bytes, uint32_t slots,
   P.serve_queue = reinterpret_cast<ServeJob*>(P.serve_ctrl + wgs);
   P.serve_slots = slots;
   P.serve_idle = uint64_t(idle_ms ? idle_ms : kServeDefaultIdleMs) * 100000ull;  // 100 MHz ticks
+  P.serve_lease = uint64_t(lease_ms) * 100000ull;
+  s->P = P;
   if (serve_launch_rw(P, rec_bytes, key_bytes, wgs, s->stream) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipStreamSynchronize(s->stream);
@@ -694,7 +717,7 @@ int raduls_server_submit(raduls_server* s, void* recs, uint64_t n, uint64_t* tic
   if (n > s->cap) return RADULS_E_UNSUPPORTED;
   if (recs && misaligned(recs)) return RADULS_E_ALIGN;
   std::lock_guard<std::mutex> lk(s->mu);
-  if (!server_running(s)) return RADULS_E_STOPPED;
+  if (!server_ensure(s)) return RADULS_E_STOPPED;
   const uint64_t t = s->next.load(std::memory_order_relaxed);
   ServeSlot& sl = s->ring->slot[t % s->slots];
   // the slot's previous request must have completed
@@ -706,6 +729,7 @@ int raduls_server_submit(raduls_server* s, void* recs, uint64_t n, uint64_t* tic
   __atomic_store_n(&sl.seq, t + 1, __ATOMIC_RELEASE);  // publish
   s->next.store(t + 1, std::memory_order_release);
   *ticket = t;
+  (void)server_ensure(s);  // (it may have left since the check above)
   return RADULS_OK;
 }
 
@@ -719,7 +743,7 @@ int raduls_server_submit_many(raduls_server* s, void* const* recs, const uint64_
     if (recs[i] && misaligned(recs[i])) return RADULS_E_ALIGN;
   }
   std::lock_guard<std::mutex> lk(s->mu);
-  if (!server_running(s)) return RADULS_E_STOPPED;
+  if (!server_ensure(s)) return RADULS_E_STOPPED;
   const uint64_t t0 = s->next.load(std::memory_order_relaxed);
   *first_ticket = t0;
   uint32_t i = 0;
@@ -734,6 +758,7 @@ int raduls_server_submit_many(raduls_server* s, void* const* recs, const uint64_
   }
   s->next.store(t0 + i, std::memory_order_release);
   *accepted = i;
+  if (i) (void)server_ensure(s);
   return RADULS_OK;
 }
 
@@ -746,9 +771,11 @@ int raduls_server_poll(raduls_server* s, uint64_t ticket, uint32_t* status) {
     return 1;
   }
   if (!server_running(s)) {
-    // the kernel may have completed the request just before leaving
+    // the kernel may have completed the request just before leaving;
+    // otherwise it left idle before seeing it and is relaunched
     if (__atomic_load_n(&sl.done, __ATOMIC_ACQUIRE) >= ticket + 1) return raduls_server_poll(s, ticket, status);
-    return RADULS_E_STOPPED;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!server_ensure(s)) return RADULS_E_STOPPED;
   }
   return 0;
 }
@@ -785,6 +812,28 @@ int raduls_server_wait_range(raduls_server* s, uint64_t first, uint64_t count,
     }
   }
   if (status_or) *status_or = acc;
+  return RADULS_OK;
+}
+
+int raduls_server_completed(raduls_server* s, uint64_t* through, uint32_t* status_or) {
+  if (!s || !through) return RADULS_E_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu_done);
+  const uint64_t next = s->next.load(std::memory_order_acquire);
+  uint64_t t = s->through;
+  uint32_t acc = 0;
+  while (t < next) {
+    const ServeSlot& sl = s->ring->slot[t % s->slots];
+    if (__atomic_load_n(&sl.done, __ATOMIC_ACQUIRE) != t + 1) break;
+    acc |= __atomic_load_n(&sl.status, __ATOMIC_RELAXED);
+    ++t;
+  }
+  s->through = t;
+  *through = t;
+  if (status_or) *status_or = acc;
+  if (t < next && !server_running(s)) {
+    std::lock_guard<std::mutex> lk2(s->mu);
+    if (!server_ensure(s)) return RADULS_E_STOPPED;
+  }
   return RADULS_OK;
 }
 

@@ -164,10 +164,20 @@ class Arena:
 
 class GpuBackend:
     """Device side of the server: per-stream batch workspaces, launches and
-    completion events."""
+    completion events, and optionally a resident server (raduls_server_*)
+    for requests that fit one LDS job: those are sorted by workgroups that
+    stay on the device, with no launch and no scratch.  Its kernel leaves
+    after `resident_lease_ms` of service (or as long without a request) and
+    is relaunched by the next call that needs it: a PyTorch process has more
+    streams than the device has hardware queues, so a batch stream may share
+    the kernel's queue, and then waits at most that long.  While the kernel
+    runs, a device-wide synchronize would wait for it: callers synchronize
+    their own streams instead, and ``close`` stops it."""
 
     def __init__(self, rec_bytes: int, key_bytes: int, n_streams: int, max_batch: int,
-                 max_records: int, use_graphs: bool = True, device: str = "cuda"):
+                 max_records: int, use_graphs: bool = True, device: str = "cuda",
+                 resident_workgroups: int = 0, resident_slots: int = 8192,
+                 resident_lease_ms: int = 2):
         import torch
         from . import binding as b
         self.torch, self.b = torch, b
@@ -187,6 +197,39 @@ class GpuBackend:
         self.capacity_bytes = max_records * rec_bytes  # scratch the arena holds for requests
         if use_graphs:
             self._capture()
+        # (after the capture, which synchronizes the device)
+        self.resident = None
+        self.resident_cap = -1
+        if resident_workgroups:
+            self.resident = b.ResidentServer(rec_bytes, key_bytes, slots=resident_slots,
+                                             workgroups=resident_workgroups,
+                                             idle_ms=resident_lease_ms, lease_ms=resident_lease_ms)
+            self.resident_cap = self.resident.max_records
+
+    # ---- resident path: requests of at most resident_cap records
+    def ready_done(self, token) -> bool:
+        """Whether the work a producer event stands for has finished."""
+        return token is None or token[1].query()
+
+    def resident_submit(self, req) -> tuple[int, int]:
+        """(0, ticket), (1, 0) when the ring is full, or (negative status, 0)."""
+        st, t = self.resident.submit_status(req.recs, req.n)
+        if st == self.b.E_BUSY:
+            return 1, 0
+        return (0, t) if st == self.b.OK else (st, 0)
+
+    def resident_completed(self) -> tuple[int, int]:
+        return self.resident.completed()
+
+    def resident_status(self, ticket: int) -> int:
+        return self.resident.poll(ticket)[1]
+
+    def close(self) -> None:
+        """Stop the resident server, if any (its kernel leaves)."""
+        if self.resident is not None:
+            r, self.resident = self.resident, None
+            self.resident_cap = -1
+            r.close()
 
     def producer_event(self, recs) -> Any:
         """(stream, event) recorded on the submitting thread's current
@@ -305,6 +348,12 @@ class Server:
         # clients append without a lock; the scheduler, cancel and stop take
         # requests out only under `lock`
         self.pending: collections.deque = collections.deque()
+        # requests small enough for the backend's resident server (if any):
+        # no budget, no slot, no batch; published to its ring in arrival
+        # order once their input is ready, completed in ticket order
+        self.resident_cap = getattr(backend, "resident_cap", -1)
+        self.res_pending: collections.deque = collections.deque()
+        self.res_inflight: collections.deque = collections.deque()  # (ticket, request)
         self.admitted: list = []
         self.inflight: dict = {}          # stream -> (token, reqs)
         self.lock = threading.Condition()
@@ -345,6 +394,11 @@ class Server:
         n = int(recs.shape[0])
         req = Request(recs, n, time.perf_counter() if t_arrival is None else t_arrival,
                       self.done_cv)
+        if n <= self.resident_cap:
+            req.ready = self._ready_token(recs, ready)
+            self.res_pending.append(req)
+            self._wake()
+            return req
         if n * self.rec_bytes > self.budget:
             self._reject(req)
             return req
@@ -367,10 +421,13 @@ class Server:
         for c in range(0, len(arrays), self.SUBMIT_CHUNK):
             reqs = [Request(a, int(a.shape[0]), t, cv, token)
                     for a in arrays[c:c + self.SUBMIT_CHUNK]]
-            ok = [r for r in reqs if r.n * R <= cap]
-            if len(ok) != len(reqs):
+            small = self.resident_cap
+            if small >= 0:
+                self.res_pending.extend(r for r in reqs if r.n <= small)
+            ok = [r for r in reqs if small < r.n and r.n * R <= cap]
+            if len(ok) + (sum(1 for r in reqs if r.n <= small) if small >= 0 else 0) != len(reqs):
                 for r in reqs:
-                    if r.n * R > cap:
+                    if r.n > small and r.n * R > cap:
                         self._reject(r)
             self.pending.extend(ok)
             self._wake()
@@ -384,7 +441,8 @@ class Server:
     def cancel(self, fut: Request) -> bool:
         """Cancel a request that has not been launched yet."""
         with self.lock:
-            for q, reserved in ((self.pending, False), (self.admitted, True)):
+            for q, reserved in ((self.pending, False), (self.admitted, True),
+                                (self.res_pending, False)):
                 if fut in q:     # identity: requests define no equality
                     q.remove(fut)
                     if reserved:  # admitted requests hold budget and a slot
@@ -407,9 +465,10 @@ class Server:
     def stop(self, drain: bool = True) -> dict:
         with self.lock:
             if not drain:
-                while self.pending:
-                    self.pending.popleft()._fail(Cancelled("server stopped"))
-                    self.stats.cancelled += 1
+                for q in (self.pending, self.res_pending):
+                    while q:
+                        q.popleft()._fail(Cancelled("server stopped"))
+                        self.stats.cancelled += 1
                 self._notify_done()
             self._stop = True
             self.lock.notify_all()
@@ -453,9 +512,69 @@ class Server:
             self.lock.notify_all()
         self._notify_done()
 
+    def _resident_step(self) -> bool:
+        """Publish ready small requests to the resident server in arrival
+        order (stopping at the first whose input is not ready yet, or when
+        the ring is full) and complete the ones it has finished."""
+        be, worked = self.backend, False
+        pend, infl = self.res_pending, self.res_inflight
+        while pend:
+            r = pend[0]
+            if not be.ready_done(r.ready):
+                break
+            # (published under the lock, so that a request cancelled before
+            # this point is never handed to the device)
+            with self.lock:
+                if not pend or pend[0] is not r:  # cancelled meanwhile
+                    continue
+                code, t = be.resident_submit(r)
+                if code == 1:  # ring full: after a completion
+                    break
+                pend.popleft()
+                if code < 0:
+                    self.stats.failed += 1
+                    r._fail(BackendError(f"resident submit failed: {code}"))
+                else:
+                    r.t_admit = r.t_launch = time.perf_counter()
+                    if not self.stats.t_first:
+                        self.stats.t_first = r.t_arrival
+                    infl.append((t, r))
+            if code < 0:
+                self._notify_done()
+            worked = True
+        if infl:
+            try:
+                through, status_or = be.resident_completed()
+                failure = None
+            except Exception as e:  # the resident kernel left: fail what it holds
+                through, status_or, failure = infl[-1][0] + 1, 0, f"resident server: {e}"
+            if infl[0][0] < through:
+                now = time.perf_counter()
+                with self.lock:
+                    st = self.stats
+                    while infl and infl[0][0] < through:
+                        t, r = infl.popleft()
+                        r.t_done = now
+                        err = failure or (be.resident_status(t) if status_or else 0)
+                        if err:
+                            st.failed += 1
+                            r._fail(BackendError(f"device error {err}"))
+                        else:
+                            st.completed += 1
+                            st.records += r.n
+                            st.latencies.append(now - r.t_arrival)
+                            st.t_last = now
+                            r._resolve(r.recs)
+                    self.lock.notify_all()
+                self._notify_done()
+                worked = True
+        return worked
+
     def step(self) -> bool:
         """One scheduling pass; returns True if it did any work."""
         worked = False
+        if self.res_pending or self.res_inflight:
+            worked = self._resident_step()
         for s, (tok, reqs) in list(self.inflight.items()):
             if self.backend.done(tok):
                 self._complete(s, tok, reqs)
@@ -518,14 +637,15 @@ class Server:
             if self.step():
                 continue
             with self.lock:
-                idle = not (self.pending or self.admitted or self.inflight)
+                idle = not (self.pending or self.admitted or self.inflight or self.res_pending
+                            or self.res_inflight)
                 if self._stop and idle:
                     return
                 if idle:
                     # a client that appends after this check sees _sleeping
                     # set and notifies; the timeout only bounds a lost race
                     self._sleeping = True
-                    if not self.pending:
+                    if not (self.pending or self.res_pending):
                         self.lock.wait(timeout=0.01)
                     self._sleeping = False
                     continue

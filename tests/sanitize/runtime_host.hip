@@ -139,7 +139,7 @@ int main() {
   uint64_t cap = 0;
   expect(raduls_server_max_records(16, 8, &cap) == RADULS_OK && cap == 5120, "server capacity");
   raduls_server* srv = nullptr;
-  expect(raduls_server_create(16, 8, 0, 1, 10, &srv) == RADULS_E_INVALID && !srv, "server slots 0");
+  expect(raduls_server_create(16, 8, 0, 1, 10, 0, &srv) == RADULS_E_INVALID && !srv, "server slots 0");
   expect(raduls_server_destroy(nullptr) == RADULS_E_INVALID, "destroy null");
   for (int st = 0; st >= -10; --st)
     expect(std::strcmp(raduls_strerror(st), "unknown status") != 0, "strerror");

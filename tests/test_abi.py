@@ -163,12 +163,13 @@ def test_server_argument_errors_on_host():
     import ctypes
     lib = b.load()
     h = ctypes.c_void_p()
-    assert lib.raduls_server_create(12, 8, 64, 1, 100, ctypes.byref(h)) == b.E_UNSUPPORTED
-    assert lib.raduls_server_create(16, 17, 64, 1, 100, ctypes.byref(h)) == b.E_INVALID
-    assert lib.raduls_server_create(16, 8, 0, 1, 100, ctypes.byref(h)) == b.E_INVALID
-    assert lib.raduls_server_create(16, 8, (1 << 20) + 1, 1, 100, ctypes.byref(h)) == b.E_INVALID
-    assert lib.raduls_server_create(16, 8, 64, 1, 600001, ctypes.byref(h)) == b.E_INVALID
-    assert lib.raduls_server_create(16, 8, 64, 1, 100, None) == b.E_INVALID
+    assert lib.raduls_server_create(12, 8, 64, 1, 100, 0, ctypes.byref(h)) == b.E_UNSUPPORTED
+    assert lib.raduls_server_create(16, 17, 64, 1, 100, 0, ctypes.byref(h)) == b.E_INVALID
+    assert lib.raduls_server_create(16, 8, 0, 1, 100, 0, ctypes.byref(h)) == b.E_INVALID
+    assert lib.raduls_server_create(16, 8, (1 << 20) + 1, 1, 100, 0, ctypes.byref(h)) == b.E_INVALID
+    assert lib.raduls_server_create(16, 8, 64, 1, 600001, 0, ctypes.byref(h)) == b.E_INVALID
+    assert lib.raduls_server_create(16, 8, 64, 1, 100, 600001, ctypes.byref(h)) == b.E_INVALID
+    assert lib.raduls_server_create(16, 8, 64, 1, 100, 0, None) == b.E_INVALID
     t = ctypes.c_uint64()
     st = ctypes.c_uint32()
     assert lib.raduls_server_submit(None, None, 0, ctypes.byref(t)) == b.E_INVALID
@@ -179,6 +180,7 @@ def test_server_argument_errors_on_host():
     assert lib.raduls_server_wait(None, 0, 1, ctypes.byref(st)) == b.E_INVALID
     assert lib.raduls_server_wait_range(None, 0, 1, 1, ctypes.byref(st)) == b.E_INVALID
     assert lib.raduls_server_info(None, None, None, None, None) == b.E_INVALID
+    assert lib.raduls_server_completed(None, ctypes.byref(t), ctypes.byref(st)) == b.E_INVALID
     assert lib.raduls_server_destroy(None) == b.E_INVALID
 
 

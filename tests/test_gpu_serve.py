@@ -97,3 +97,39 @@ def test_budget_larger_than_backend_scratch_is_refused():
     be = serve.GpuBackend(16, 8, n_streams=1, max_batch=4, max_records=1024, use_graphs=False)
     with pytest.raises(ValueError):
         serve.Server(be, rec_bytes=16, budget_bytes=1024 * 16 + 1, max_slots=4)
+
+
+def test_small_requests_through_the_resident_server():
+    """With a resident server in the backend, requests of at most one LDS
+    job go to it and the others to batched launches; every result equals the
+    plain call's.  The inputs are written on the current stream and
+    submitted at once (each sort waits for its producer's event); nothing
+    synchronizes the whole device while the resident kernel runs."""
+    hosts = _requests(200, seed=27)
+    alone = [_alone(h) for h in hosts]
+    budget = 64 << 20
+    be = serve.GpuBackend(16, 8, n_streams=2, max_batch=16, max_records=budget // 16,
+                          resident_workgroups=4, resident_slots=64)
+    try:
+        cap = be.resident_cap
+        assert cap == b.raduls_server_max_records(16, 8)
+        srv = serve.Server(be, rec_bytes=16, budget_bytes=budget, max_slots=32).start()
+        stream = torch.cuda.current_stream()
+        devs = []
+        futs = []
+        for h in hosts:
+            d = torch.empty(h.shape, dtype=torch.uint8, device="cuda")
+            d.copy_(torch.from_numpy(h), non_blocking=False)
+            d.add_(0)  # (a kernel on the current stream writes it last)
+            devs.append(d)
+            futs.append(srv.submit(d))
+        res = [f.result(timeout=60) for f in futs]
+        s = srv.stop()
+        stream.synchronize()
+        assert s["requests"] == len(hosts) and s["failed"] == 0
+        assert any(h.shape[0] <= cap for h in hosts) and any(h.shape[0] > cap for h in hosts)
+        for r, a in zip(res, alone):
+            assert np.array_equal(r.cpu().numpy(), a)
+    finally:
+        be.close()
+    torch.cuda.synchronize()

@@ -125,8 +125,11 @@ def test_server_busy_slot_then_free():
     assert np.array_equal(d.cpu().numpy(), expect) and np.array_equal(e.cpu().numpy(), expect)
 
 
-def test_server_idle_limit_ends_the_kernel():
+def test_server_idle_limit_ends_the_kernel_and_submit_relaunches():
     r, k = 16, 8
+    h = wl.random_records(np.random.default_rng(21), 700, r, k, distinct_keys=90)
+    d = _device(h)
+    torch.cuda.synchronize()
     srv = b.ResidentServer(r, k, slots=8, workgroups=2, idle_ms=50)
     try:
         deadline = time.time() + 20
@@ -134,10 +137,32 @@ def test_server_idle_limit_ends_the_kernel():
             time.sleep(0.05)
         _, _, running, reason = srv.info()
         assert not running and reason == 2
-        buf = torch.zeros(64 * r, dtype=torch.uint8, device=DEV)
-        assert srv.submit_status(buf, 64)[0] == b.E_STOPPED
+        # the next submit relaunches the kernel on the same ring and state
+        t = srv.submit(d)
+        assert t == 0 and srv.wait(t) == 0
+        assert np.array_equal(d.cpu().numpy(), oracle.sort(h, k))
     finally:
         srv.close()
+
+
+def test_server_lease_relaunches_under_load():
+    """A lease of 1 ms: the kernel leaves many times while requests are
+    queued and the host's waits relaunch it; every request completes."""
+    r, k = 16, 8
+    cap = b.raduls_server_max_records(r, k)
+    rng = np.random.default_rng(23)
+    sizes = [int(x) for x in rng.integers(cap // 2, cap + 1, size=600)]
+    hosts = [wl.random_records(rng, n, r, k, distinct_keys=max(1, n // 4)) for n in sizes]
+    devs = [_device(h) for h in hosts]
+    torch.cuda.synchronize()
+    with b.ResidentServer(r, k, slots=1024, workgroups=2, idle_ms=IDLE_MS, lease_ms=1) as srv:
+        first, acc = srv.submit_many([d.data_ptr() for d in devs], sizes)
+        assert first == 0 and acc == len(sizes)
+        assert srv.wait_range(0, len(sizes)) == 0
+        reason = srv.info()[3]
+        assert reason in (0, 3)  # running, or last left at its lease
+    for i in rng.choice(len(sizes), size=40, replace=False):
+        assert np.array_equal(devs[i].cpu().numpy(), oracle.sort(hosts[i], k)), i
 
 
 def test_server_stop_is_prompt():

@@ -238,3 +238,119 @@ def test_ticket_times_out_while_pending():
         f.result(timeout=0.01)
     assert f.result(timeout=10) is not None and f.done()
     srv.stop()
+
+
+class FakeResidentBackend(FakeBackend):
+    """FakeBackend plus a resident path for requests of at most `cap`
+    records: a ring of `slots` entries that the stand-in device completes in
+    ticket order `res_delay_s` after submission (sorting with the oracle);
+    a readiness token is a callable that says whether the input is written."""
+
+    def __init__(self, cap=100, slots=4, res_delay_s=0.002, fail_ticket=None, **kw):
+        super().__init__(**kw)
+        self.resident_cap = cap
+        self.slots, self.res_delay_s, self.fail_ticket = slots, res_delay_s, fail_ticket
+        self.ring = []            # (ticket, due, request)
+        self.next = self.through = 0
+        self.resident_sizes = []
+        self.max_outstanding = 0
+
+    def ready_done(self, token):
+        return token is None or token()
+
+    def _advance(self):
+        now = time.perf_counter()
+        while self.ring and self.ring[0][1] <= now:
+            t, _, req = self.ring.pop(0)
+            req.recs[:] = oracle.sort(req.recs, self.key_bytes)
+            self.through = t + 1
+
+    def resident_submit(self, req):
+        self._advance()
+        if self.next - self.through >= self.slots:
+            return 1, 0
+        t = self.next
+        self.next += 1
+        self.ring.append((t, time.perf_counter() + self.res_delay_s, req))
+        self.resident_sizes.append(req.n)
+        self.max_outstanding = max(self.max_outstanding, self.next - self.through)
+        return 0, t
+
+    def resident_completed(self):
+        before = self.through
+        self._advance()
+        bad = self.fail_ticket is not None and before <= self.fail_ticket < self.through
+        return self.through, (7 if bad else 0)
+
+    def resident_status(self, ticket):
+        return 7 if ticket == self.fail_ticket else 0
+
+
+def test_resident_path_takes_small_requests_and_batches_the_rest():
+    be = FakeResidentBackend(cap=100, n_streams=2, max_batch=8)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 20, max_slots=8).start()
+    rng = np.random.default_rng(31)
+    sizes = [50, 500, 20, 1000, 0, 100, 101, 7]
+    arrays = [wl.random_records(rng, n, 16, 8, distinct_keys=max(1, n // 3)) for n in sizes]
+    expect = [oracle.sort(a, 8) for a in arrays]
+    futs = [srv.submit(a) for a in arrays[:4]] + srv.submit_many(arrays[4:])
+    for f, e in zip(futs, expect):
+        assert np.array_equal(f.result(timeout=30), e)
+    s = srv.stop()
+    assert be.resident_sizes == [n for n in sizes if n <= 100]  # in arrival order
+    assert sum(be.batch_sizes) == 3  # the three larger requests went to batches
+    assert s["requests"] == len(sizes) and srv.free == srv.budget and srv.slots == srv.max_slots
+
+
+def test_resident_request_waits_for_its_input():
+    be = FakeResidentBackend(cap=100)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 20, max_slots=8).start()
+    written = threading.Event()
+    a = wl.random_records(np.random.default_rng(32), 60, 16, 8)
+    f = srv.submit(a, ready=written.is_set)
+    b2 = srv.submit(wl.random_records(np.random.default_rng(33), 30, 16, 8), ready=False)
+    time.sleep(0.05)
+    # nothing overtakes a request whose input is not written yet
+    assert be.resident_sizes == [] and not f.done() and not b2.done()
+    written.set()
+    assert np.array_equal(f.result(timeout=10), oracle.sort(a, 8))
+    b2.result(timeout=10)
+    srv.stop()
+    assert be.resident_sizes == [60, 30]
+
+
+def test_resident_ring_full_holds_requests_back():
+    be = FakeResidentBackend(cap=100, slots=2, res_delay_s=0.003)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 20, max_slots=8).start()
+    arrays = _arrays(12, seed=34, max_log2=6)
+    futs = [srv.submit(a) for a in arrays]
+    for f, a in zip(futs, arrays):
+        assert np.array_equal(f.result(timeout=30), oracle.sort(a, 8))
+    srv.stop()
+    assert be.max_outstanding <= 2 and len(be.resident_sizes) == 12
+
+
+def test_resident_failure_fails_only_its_request():
+    be = FakeResidentBackend(cap=100, fail_ticket=1)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 20, max_slots=8).start()
+    arrays = _arrays(4, seed=35, max_log2=6)
+    futs = [srv.submit(a) for a in arrays]
+    with pytest.raises(serve.BackendError):
+        futs[1].result(timeout=10)
+    for i in (0, 2, 3):
+        assert np.array_equal(futs[i].result(timeout=10), oracle.sort(arrays[i], 8))
+    s = srv.stop()
+    assert s["failed"] == 1 and s["requests"] == 3
+
+
+def test_resident_request_cancelled_before_publication():
+    be = FakeResidentBackend(cap=100)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 20, max_slots=8).start()
+    never = threading.Event()
+    f = srv.submit(wl.random_records(np.random.default_rng(36), 40, 16, 8), ready=never.is_set)
+    time.sleep(0.01)
+    assert srv.cancel(f)
+    with pytest.raises(serve.Cancelled):
+        f.result(timeout=5)
+    s = srv.stop()
+    assert be.resident_sizes == [] and s["cancelled"] == 1
