@@ -111,7 +111,8 @@ typedef struct raduls_stats {
   uint32_t scattered_bins; /* large bins that were moved (not constant / all equal) */
   uint32_t mid_jobs;       /* bins finished by a final sort job: in one workgroup's LDS,
                               or (at most 64 records) by one wave in registers */
-  uint32_t copy_jobs;      /* tmp -> recs copies of finished bins */
+  uint32_t copy_jobs;      /* tmp -> recs copies of finished runs (pieces of at most
+                              mid_max records, taken by the LDS sorter) */
   uint64_t moved_records;  /* records moved by global scatter passes */
   uint64_t large_records;  /* records in large bins, summed over rounds */
   uint32_t pair_rounds;    /* 1 if the second round took its histograms from the

@@ -105,9 +105,6 @@ constexpr uint32_t kMaxRanges = 4096;
 constexpr uint32_t kPairWords = 1u << 15;
 constexpr uint32_t kPairRanges = 512;
 
-// Finished bins that sit in tmp are copied back in chunks of this many records.
-constexpr uint32_t kCopyChunk = 1u << 16;
-
 // Device error bits (raduls_stats.error).
 constexpr uint32_t kErrCapacity = 1u << 0;
 constexpr uint32_t kErrSpin = 1u << 1;
@@ -180,8 +177,8 @@ static_assert(sizeof(MidJob) == 32, "job descriptors are read as two 16-byte vec
 // the start of every call.
 struct Ctrl {
   uint32_t large_count[2];  // large-bin list sizes (ping-pong by round)
-  uint32_t mid_count;
-  uint32_t copy_count;
+  uint32_t mid_count;      // LDS-sort jobs, including the copy jobs
+  uint32_t copy_count;     // copy jobs (finished runs in tmp) among them
   uint32_t ticket;       // scatter tile tickets of the current round
   uint32_t round_tiles;  // tiles of the current round
   uint32_t error;
@@ -259,11 +256,10 @@ struct Layout {
   uint32_t* wg_flag;      // [cap_ranges] range starts a bin (1) / lies in one bin (2)
   MidJob* mid;
   MidJob* tiny;           // [cap_mid] jobs of at most kTinyJob records
-  Bin* copy;
   uint32_t* pair_part;    // [kPairRanges][kPairWords] per-range packed pair counts
   uint32_t* pair_hist;    // [2^16] pair counts of the whole array
   uint32_t* pair_d1;      // [kRadix] top digit of each second-round bin (when used)
-  uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges;
+  uint32_t cap_large, cap_tiles, cap_mid, cap_ranges;
 };
 
 enum Mode : uint32_t { kModeSort = 0, kModeBatch = 1, kModeHist = 2, kModePartition = 3 };
@@ -299,7 +295,7 @@ struct Params {
   uint32_t* d_counts_out;
   uint32_t* d_offsets_out;
   // launch shapes
-  uint32_t grid_hist, grid_scatter, grid_classify, grid_mid, grid_copy, grid_tiny;
+  uint32_t grid_hist, grid_scatter, grid_classify, grid_mid, grid_tiny;
   uint32_t mid_lds_bytes, scatter_lds_bytes;
   // resident server
   ServeRing* ring;          // device address of the host-pinned ring

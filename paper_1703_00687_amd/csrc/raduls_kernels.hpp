@@ -14,8 +14,8 @@
 //                          k_classify child bins -> next round / LDS jobs
 //   then                   k_tiny     jobs of at most 64 records, one wave each
 //                          k_mid      bins that fit in LDS, sorted there; tiny
-//                                     sub-bins by enumeration sort
-//                          k_copy     finished bins left in tmp -> recs
+//                                     sub-bins by enumeration sort; finished
+//                                     runs left in tmp back to recs
 #pragma once
 
 #include "raduls_common.hpp"
@@ -393,25 +393,46 @@ __device__ __forceinline__ void push_mid(const Params& P, const Bin& b, const Ar
   (tiny ? P.L.tiny : P.L.mid)[i] = j;
 }
 
-// Copy jobs for a finished run of records that sits in tmp.
-__device__ __forceinline__ void push_copy(const Params& P, uint32_t array, uint32_t start,
-                                          uint32_t size) {
-  const uint32_t chunks = (size + kCopyChunk - 1) / kCopyChunk;
-  const uint32_t i0 = atomicAdd(&P.L.ctrl->copy_count, chunks);
-  for (uint32_t c = 0; c < chunks; ++c) {
-    if (i0 + c >= P.L.cap_copy) {
-      atomicOr(&P.L.ctrl->error, kErrCapacity);
-      return;
-    }
-    Bin j;
-    j.start = start + c * kCopyChunk;
-    j.size = min(kCopyChunk, size - c * kCopyChunk);
-    j.array = array;
-    j.bits = 0;
-    j.side = 1;
-    j.flags = 0;
-    P.L.copy[i0 + c] = j;
+// A finished run of records that sits in tmp, [start, start + size) of array
+// `array`, goes back to recs as LDS-sort jobs of at most mid_max records:
+// a run whose keys are all equal (or already in order, as an exhausted key's
+// buckets are) is its own stable sort, and the sorter moves such a job
+// through LDS unchanged without a pass.  So the copies interleave with the
+// sort jobs of the same launch, which are bound by their instructions
+// rather than by HBM, instead of following them in a launch of their own.
+// All threads of the workgroup call; the one thread with `want` set supplies
+// the run, and the workgroup writes the pieces' descriptors together.
+__device__ void push_copy_jobs(const Params& P, bool want, uint32_t array, uint32_t start,
+                               uint32_t size) {
+  __shared__ uint32_t s_cp[4];  // first list index, start, size, array
+  if (!__syncthreads_or(want && size > 0)) return;
+  const uint32_t T = P.mid_max;
+  if (want && size > 0) {
+    const uint32_t pieces = (size + T - 1) / T;
+    s_cp[0] = atomicAdd(&P.L.ctrl->mid_count, pieces);
+    s_cp[1] = start;
+    s_cp[2] = size;
+    s_cp[3] = array;
+    atomicAdd(&P.L.ctrl->copy_count, pieces);
   }
+  __syncthreads();
+  const uint32_t base = s_cp[0], st = s_cp[1], sz = s_cp[2];
+  const ArrayDesc a = P.L.arrays[s_cp[3]];
+  const uint32_t pieces = (sz + T - 1) / T;
+  for (uint32_t k = threadIdx.x; k < pieces; k += blockDim.x) {
+    if (base + k >= P.L.cap_mid) {
+      atomicOr(&P.L.ctrl->error, kErrCapacity);
+      break;
+    }
+    const uint64_t at = uint64_t(st) + uint64_t(k) * T;
+    MidJob jb;
+    jb.src = a.tmp + at * P.R;
+    jb.dst = a.recs + at * P.R;
+    jb.size = min(T, sz - k * T);
+    jb.pad[0] = jb.pad[1] = jb.pad[2] = 0;
+    P.L.mid[base + k] = jb;
+  }
+  __syncthreads();  // s_cp is written again by the next call
 }
 
 // ------------------------------------------------------------ seeding
@@ -1433,7 +1454,7 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32
     }
     const int tb = top_bit<KW>(dif);
     if (tb < 0) {  // every key equal: finished where it is
-      if (tid == 0 && bin.side == 1) push_copy(P, bin.array, bin.start, bin.size);
+      push_copy_jobs(P, tid == 0 && bin.side == 1, bin.array, bin.start, bin.size);
       continue;
     }
     const uint32_t* hrow = fused ? P.L.pair_hist + P.L.pair_d1[b] * kRadix
@@ -1457,12 +1478,12 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32
       atomicAdd(&c->moved_records, (unsigned long long)bin.size);
     }
     if (lob == 0) {  // key exhausted: every child holds equal keys
-      if (tid == 0 && cside == 1) push_copy(P, bin.array, bin.start, bin.size);
+      push_copy_jobs(P, tid == 0 && cside == 1, bin.array, bin.start, bin.size);
       continue;
     }
     // the equal part of an equality split is finished: all its keys are equal
     const bool eq_done = eqb && tid == 1;
-    if (eq_done && h > 0 && cside == 1) push_copy(P, bin.array, bin.start + s_off[1], h);
+    push_copy_jobs(P, eq_done && h > 0 && cside == 1, bin.array, bin.start + s_off[1], h);
     if (tid < nb && h > P.mid_max && !eq_done) {
       Bin ch;
       ch.start = bin.start + s_off[tid];
@@ -3111,38 +3132,6 @@ __global__ void __launch_bounds__(kMidBlock) k_tiny(Params P) {
   }
 }
 
-template <int RW>
-__global__ void __launch_bounds__(256) k_copy(Params P) {
-  Ctrl* c = P.L.ctrl;
-  const uint32_t njobs = min(c->copy_count, P.L.cap_copy);
-  for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
-    const Bin job = P.L.copy[jb];
-    const ArrayDesc arr = P.L.arrays[job.array];
-    const RADULS_GLOBAL uint64_t* s =
-        gmem(reinterpret_cast<const uint64_t*>(arr.tmp)) + uint64_t(job.start) * RW;
-    RADULS_GLOBAL uint64_t* d = gmem(reinterpret_cast<uint64_t*>(arr.recs)) + uint64_t(job.start) * RW;
-    const uint64_t words = uint64_t(job.size) * RW;
-    if ((reinterpret_cast<uintptr_t>(s) & 15) == 0 && (reinterpret_cast<uintptr_t>(d) & 15) == 0) {
-      const RADULS_GLOBAL u64x2* s2 = reinterpret_cast<const RADULS_GLOBAL u64x2*>(s);
-      RADULS_GLOBAL u64x2* d2 = reinterpret_cast<RADULS_GLOBAL u64x2*>(d);
-      // four 16-byte loads in flight per thread before their stores
-      const uint64_t n2 = words / 2;
-      for (uint64_t q0 = threadIdx.x; q0 < n2; q0 += 4 * 256) {
-        u64x2 v[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (q0 + k * 256 < n2) v[k] = s2[q0 + k * 256];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (q0 + k * 256 < n2) d2[q0 + k * 256] = v[k];
-      }
-      if ((words & 1) && threadIdx.x == 0) d[words - 1] = s[words - 1];
-    } else {
-      for (uint64_t q = threadIdx.x; q < words; q += 256) d[q] = s[q];
-    }
-  }
-}
-
 // ------------------------------------------------------------ step outputs
 
 // Copies the single bin's histogram (and its exclusive prefix) out of the
@@ -3247,7 +3236,6 @@ hipError_t run_sequence(const Params& P, hipStream_t s) {
   if (!one_job || P.n > P.tiny_job)
     k_mid<RW, KW><<<P.grid_mid, kMidBlock, P.mid_lds_bytes, s>>>(P);
   prof_mark(kProfMid, 1, s);
-  if (!one_job) k_copy<RW><<<P.grid_copy, 256, 0, s>>>(P);
   return hipGetLastError();
 }
 

@@ -86,11 +86,11 @@ bool use_pair(const Eff& e, uint64_t n, uint32_t K) {
 }
 
 struct Shape {
-  uint32_t cap_large, cap_tiles, cap_mid, cap_copy, cap_ranges, rounds, pair;
+  uint32_t cap_large, cap_tiles, cap_mid, cap_ranges, rounds, pair;
   uint32_t eq_split;
   uint64_t off_ctrl, off_arrays, off_large[2], off_hist[2], off_diff[2], off_eqkey[2], off_tp, off_tb,
       off_status,
-      off_tail, off_carry, off_flag, off_mid, off_tiny, off_copy, off_pair_part, off_pair_hist, off_pair_d1,
+      off_tail, off_carry, off_flag, off_mid, off_tiny, off_pair_part, off_pair_hist, off_pair_d1,
       bytes;
 };
 
@@ -98,7 +98,8 @@ struct Shape {
 // hold more than mid_max records each; every round consumes at least one key
 // bit per bin, so there are at most ceil(8K / digit_bits) rounds.  LDS jobs:
 // a parent's greedy packing yields at most 2*small/mid_max + (large children)
-// + 2 jobs.  Copy jobs: every record is copied at most once, in chunks.
+// + 2 jobs; copy jobs (finished runs left in tmp, on the same list): every
+// record is copied at most once, each run in pieces of at most mid_max.
 Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const Eff& e,
                  bool step, bool pair = false) {
   Shape s{};
@@ -113,12 +114,13 @@ Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const
   if (s.eq_split) s.rounds += kEqRounds;
   const uint64_t large = step ? 1 : n_total / (T + 1) + 1;
   const uint64_t tiles = n_total / e.tile + large + 1;
-  const uint64_t mid = step ? 1 : 2 * (n_total / std::max<uint64_t>(T, 1) + 1) + 3ull * s.rounds * large + count + 16;
-  const uint64_t copy = step ? 1 : n_total / kCopyChunk + uint64_t(s.rounds) * large + 16;
+  // (plus copy jobs: finished runs left in tmp, at most mid_max records each)
+  const uint64_t mid = step ? 1
+                            : 3 * (n_total / std::max<uint64_t>(T, 1) + 1) + 4ull * s.rounds * large +
+                                  count + 32;
   s.cap_large = uint32_t(std::min<uint64_t>(large, 0xFFFFFFFFull));
   s.cap_tiles = uint32_t(std::min<uint64_t>(tiles, 0xFFFFFFFFull));
   s.cap_mid = uint32_t(std::min<uint64_t>(mid, 0xFFFFFFFFull));
-  s.cap_copy = uint32_t(std::min<uint64_t>(copy, 0xFFFFFFFFull));
   s.cap_ranges = uint32_t(std::min<uint64_t>(tiles, kMaxRanges));
   // look-back status rows are needed only when that scatter is selected
   const uint64_t status_rows = e.lookback ? s.cap_tiles : 1;
@@ -142,7 +144,6 @@ Shape plan_shape(uint64_t n_total, uint32_t count, uint32_t R, uint32_t K, const
   s.off_flag = take(uint64_t(s.cap_ranges) * 4);
   s.off_mid = take(uint64_t(s.cap_mid) * sizeof(MidJob));
   s.off_tiny = take(uint64_t(s.cap_mid) * sizeof(MidJob));
-  s.off_copy = take(uint64_t(s.cap_copy) * sizeof(Bin));
   // per-range pair counts, one row per histogram workgroup (at most
   // kPairRanges of them when pairs are counted), and their sum
   const uint64_t pair_rows = pair ? std::min<uint64_t>(s.cap_ranges, kPairRanges) : 0;
@@ -172,14 +173,12 @@ Layout make_layout(uint8_t* aux, const Shape& s) {
   L.cap_ranges = s.cap_ranges;
   L.mid = reinterpret_cast<MidJob*>(aux + s.off_mid);
   L.tiny = reinterpret_cast<MidJob*>(aux + s.off_tiny);
-  L.copy = reinterpret_cast<Bin*>(aux + s.off_copy);
   L.pair_part = reinterpret_cast<uint32_t*>(aux + s.off_pair_part);
   L.pair_hist = reinterpret_cast<uint32_t*>(aux + s.off_pair_hist);
   L.pair_d1 = reinterpret_cast<uint32_t*>(aux + s.off_pair_d1);
   L.cap_large = s.cap_large;
   L.cap_tiles = s.cap_tiles;
   L.cap_mid = s.cap_mid;
-  L.cap_copy = s.cap_copy;
   return L;
 }
 
@@ -265,7 +264,6 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
   P.mid_lds_bytes = mid_dynamic_lds(mid_capacity(R / 8, (K + 7) / 8), int(R / 8));
   P.grid_mid = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_mid, cus));
   P.grid_tiny = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_mid / kMidWaves + 1, 4 * cus));
-  P.grid_copy = std::max<uint32_t>(1, std::min<uint32_t>(s.cap_copy, 8 * cus));
 }
 
 int launch(const Params& P, uint32_t R, uint32_t K, hipStream_t stream) {
@@ -599,7 +597,7 @@ int raduls_check(const void* tmp_or_ws, uint64_t n, uint32_t rec_bytes, int ws_o
   stats->rounds = c.rounds;
   stats->large_bins = c.large_bins;
   stats->scattered_bins = c.scattered_bins;
-  stats->mid_jobs = c.mid_count + c.tiny_count;
+  stats->mid_jobs = c.mid_count + c.tiny_count - c.copy_count;
   stats->copy_jobs = c.copy_count;
   stats->moved_records = c.moved_records;
   stats->large_records = c.large_records;

@@ -76,7 +76,7 @@ int main() {
                                      s.off_hist[0], s.off_hist[1], s.off_diff[0], s.off_diff[1],
                                      s.off_eqkey[0], s.off_eqkey[1], s.off_tp, s.off_tb,
                                      s.off_status, s.off_tail, s.off_carry, s.off_flag,
-                                     s.off_mid, s.off_tiny, s.off_copy, s.off_pair_part,
+                                     s.off_mid, s.off_tiny, s.off_pair_part,
                                      s.off_pair_hist, s.off_pair_d1, s.bytes};
             for (size_t i = 1; i < sizeof(offs) / sizeof(offs[0]); ++i)
               expect(offs[i - 1] <= offs[i] && offs[i] % 256 == 0, "regions in order, aligned");
@@ -99,7 +99,6 @@ int main() {
             touch_last(L.wg_flag, s.cap_ranges);
             touch_last(L.mid, s.cap_mid);
             touch_last(L.tiny, s.cap_mid);
-            touch_last(L.copy, s.cap_copy);
             if (pair) {
               touch_last(L.pair_part,
                          std::min<uint64_t>(s.cap_ranges, kPairRanges) * kPairWords);

@@ -188,3 +188,25 @@ def test_runs_of_equal_keys_across_waves(block, n):
     inp[:, :k] = np.repeat(run_keys, block, axis=0)[:n]
     out, _ = gpu_sort(inp, k)
     _assert_parity(out, inp, k)
+
+
+@pytest.mark.parametrize("r,k", [(8, 8), (16, 8), (24, 13), (32, 16), (64, 9)])
+def test_finished_runs_in_tmp_copied_in_pieces(r, k):
+    """Runs of one key that end in tmp after the top round (two keys that
+    differ in the top byte, each with more records than one LDS job) go back
+    to recs as copy jobs on the LDS sorter's list, in pieces of at most
+    mid_max records: sizes at and around the piece boundaries."""
+    cap = b.raduls_server_max_records(r, k)  # mid_max of this layout
+    rng = np.random.default_rng(r * 31 + k)
+    for ca, cb in ((cap + 1, cap + 1), (2 * cap, 2 * cap + 1), (3 * cap + 7, cap + 2)):
+        n = ca + cb
+        inp = wl.random_records(rng, n, r, k)
+        lo = np.zeros(k, np.uint8)
+        hi = np.zeros(k, np.uint8)
+        lo[k - 1], hi[k - 1] = 0x10, 0xE0  # (the top byte is the key's last)
+        which = rng.permutation(np.r_[np.zeros(ca, bool), np.ones(cb, bool)])
+        inp[:, :k] = np.where(which[:, None], hi, lo)
+        out, stats = gpu_sort(inp, k)
+        _assert_parity(out, inp, k)
+        pieces = -(-ca // cap) + -(-cb // cap)
+        assert stats["copy_jobs"] == pieces, (ca, cb, stats)
