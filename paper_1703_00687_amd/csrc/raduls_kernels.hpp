@@ -400,8 +400,9 @@ __device__ __forceinline__ void push_mid(const Params& P, const Bin& b, const Ar
 // through LDS unchanged without a pass.  So the copies interleave with the
 // sort jobs of the same launch, which are bound by their instructions
 // rather than by HBM, instead of following them in a launch of their own.
-// All threads of the workgroup call; the one thread with `want` set supplies
-// the run, and the workgroup writes the pieces' descriptors together.
+// All threads of the workgroup call (the callers' conditions are uniform);
+// the one thread with `want` set supplies the run, and the workgroup writes
+// the pieces' descriptors together.
 __device__ void push_copy_jobs(const Params& P, bool want, uint32_t array, uint32_t start,
                                uint32_t size) {
   __shared__ uint32_t s_cp[4];  // first list index, start, size, array
@@ -1427,12 +1428,17 @@ template <int KW>
 __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32_t round) {
   __shared__ uint32_t s_cnt[kRadix], s_off[kRadix], s_scan[8];
   __shared__ uint32_t s_px[kRadix + 1], s_jmp[kRadix], s_st[kRadix], s_wt[4], s_wm[4];
-  __shared__ uint32_t s_jbase, s_tbase;
+  __shared__ uint32_t s_jbase, s_tbase, s_eqn;
   __shared__ uint64_t s_bm[4], s_sm[4];
   Ctrl* c = P.L.ctrl;
   const uint32_t nbins = min(c->large_count[cur], P.L.cap_large);
   const uint32_t nxt = cur ^ 1;
   const uint32_t tid = threadIdx.x;
+  // statistics, added to the control block once per workgroup (atomics on
+  // its few words from every bin of a round with thousands of bins queue up)
+  uint32_t n_scattered = 0;        // (thread 0)
+  unsigned long long n_moved = 0;  // (thread 0)
+  if (tid == 0) s_eqn = 0;
   for (uint32_t b = blockIdx.x; b < nbins; b += gridDim.x) {
     __syncthreads();
     const Bin bin = P.L.large[cur][b];
@@ -1454,7 +1460,7 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32
     }
     const int tb = top_bit<KW>(dif);
     if (tb < 0) {  // every key equal: finished where it is
-      push_copy_jobs(P, tid == 0 && bin.side == 1, bin.array, bin.start, bin.size);
+      if (bin.side == 1) push_copy_jobs(P, tid == 0, bin.array, bin.start, bin.size);
       continue;
     }
     const uint32_t* hrow = fused ? P.L.pair_hist + P.L.pair_d1[b] * kRadix
@@ -1474,16 +1480,16 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32
     block_exclusive_scan256(h, s_off, s_scan);
     const uint8_t cside = bin.side ^ 1;
     if (tid == 0) {
-      atomicAdd(&c->scattered_bins, 1u);
-      atomicAdd(&c->moved_records, (unsigned long long)bin.size);
+      ++n_scattered;
+      n_moved += bin.size;
     }
     if (lob == 0) {  // key exhausted: every child holds equal keys
-      push_copy_jobs(P, tid == 0 && cside == 1, bin.array, bin.start, bin.size);
+      if (cside == 1) push_copy_jobs(P, tid == 0, bin.array, bin.start, bin.size);
       continue;
     }
     // the equal part of an equality split is finished: all its keys are equal
     const bool eq_done = eqb && tid == 1;
-    push_copy_jobs(P, eq_done && h > 0 && cside == 1, bin.array, bin.start + s_off[1], h);
+    if (eqb && cside == 1) push_copy_jobs(P, eq_done && h > 0, bin.array, bin.start + s_off[1], h);
     if (tid < nb && h > P.mid_max && !eq_done) {
       Bin ch;
       ch.start = bin.start + s_off[tid];
@@ -1501,7 +1507,7 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32
         const uint8_t* base = (cside ? a.tmp : a.recs) + uint64_t(ch.start) * P.R;
         if (dominant_key<KW>(base, h, P.R, P.kmask, eqk)) {
           ch.flags |= kBinEq;
-          atomicAdd(&c->eq_bins, 1u);
+          atomicAdd(&s_eqn, 1u);
         }
       }
       // a child of 1.6 to 230 jobs' worth of records is split next round on
@@ -1617,6 +1623,14 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32
         }
       }
     }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (n_scattered) {
+      atomicAdd(&c->scattered_bins, n_scattered);
+      atomicAdd(&c->moved_records, n_moved);
+    }
+    if (s_eqn) atomicAdd(&c->eq_bins, s_eqn);
   }
 }
 
