@@ -473,7 +473,8 @@ def bench_batch(args) -> dict:
     if args.serve_requests > 0:
         nreq = min(args.serve_requests, count)
         budget = min(args.serve_budget_gib << 30, total * R)
-        be = serve.GpuBackend(R, K, n_streams=3, max_batch=2048, max_records=budget // R)
+        be = serve.GpuBackend(R, K, n_streams=args.serve_streams, max_batch=args.serve_max_batch,
+                              max_records=budget // R)
         views = [recs[int(starts[j]):int(starts[j]) + int(sizes[j])] for j in range(nreq)]
         import gc
 
@@ -532,6 +533,8 @@ def bench_batch(args) -> dict:
         closed = serve_run(None)
         log(f"[serve] closed: {closed}")
         out["served_closed"] = closed
+        out["served_config"] = {"streams": be.n_streams, "max_batch": be.max_batch,
+                                "budget_gib": budget / 2**30}
         closed1 = serve_run(None, many=False)
         log(f"[serve] closed, one submit per request: {closed1}")
         out["served_closed_per_request"] = closed1
@@ -793,6 +796,10 @@ def main() -> int:
                     help="Poisson arrival rates as fractions of the rate the server sustains "
                          "with every request present at once")
     ap.add_argument("--serve-budget-gib", type=int, default=32)
+    ap.add_argument("--serve-max-batch", type=int, default=2048,
+                    help="most requests the server puts in one batched launch")
+    ap.add_argument("--serve-streams", type=int, default=3,
+                    help="streams the server launches batches on")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched / served comparison (run only with uniform16)")
     ap.add_argument("--no-resident", action="store_true",
