@@ -340,7 +340,9 @@ struct raduls_server {
   std::atomic<uint64_t> next{0};             // next ticket
   uint64_t through = 0;                      // tickets below it have all completed (under mu_done)
   std::mutex mu_done;
-  std::atomic<bool> exited{false};           // the kernel has left
+  // launches of the kernel so far, and the last launch seen to have left
+  // (a stale observation never hides a later launch)
+  std::atomic<uint64_t> launched{0}, exited{0};
   std::mutex mu;                             // submitters, relaunches
   raduls::Params P{};                        // the kernel's launch parameters
 };
@@ -349,11 +351,16 @@ namespace raduls {
 namespace {
 
 bool server_running(raduls_server* s) {
-  if (s->exited.load(std::memory_order_acquire)) return false;
+  const uint64_t g = s->launched.load(std::memory_order_acquire);
+  if (s->exited.load(std::memory_order_acquire) >= g) return false;
   const hipError_t q = hipStreamQuery(s->stream);
   if (q == hipErrorNotReady) return true;
   if (q != hipSuccess) (void)hipGetLastError();
-  s->exited.store(true, std::memory_order_release);
+  // launch g (and every one before it) has left; a relaunch since the
+  // query has a larger number and is not covered
+  uint64_t e = s->exited.load(std::memory_order_relaxed);
+  while (e < g && !s->exited.compare_exchange_weak(e, g, std::memory_order_acq_rel)) {
+  }
   return false;
 }
 
@@ -369,7 +376,7 @@ bool server_ensure(raduls_server* s) {
     (void)hipGetLastError();
     return false;
   }
-  s->exited.store(false, std::memory_order_release);
+  s->launched.fetch_add(1, std::memory_order_acq_rel);
   return true;
 }
 
@@ -706,6 +713,7 @@ int raduls_server_create(uint32_t rec_bytes, uint32_t key_bytes, uint32_t slots,
     server_free(s);
     return RADULS_E_HIP;
   }
+  s->launched.store(1, std::memory_order_release);
   *out = s;
   return RADULS_OK;
 }

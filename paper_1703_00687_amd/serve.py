@@ -212,16 +212,23 @@ class GpuBackend:
         return token is None or token[1].query()
 
     def resident_submit(self, req) -> tuple[int, int]:
-        """(0, ticket), (1, 0) when the ring is full, or (negative status, 0)."""
+        """(0, ticket), (1, 0) when the ring is full, or (negative status, 0)
+        (also after close)."""
+        if self.resident is None:
+            return self.b.E_STOPPED, 0
         st, t = self.resident.submit_status(req.recs, req.n)
         if st == self.b.E_BUSY:
             return 1, 0
         return (0, t) if st == self.b.OK else (st, 0)
 
     def resident_completed(self) -> tuple[int, int]:
+        if self.resident is None:
+            raise self.b.RadulsError(self.b.E_STOPPED, "resident server closed")
         return self.resident.completed()
 
     def resident_status(self, ticket: int) -> int:
+        if self.resident is None:
+            return -1
         return self.resident.poll(ticket)[1]
 
     def close(self) -> None:

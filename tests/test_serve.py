@@ -354,3 +354,31 @@ def test_resident_request_cancelled_before_publication():
         f.result(timeout=5)
     s = srv.stop()
     assert be.resident_sizes == [] and s["cancelled"] == 1
+
+
+def test_resident_server_gone_fails_small_requests_and_serves_the_rest():
+    """A backend whose resident server has stopped (submits refused with a
+    negative status, completions raising): small requests fail with a
+    backend error, larger ones still go to batches, and nothing hangs."""
+
+    class Gone(FakeResidentBackend):
+        def resident_submit(self, req):
+            return -9, 0
+
+        def resident_completed(self):
+            raise RuntimeError("resident server closed")
+
+    be = Gone(cap=100, n_streams=2, max_batch=8)
+    srv = serve.Server(be, rec_bytes=16, budget_bytes=1 << 20, max_slots=8).start()
+    rng = np.random.default_rng(37)
+    sizes = [40, 400, 7, 1000]
+    arrays = [wl.random_records(rng, n, 16, 8) for n in sizes]
+    futs = [srv.submit(a) for a in arrays]
+    for f, a, n in zip(futs, arrays, sizes):
+        if n <= 100:
+            with pytest.raises(serve.BackendError):
+                f.result(timeout=10)
+        else:
+            assert np.array_equal(f.result(timeout=10), oracle.sort(a, 8))
+    s = srv.stop()
+    assert s["failed"] == 2 and s["requests"] == 2
