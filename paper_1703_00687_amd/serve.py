@@ -423,20 +423,22 @@ class Server:
             return []
         token = self._ready_token(arrays[0], ready)
         t = time.perf_counter() if t_arrival is None else t_arrival
-        cap, R, cv = self.budget, self.rec_bytes, self.done_cv
+        lim, cv, mk = self.budget // self.rec_bytes, self.done_cv, Request
+        small = self.resident_cap
         out = []
         for c in range(0, len(arrays), self.SUBMIT_CHUNK):
-            reqs = [Request(a, int(a.shape[0]), t, cv, token)
-                    for a in arrays[c:c + self.SUBMIT_CHUNK]]
-            small = self.resident_cap
-            if small >= 0:
-                self.res_pending.extend(r for r in reqs if r.n <= small)
-            ok = [r for r in reqs if small < r.n and r.n * R <= cap]
-            if len(ok) + (sum(1 for r in reqs if r.n <= small) if small >= 0 else 0) != len(reqs):
+            chunk = arrays[c:c + self.SUBMIT_CHUNK]
+            ns = [a.shape[0] for a in chunk]
+            reqs = [mk(a, n, t, cv, token) for a, n in zip(chunk, ns)]
+            if small < min(ns) and max(ns) <= lim:  # (the usual case: all batched)
+                self.pending.extend(reqs)
+            else:
+                if small >= 0:
+                    self.res_pending.extend(r for r in reqs if r.n <= small)
+                self.pending.extend(r for r in reqs if small < r.n <= lim)
                 for r in reqs:
-                    if r.n > small and r.n * R > cap:
+                    if r.n > small and r.n > lim:
                         self._reject(r)
-            self.pending.extend(ok)
             self._wake()
             out += reqs
         return out
@@ -499,19 +501,32 @@ class Server:
         with self.lock:
             del self.inflight[s]
             st = self.stats
-            freed = 0
             lat = st.latencies
-            for r, err in zip(reqs, errs):
-                freed += r.n * R
-                r.t_done = now
-                if err:
-                    st.failed += 1
-                    r._fail(BackendError(err))
-                else:
-                    st.completed += 1
-                    st.records += r.n
-                    lat.append(now - r.t_arrival)
-                    r._resolve(r.recs)
+            if not any(errs):  # (the usual case: the whole batch sorted)
+                recs = 0
+                ok = Request._OK
+                for r in reqs:
+                    recs += r.n
+                    r.t_done = now
+                    r._value = r.recs
+                    r._state = ok
+                lat.extend([now - r.t_arrival for r in reqs])
+                st.completed += len(reqs)
+                st.records += recs
+                freed = recs * R
+            else:
+                freed = 0
+                for r, err in zip(reqs, errs):
+                    freed += r.n * R
+                    r.t_done = now
+                    if err:
+                        st.failed += 1
+                        r._fail(BackendError(err))
+                    else:
+                        st.completed += 1
+                        st.records += r.n
+                        lat.append(now - r.t_arrival)
+                        r._resolve(r.recs)
             if st.completed:
                 st.t_last = now
             self.free += freed
@@ -592,20 +607,24 @@ class Server:
             pend, adm, R = self.pending, self.admitted, self.rec_bytes
             room = min(self.slots, self.max_batch - len(adm))
             took = 0
-            while pend and took < room:
-                nb = pend[0].n * R
-                if nb > self.free:
-                    break
-                self.free -= nb
-                adm.append(pend.popleft())
-                took += 1
+            if pend and room > 0:
+                free, popleft, push = self.free, pend.popleft, adm.append
+                now = time.perf_counter()
+                while pend and took < room:
+                    r = pend[0]
+                    nb = r.n * R
+                    if nb > free:
+                        break
+                    free -= nb
+                    popleft()
+                    r.t_admit = now
+                    push(r)
+                    took += 1
+                self.free = free
             if took:
                 self.slots -= took
-                now = time.perf_counter()
                 if not self.stats.t_first:  # admission is in arrival order
                     self.stats.t_first = adm[-took].t_arrival
-                for r in adm[-took:]:
-                    r.t_admit = now
                 worked = True
             if s_idx is None or not adm:
                 return worked
