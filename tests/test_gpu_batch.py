@@ -50,6 +50,31 @@ def test_batch_many_small_arrays():
         assert np.array_equal(o, oracle.sort(a, 8))
 
 
+
+@pytest.mark.parametrize("r,k", [(16, 8), (32, 16)])
+def test_batch_runs_finished_in_tmp(r, k):
+    """Arrays whose records hold two keys that differ in the top byte, each
+    key on more records than one LDS job: every array's runs end in tmp
+    after the top round and come back as copy jobs (pieces of at most
+    mid_max) among the other arrays' sort jobs."""
+    cap = b.raduls_server_max_records(r, k)  # mid_max of this layout
+    rng = np.random.default_rng(41 + r)
+    arrays, pieces = [], 0
+    for ca, cb in ((cap + 1, cap + 3), (2 * cap, 5), (3 * cap + 1, 2 * cap + 1), (0, 0),
+                   (700, 1200)):
+        a = wl.random_records(rng, ca + cb, r, k)
+        lo, hi = np.zeros(k, np.uint8), np.zeros(k, np.uint8)
+        lo[k - 1], hi[k - 1] = 0x21, 0xC4
+        which = rng.permutation(np.r_[np.zeros(ca, bool), np.ones(cb, bool)])
+        a[:, :k] = np.where(which[:, None], hi, lo)
+        arrays.append(a)
+        if ca + cb > cap:  # (a smaller array is one LDS job as a whole)
+            pieces += sum(-(-c // cap) for c in (ca, cb) if c > cap)
+    outs, stats = _run_batch(arrays, r, k)
+    for a, o in zip(arrays, outs):
+        assert np.array_equal(o, oracle.sort(a, k))
+    assert stats["copy_jobs"] == pieces, stats
+
 def test_batch_total_capacity_error_is_reported():
     a = torch.from_numpy(wl.uniform16(1000).reshape(-1).copy()).cuda().view(1000, 16)
     t = torch.empty_like(a)
