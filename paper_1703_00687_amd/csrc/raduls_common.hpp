@@ -151,6 +151,8 @@ constexpr uint8_t kBinWidthMask = 0x3C;
 // split consumes a round but no key bit), and the samples that decide one.
 constexpr uint32_t kEqRounds = 2;
 constexpr uint32_t kEqSamples = 16, kEqDominant = 12;
+// Records sampled (evenly spaced) to guess the root's highest differing key bit.
+constexpr uint32_t kSpecSamples = 1024;
 
 // A bin (a contiguous run of records that share all key bits above `bits`)
 // or an LDS sort job / copy job over such runs.  16 bytes.
@@ -278,6 +280,8 @@ struct Params {
   uint32_t nontemporal;
   uint32_t lookback;      // 1: decoupled look-back scatter, 0: carry scan
   uint32_t pair;          // 1: the top-level histogram also counts digit pairs
+  uint32_t spec;          // 1: the root's first split starts at the highest key bit in
+                          // which sampled records differ (checked by round 0)
   uint32_t pair_min_bins; // fewest second-round bins that take the pair counts
   uint32_t rounds;         // rounds launched
   uint32_t round_budget;  // rounds a full sort launches (equality splits must fit in them)

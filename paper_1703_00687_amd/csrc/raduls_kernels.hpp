@@ -156,6 +156,21 @@ __device__ __forceinline__ int top_bit(const uint64_t (&d)[KW]) {
   return r;
 }
 
+// Whether a key spread has a bit at or above `bits`: the keys of a bin then
+// differ where the bin says they agree (only a root whose first split was
+// guessed from a sample can be such a bin; see k_seed_single).
+template <int KW>
+__device__ __forceinline__ bool spread_above(const uint64_t (&d)[KW], uint32_t bits) {
+  bool a = false;
+#pragma unroll
+  for (int i = 0; i < KW; ++i) {
+    const uint32_t b0 = 64u * uint32_t(i);
+    const uint64_t m = bits <= b0 ? ~0ull : (bits >= b0 + 64 ? 0ull : ~((1ull << (bits - b0)) - 1ull));
+    a = a || (d[i] & m) != 0;
+  }
+  return a;
+}
+
 // How a large bin's records are bucketed in a round: by the digit
 // [lob, lob + w) of the key (Sec. 1), or, for a bin marked for an equality
 // split (kBinEq), into 0: keys below its equality key, 1: that key, 2: keys
@@ -439,8 +454,41 @@ __device__ void push_copy_jobs(const Params& P, bool want, uint32_t array, uint3
 // ------------------------------------------------------------ seeding
 
 // Clears the control block and installs the root bin of a single-array call.
+//
+// With P.spec, the root's first digit is not the key's top byte but the one
+// just below the highest key bit in which kSpecSamples evenly spaced records
+// differ from the first record (key bits above it are then constant in the
+// sample, as when keys are narrower than their field): the top-level pass
+// would only find them constant and move nothing.  Round 0's histogram pass
+// measures the true spread of the keys; if a record differs above the guess,
+// that round moves nothing and the root is pushed again from its true top
+// bit, as for a constant digit (the sort then uses one of the rounds that it
+// keeps for equality splits).
 static __global__ void __launch_bounds__(64) k_seed_single(Params P) {
   Ctrl* c = P.L.ctrl;
+  uint32_t top = 8 * P.K;  // the root's bits
+  if (P.spec && P.mode == kModeSort && P.n > P.mid_max) {
+    const uint32_t kw = (P.K + 7) / 8, lane = threadIdx.x;
+    const RADULS_GLOBAL uint64_t* base = gmem(reinterpret_cast<const uint64_t*>(P.recs));
+    const uint32_t rw = P.R / 8;
+    int tb = -1;
+    for (uint32_t q = kw; q-- > 0;) {
+      const uint64_t m = q == kw - 1 ? P.kmask : ~0ull;
+      const uint64_t k0 = base[q] & m;
+      uint64_t d = 0;
+      for (uint32_t i = lane; i < kSpecSamples; i += 64) {
+        const uint64_t pos = (uint64_t(2 * i + 1) * P.n) / (2 * kSpecSamples);
+        d |= (base[pos * rw + q] & m) ^ k0;
+      }
+      d = wave_or(d);
+      if (d) {
+        tb = int(64 * q) + 63 - __clzll(static_cast<long long>(d));
+        break;
+      }
+    }
+    // (the top-level pair counts take the digit below the first: 16 bits)
+    if (tb >= 0) top = max(uint32_t(tb + 1), P.pair ? 16u : 8u);
+  }
   if (threadIdx.x == 0) {
     *c = Ctrl{};
     ArrayDesc a;
@@ -459,7 +507,7 @@ static __global__ void __launch_bounds__(64) k_seed_single(Params P) {
       P.L.large[0][0] = b;
       c->large_count[0] = P.n ? 1 : 0;
     } else {
-      b.bits = uint16_t(8 * P.K);
+      b.bits = uint16_t(top);
       if (P.n > P.mid_max) {
         P.L.large[0][0] = b;
         c->large_count[0] = 1;
@@ -542,7 +590,8 @@ __device__ uint32_t pair_decide(const Params& P, uint32_t cur, uint32_t nb, uint
   atomicMax(&s_max, max_tiles_thread);
   const uint32_t h0 = t < kRadix ? root[t] : 0u;
   block_exclusive_scan256(h0, s_pre, s_scan);  // all threads; ends with a barrier
-  const uint32_t bits = 8u * P.K - 8u;
+  // (children of the root, split on the digit below its first)
+  const uint32_t bits = uint32_t(P.L.large[0][0].bits) - 8u;
   if (t == 0 && !(nb >= P.pair_min_bins && nb <= kRadix && nb <= P.grid_hist &&
                   4ull * s_max * nb <= 5ull * tiles))
     s_ok = 0;
@@ -1203,10 +1252,16 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter_carry(Params P, uint3
     active = true;
     if (P.mode != kModePartition) {
       uint64_t any = whole_bin ? 1u : 0u;  // (a bin of pair counts is never constant)
+      uint64_t dw[KW];
 #pragma unroll
-      for (int i = 0; i < KW; ++i) any |= whole_bin ? 0ull : P.L.diff[cur][uint64_t(b) * 8 + i];
-      // all keys equal, or a digit shared by the whole bin: nothing moves
-      active = any != 0 && !__syncthreads_or(tid < nb && h == bin.size);
+      for (int i = 0; i < KW; ++i) {
+        dw[i] = whole_bin ? 0ull : P.L.diff[cur][uint64_t(b) * 8 + i];
+        any |= dw[i];
+      }
+      // all keys equal, a digit shared by the whole bin, or keys that differ
+      // above the bin's bits (a wrong guess of the root's top): nothing moves
+      active = any != 0 && !spread_above<KW>(dw, bin.bits) &&
+               !__syncthreads_or(tid < nb && h == bin.size);
     }
     if (active) block_exclusive_scan256(h, s_binoff, s_scan);
   };
@@ -1466,7 +1521,10 @@ __global__ void __launch_bounds__(256) k_classify(Params P, uint32_t cur, uint32
     const uint32_t* hrow = fused ? P.L.pair_hist + P.L.pair_d1[b] * kRadix
                                  : P.L.hist[cur] + uint64_t(b) * kRadix;
     const uint32_t h = tid < nb ? hrow[tid] : 0;
-    if (__syncthreads_or(tid < nb && h == bin.size)) {
+    // one digit for the whole bin, or (a root whose top was guessed from a
+    // sample) keys that differ above its bits: nothing moved; split next
+    // round from the highest differing bit
+    if (tb >= int(bin.bits) || __syncthreads_or(tid < nb && h == bin.size)) {
       if (tid == 0) {
         Bin nbn = bin;
         nbn.bits = uint16_t(tb + 1);

@@ -247,6 +247,9 @@ void fill_params(Params& P, const Eff& e, const Shape& s, uint8_t* aux, uint32_t
   P.rounds = s.rounds;
   P.round_budget = s.rounds;
   P.eq_split = s.eq_split;
+  // a single array large enough to keep rounds for equality splits guesses
+  // its root's top bit from a sample: a wrong guess costs one of those rounds
+  P.spec = mode == kModeSort && s.eq_split ? 1u : 0u;
   P.mode = mode;
   P.count = count;
   const DevInfo d = device_info();

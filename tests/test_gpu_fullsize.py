@@ -156,7 +156,10 @@ def test_deep32_full():
     n = 1 << 27
     inp = wl.deep32_torch(n)
     out, stats = _sort_full(inp, 16)
-    assert stats["rounds"] >= 3  # the high key word forces deep recursion
+    # the top 44 key bits are zero: the root's first split starts below them
+    # (its top bit guessed from a sample), so two global rounds leave bins
+    # of about 2048 records, none of them a round that moves nothing
+    assert stats["rounds"] == 2 and stats["scattered_bins"] == stats["large_bins"], stats
     check_stable_device(out, inp, 4, 2, 2)
     sample_windows(out, inp, 4, 2, 16, seed=2)
 

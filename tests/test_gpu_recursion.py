@@ -141,3 +141,38 @@ def test_narrow_digit_for_bins_of_a_few_jobs():
         st, stats = b.raduls_check(tmp, n, 16, False)
         assert st == b.OK, stats
         assert np.array_equal(recs.cpu().numpy().reshape(n, 16), oracle.sort(host, 8))
+
+
+def test_root_top_guessed_from_a_sample():
+    """Deep keys (the top 44 key bits zero) at a size where the root's first
+    digit is guessed from sampled records: round 0 already splits below the
+    constant bits (no round that only finds them constant)."""
+    host = wl.deep32(1 << 21, seed=44)
+    bins = check_round(host, 16, 2, 1)
+    assert bins and all(bt <= 76 for _, _, bt, _, _ in bins)
+    bins = check_round(host, 16, 2, 2)
+
+
+@pytest.mark.parametrize("hi_count", [1, 3, 1000])
+def test_root_top_guess_missed(hi_count):
+    """Keys below 2^40 except a few records with bit 62 set, which the
+    sample (most likely) misses: round 0's histogram sees the true spread,
+    moves nothing, and the root is split from its true top next round; the
+    sort is still the stable sort."""
+    n = 1 << 21
+    rng = np.random.default_rng(45 + hi_count)
+    host = wl.random_records(rng, n, 16, 8)
+    keys = host[:, :8].copy().view("<u8").ravel()
+    keys &= np.uint64((1 << 40) - 1)
+    hit = rng.choice(n, size=hi_count, replace=False)
+    keys[hit] |= np.uint64(1 << 62)
+    host[:, :8] = keys.view(np.uint8).reshape(n, 8)
+    host[:, 8:] = np.arange(n, dtype="<u8").view(np.uint8).reshape(n, 8)
+    bins = check_round(host, 8, 1, 1)
+    assert bins
+    recs = torch.from_numpy(host.reshape(-1).copy()).cuda()
+    tmp = torch.empty(b.raduls_tmp_bytes(n, 16, 8), dtype=torch.uint8, device="cuda")
+    b.raduls_sort(recs, tmp, n, 16, 8)
+    st, stats = b.raduls_check(tmp, n, 16, False)
+    assert st == b.OK, stats
+    assert np.array_equal(recs.cpu().numpy().reshape(n, 16), oracle.sort(host, 8))
