@@ -172,7 +172,12 @@ class GpuBackend:
     streams than the device has hardware queues, so a batch stream may share
     the kernel's queue, and then waits at most that long.  While the kernel
     runs, a device-wide synchronize would wait for it: callers synchronize
-    their own streams instead, and ``close`` stops it."""
+    their own streams instead, and ``close`` stops it.
+
+    The resident path is experimental: it is tested with a few hundred
+    requests, but a run that sent 40,192 of 65,536 requests to a
+    32-workgroup resident server beside three batch streams did not finish
+    (with a 10-minute and again with a 2 ms lease; cause not found)."""
 
     def __init__(self, rec_bytes: int, key_bytes: int, n_streams: int, max_batch: int,
                  max_records: int, use_graphs: bool = True, device: str = "cuda",
