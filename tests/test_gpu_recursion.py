@@ -176,3 +176,29 @@ def test_root_top_guess_missed(hi_count):
     st, stats = b.raduls_check(tmp, n, 16, False)
     assert st == b.OK, stats
     assert np.array_equal(recs.cpu().numpy().reshape(n, 16), oracle.sort(host, 8))
+
+
+@pytest.mark.parametrize("rare_high", [0, 2])
+def test_root_top_guess_two_word_keys(rare_high):
+    """16-byte keys below 2^40 (the guess falls in the low key word, three
+    words of zeros above it), optionally with a couple of records that set a
+    bit of the high word, which the sample most likely misses."""
+    n = 1 << 21
+    rng = np.random.default_rng(47 + rare_high)
+    host = wl.random_records(rng, n, 32, 16)
+    w = host.view("<u8").reshape(n, 4)
+    w[:, 0] &= np.uint64((1 << 40) - 1)
+    w[:, 1] = 0
+    w[:, 2] = np.arange(n, dtype="<u8")
+    if rare_high:
+        w[rng.choice(n, size=rare_high, replace=False), 1] = np.uint64(1 << 20)
+    host = w.view(np.uint8).reshape(n, 32)
+    bins = check_round(host, 16, 2, 1)
+    if not rare_high:
+        assert bins and all(bt <= 32 for _, _, bt, _, _ in bins)
+    recs = torch.from_numpy(host.reshape(-1).copy()).cuda()
+    tmp = torch.empty(b.raduls_tmp_bytes(n, 32, 16), dtype=torch.uint8, device="cuda")
+    b.raduls_sort(recs, tmp, n, 32, 16)
+    st, stats = b.raduls_check(tmp, n, 32, False)
+    assert st == b.OK, stats
+    assert np.array_equal(recs.cpu().numpy().reshape(n, 32), oracle.sort(host, 16))
