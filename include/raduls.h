@@ -142,7 +142,7 @@ int raduls_sort(void *recs, void *tmp, uint64_t n, uint32_t rec_bytes, uint32_t 
  * tmp needs only n*R bytes.  Allocates and frees nothing.  The top-level
  * digit-pair counts (tuning pair_hist) are never used here.  Returns
  * RADULS_E_SCRATCH when the workspace for n records does not fit the array
- * (with 16-byte records and default tuning about 6e7 records fit).  Every
+ * (with 16-byte records and default tuning about 5.8e7 records fit).  Every
  * call on one GPU uses that GPU's one array, which keeps the last call's
  * contents: calls that overlap on one GPU (other streams, other threads)
  * race and must be serialized by the caller.  raduls_check(tmp, ...) does
