@@ -210,3 +210,23 @@ def test_finished_runs_in_tmp_copied_in_pieces(r, k):
         _assert_parity(out, inp, k)
         pieces = -(-ca // cap) + -(-cb // cap)
         assert stats["copy_jobs"] == pieces, (ca, cb, stats)
+
+
+@pytest.mark.parametrize("r,k", [(8, 5), (24, 13), (40, 9), (16, 16)])
+@pytest.mark.parametrize("rare", [0, 3])
+def test_narrow_keys_in_wide_fields(r, k, rare):
+    """Keys whose bytes above the lowest three are one constant, non-zero
+    pattern (the top of the key field is constant but not zero), at a size
+    where the root's first digit is guessed from a sample of the records;
+    `rare` records differ in the key's top byte, which the sample most
+    likely misses.  Byte-identical to the stable oracle either way."""
+    n = 1 << 21
+    if n <= 256 * b.raduls_server_max_records(r, k):
+        n = 512 * b.raduls_server_max_records(r, k)
+    rng = np.random.default_rng(r * 100 + k + rare)
+    inp = wl.random_records(rng, n, r, k)
+    inp[:, 3:k] = 0x5A
+    if rare:
+        inp[rng.choice(n, size=rare, replace=False), k - 1] = 0x7E
+    out, stats = gpu_sort(inp, k)
+    _assert_parity(out, inp, k)
