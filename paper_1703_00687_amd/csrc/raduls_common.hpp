@@ -16,16 +16,19 @@ constexpr int kWave = 64;                   // CDNA wavefront width
 
 // Scatter / histogram workgroups: 16 waves, one per CU.  Records per thread
 // per tile are chosen per record width so that a tile stages up to about
-// 100-130 KiB in LDS: big tiles give every digit long runs per tile.
+// 100-130 KiB in LDS: big tiles give every digit long runs per tile.  For
+// 32-byte records three per thread leave room for the line buffers below.
 constexpr int kScatterBlock = 1024;
 constexpr int kScatterWaves = kScatterBlock / kWave;
 __host__ __device__ constexpr int scatter_items(int rw) {
-  return rw == 1 ? 7 : rw == 2 ? 6 : rw == 3 ? 5 : rw == 4 ? 4 : rw == 5 ? 3 : 2;
+  return rw == 1 ? 7 : rw == 2 ? 6 : rw == 3 ? 5 : rw == 4 ? 3 : rw == 5 ? 3 : 2;
 }
-// Records of 8 and 16 bytes leave the carry-mode scatter through per-digit
-// line buffers in LDS, so that every store but the first and last line of a
-// digit's output in a workgroup's range covers whole 128-byte lines.
-__host__ __device__ constexpr bool scatter_lines(int rw) { return rw <= 2; }
+// Records of 8, 16 and 32 bytes leave the carry-mode scatter through
+// per-digit line buffers in LDS, so that every store but the first and last
+// line of a digit's output in a workgroup's range covers whole 128-byte
+// lines (longer records take too much LDS; 24, 40, 48 and 56 bytes do not
+// divide a line).
+__host__ __device__ constexpr bool scatter_lines(int rw) { return rw <= 2 || rw == 4; }
 // Dynamic LDS of one scatter workgroup: the tile's records (input order) and
 // a 16-bit permutation (or, for the look-back variant, the records in digit
 // order and their digits), per-wave counters, three 256-entry tables, the
